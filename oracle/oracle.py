@@ -1,0 +1,135 @@
+"""ctypes wrapper of the C oracle (gj.c, textbook.c) -- TEST INFRASTRUCTURE ONLY.
+
+``gj`` computes the full conjunctive query of Section 2, Eq. (1), under set
+semantics, by Generic Join over sorted tuple arrays.  Rows come back in head
+order; ``emit=True`` returns them sorted lexicographically.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SOURCES = ["gj.c", "textbook.c"]
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle (plain gcc, -O2, OpenMP)."""
+    if not force and os.path.exists(_LIB_PATH):
+        return _LIB_PATH
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES]
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        L.oracle_gj.restype = ctypes.c_int64
+        L.oracle_gj.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P, P,
+                                ctypes.c_int64, P, P, ctypes.c_int]
+        L.oracle_digest_rows.restype = None
+        L.oracle_digest_rows.argtypes = [P, ctypes.c_int64, ctypes.c_int, P]
+        L.textbook_triangles.restype = ctypes.c_int64
+        L.textbook_triangles.argtypes = [P, ctypes.c_int64, ctypes.c_int]
+        L.textbook_4cliques.restype = ctypes.c_int64
+        L.textbook_4cliques.argtypes = [P, ctypes.c_int64, ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Result:
+    def __init__(self, count, rows=None, digest=None, work=None):
+        self.count = count
+        self.rows = rows
+        self.digest = digest
+        self.work = work
+
+
+def gj(n_vars: int, atoms, relations, order=None, lo=None, hi=None, emit=False,
+       digest=False, work=False, threads: int = 0) -> Result:
+    """Generic Join.
+
+    atoms: list of variable tuples, one per atom (head-order variable ids).
+    relations: list of int arrays [rows, arity], one per atom (may repeat objects).
+    order: variable order (default 0..n-1).  lo/hi: optional per-variable range
+    predicate lo[v] <= x_v < hi[v] on raw ids.
+    """
+    L = lib()
+    order = list(range(n_vars)) if order is None else list(order)
+    arity = np.array([len(a) for a in atoms], dtype=np.int32)
+    avars = np.array([v for a in atoms for v in a], dtype=np.int32)
+    rels = [np.ascontiguousarray(np.asarray(r, dtype=np.int64).reshape(-1, len(a)))
+            for r, a in zip(relations, atoms)]
+    rows = np.array([r.shape[0] for r in rels], dtype=np.int64)
+    ptrs = (ctypes.c_void_p * len(rels))(*[r.ctypes.data for r in rels])
+    ordr = np.array(order, dtype=np.int32)
+    lo_a = hi_a = None
+    if lo is not None:
+        lo_a = np.array(lo, dtype=np.int64)
+        hi_a = np.array(hi, dtype=np.int64)
+    out = None
+    cap = 0
+    if emit:
+        # first pass: count, to size the buffer exactly
+        c0 = L.oracle_gj(n_vars, len(atoms), _ptr(arity), _ptr(avars), ptrs, _ptr(rows), _ptr(ordr),
+                         _ptr(lo_a) if lo_a is not None else None,
+                         _ptr(hi_a) if hi_a is not None else None,
+                         None, 0, None, None, threads)
+        if c0 < 0:
+            raise ValueError("invalid query")
+        cap = max(int(c0), 1)
+        out = np.zeros((cap, n_vars), dtype=np.int64)
+    dg = np.zeros(2, dtype=np.uint64) if digest else None
+    wk = np.zeros(1, dtype=np.uint64) if work else None
+    c = L.oracle_gj(n_vars, len(atoms), _ptr(arity), _ptr(avars), ptrs, _ptr(rows), _ptr(ordr),
+                    _ptr(lo_a) if lo_a is not None else None,
+                    _ptr(hi_a) if hi_a is not None else None,
+                    _ptr(out) if out is not None else None, cap,
+                    _ptr(dg) if dg is not None else None,
+                    _ptr(wk) if wk is not None else None, threads)
+    if c < 0:
+        raise ValueError("invalid query")
+    res_rows = None
+    if emit:
+        res_rows = out[:c]
+        if c:
+            res_rows = res_rows[np.lexsort(res_rows.T[::-1])]
+    return Result(int(c), res_rows,
+                  (int(dg[0]), int(dg[1])) if dg is not None else None,
+                  int(wk[0]) if wk is not None else None)
+
+
+def digest_rows(rows: np.ndarray) -> tuple:
+    rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+    n = rows.shape[1] if rows.ndim == 2 else 1
+    d = np.zeros(2, dtype=np.uint64)
+    lib().oracle_digest_rows(_ptr(rows), rows.shape[0], n, _ptr(d))
+    return int(d[0]), int(d[1])
+
+
+def textbook_triangles(edges, threads: int = 0) -> int:
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int64))
+    return int(lib().textbook_triangles(_ptr(e), e.shape[0], threads))
+
+
+def textbook_4cliques(edges, threads: int = 0) -> int:
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int64))
+    return int(lib().textbook_4cliques(_ptr(e), e.shape[0], threads))

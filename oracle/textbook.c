@@ -1,0 +1,146 @@
+/*
+ * Textbook subgraph counters used only to pin the oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * These are classical algorithms unrelated to Generic Join, so agreement with
+ * the oracle on large graphs is evidence that the oracle has no dropped term or
+ * wrong index:
+ *  - triangles: the degree-ordered "forward" algorithm (Schank and Wagner 2005;
+ *    Latapy 2008): orient every edge from lower to higher (degree, id) rank and
+ *    count, for each oriented edge (u, v), the common out-neighbours of u and v;
+ *  - 4-cliques: the same orientation (Chiba and Nishizeki 1985 style): for each
+ *    oriented edge (u, v), W = out(u) & out(v), then count oriented edges inside W.
+ * Both count unordered subgraphs of a simple undirected graph given as its
+ * symmetric edge list (duplicates and self-loops ignored).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int64_t n;
+    int64_t* off;   /* n+1 */
+    int64_t* adj;   /* oriented out-neighbours */
+} tb_graph;
+
+static int cmp_i64(const void* a, const void* b) {
+    int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+    return (x > y) - (x < y);
+}
+
+/* Build the degree-oriented graph from a symmetric edge list. */
+static int tb_build(const int64_t* e, int64_t m, tb_graph* g) {
+    int64_t n = 0;
+    for (int64_t i = 0; i < 2 * m; ++i) {
+        if (e[i] < 0) return -1;
+        if (e[i] + 1 > n) n = e[i] + 1;
+    }
+    int64_t* deg = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t* off = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t i = 0; i < m; ++i) if (e[2 * i] != e[2 * i + 1]) off[e[2 * i] + 1]++;
+    for (int64_t v = 0; v < n; ++v) off[v + 1] += off[v];
+    int64_t* nb = (int64_t*)malloc(sizeof(int64_t) * (size_t)(off[n] > 0 ? off[n] : 1));
+    int64_t* cur = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    memcpy(cur, off, sizeof(int64_t) * (size_t)(n + 1));
+    for (int64_t i = 0; i < m; ++i)
+        if (e[2 * i] != e[2 * i + 1]) nb[cur[e[2 * i]]++] = e[2 * i + 1];
+    /* dedup neighbour lists to get true degrees */
+    for (int64_t v = 0; v < n; ++v) {
+        int64_t a = off[v], b = off[v + 1];
+        qsort(nb + a, (size_t)(b - a), sizeof(int64_t), cmp_i64);
+        int64_t w = 0;
+        for (int64_t i = a; i < b; ++i) if (w == 0 || nb[i] != nb[a + w - 1]) nb[a + w++] = nb[i];
+        deg[v] = w;
+    }
+    /* oriented adjacency: keep v->w when rank(v) < rank(w) */
+    int64_t* oo = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t v = 0; v < n; ++v) {
+        int64_t c = 0;
+        for (int64_t i = off[v]; i < off[v] + deg[v]; ++i) {
+            int64_t w = nb[i];
+            if (deg[v] < deg[w] || (deg[v] == deg[w] && v < w)) ++c;
+        }
+        oo[v + 1] = c;
+    }
+    for (int64_t v = 0; v < n; ++v) oo[v + 1] += oo[v];
+    int64_t* oa = (int64_t*)malloc(sizeof(int64_t) * (size_t)(oo[n] > 0 ? oo[n] : 1));
+    for (int64_t v = 0; v < n; ++v) {
+        int64_t c = oo[v];
+        for (int64_t i = off[v]; i < off[v] + deg[v]; ++i) {
+            int64_t w = nb[i];
+            if (deg[v] < deg[w] || (deg[v] == deg[w] && v < w)) oa[c++] = w;
+        }
+    }
+    free(deg); free(off); free(nb); free(cur);
+    g->n = n; g->off = oo; g->adj = oa;
+    return 0;
+}
+
+/* e: symmetric edge list, m rows of (u, v). Returns the number of triangles. */
+int64_t textbook_triangles(const int64_t* e, int64_t m, int nthreads) {
+    tb_graph g;
+    if (tb_build(e, m, &g) != 0) return -1;
+    uint64_t total = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+    {
+        unsigned char* mark = (unsigned char*)calloc((size_t)g.n + 1, 1);
+        uint64_t local = 0;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t u = 0; u < g.n; ++u) {
+            for (int64_t i = g.off[u]; i < g.off[u + 1]; ++i) mark[g.adj[i]] = 1;
+            for (int64_t i = g.off[u]; i < g.off[u + 1]; ++i) {
+                int64_t v = g.adj[i];
+                for (int64_t j = g.off[v]; j < g.off[v + 1]; ++j) local += mark[g.adj[j]];
+            }
+            for (int64_t i = g.off[u]; i < g.off[u + 1]; ++i) mark[g.adj[i]] = 0;
+        }
+#pragma omp atomic
+        total += local;
+        free(mark);
+    }
+    free(g.off); free(g.adj);
+    return (int64_t)total;
+}
+
+/* Returns the number of 4-cliques. */
+int64_t textbook_4cliques(const int64_t* e, int64_t m, int nthreads) {
+    tb_graph g;
+    if (tb_build(e, m, &g) != 0) return -1;
+    uint64_t total = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+    {
+        unsigned char* mu = (unsigned char*)calloc((size_t)g.n + 1, 1);
+        unsigned char* mw = (unsigned char*)calloc((size_t)g.n + 1, 1);
+        int64_t* wl = (int64_t*)malloc(sizeof(int64_t) * (size_t)(g.n + 1));
+        uint64_t local = 0;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t u = 0; u < g.n; ++u) {
+            for (int64_t i = g.off[u]; i < g.off[u + 1]; ++i) mu[g.adj[i]] = 1;
+            for (int64_t i = g.off[u]; i < g.off[u + 1]; ++i) {
+                int64_t v = g.adj[i];
+                int64_t nw = 0;
+                for (int64_t j = g.off[v]; j < g.off[v + 1]; ++j)
+                    if (mu[g.adj[j]]) { wl[nw++] = g.adj[j]; mw[g.adj[j]] = 1; }
+                for (int64_t a = 0; a < nw; ++a) {
+                    int64_t w = wl[a];
+                    for (int64_t j = g.off[w]; j < g.off[w + 1]; ++j) local += mw[g.adj[j]];
+                }
+                for (int64_t a = 0; a < nw; ++a) mw[wl[a]] = 0;
+            }
+            for (int64_t i = g.off[u]; i < g.off[u + 1]; ++i) mu[g.adj[i]] = 0;
+        }
+#pragma omp atomic
+        total += local;
+        free(mu); free(mw); free(wl);
+    }
+    free(g.off); free(g.adj);
+    return (int64_t)total;
+}

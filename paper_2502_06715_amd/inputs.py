@@ -1,0 +1,221 @@
+"""Seeded synthetic inputs shared by the tests, the oracle runs and the bench.
+
+This module holds only input generation: a counter-based random stream and
+graph generators shaped like the graph workloads of the paper's experiments
+(Section 7.1: sparse/skewed, dense/skewed and sparse/uniform graphs).  It
+contains none of the join method's arithmetic (no key mixing, no sorting into
+a variable order, no intersections), so the GPU path and the CPU oracle can
+both consume its arrays without sharing any of the method's code.
+
+Random numbers come from SplitMix64 (Steele, Lea and Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014) used counter-style: the i-th
+draw of stream ``seed`` is ``finalize(seed + (i + 1) * GAMMA)`` with the
+published golden-ratio increment and finaliser constants.
+
+Every generator returns the *directed, symmetric* tuple array of an
+undirected simple graph: each kept undirected edge {u, v} (u != v) appears as
+(u, v) and (v, u), rows shuffled so that a consumer really has to sort.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+_MASK64 = (1 << 64) - 1
+
+# Seed conventions: one stream family per workload.
+SEED_CONFIG = 0x4843_0000            # + config number (1, 2, 3)
+SEED_BATCH = 0x4843_1000_0000        # + query index (batched workload)
+SEED_SERVE = 0x4843_2000_0000        # + graph index (served workload)
+SHUFFLE_SALT = 0x5348_5546_464C_4521  # separates the shuffle stream
+
+
+def splitmix64(seed: int, start: int, count: int) -> np.ndarray:
+    """Draws ``start .. start+count-1`` of the SplitMix64 stream ``seed``."""
+    idx = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & _MASK64) + idx * GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def splitmix64_scalar(seed: int, i: int) -> int:
+    """Pure-Python single draw, used to pin the vectorised stream."""
+    z = (seed + (i + 1) * 0x9E3779B97F4A7C15) & _MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+    return z ^ (z >> 31)
+
+
+def _unit_double(r: np.ndarray) -> np.ndarray:
+    """Top 53 bits of each draw as a double in [0, 1)."""
+    return (r >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+def _bits(x: int) -> int:
+    return max(1, int(x).bit_length())
+
+
+def _draw_until(m: int, seed: int, id_bits: int, draw_batch) -> np.ndarray:
+    """Draw candidate edges in generation order until ``m`` unique undirected edges
+    (self-loops rejected, {u, v} canonicalised to (min, max)) have been kept; the
+    first occurrence of each edge in generation order is the one kept."""
+    key_bits = 2 * id_bits
+    batch_bits = min(23, 64 - key_bits)
+    assert batch_bits >= 10, "ids too wide for the packed dedup"
+    batch = 1 << batch_bits
+    accepted = np.zeros(0, dtype=np.uint64)          # sorted kept keys
+    kept = []                                        # kept keys in generation order
+    n_kept = 0
+    start = 0
+    while n_kept < m:
+        u, v = draw_batch(start, batch)
+        start += batch
+        lo = np.minimum(u, v).astype(np.uint64)
+        hi = np.maximum(u, v).astype(np.uint64)
+        local = np.arange(batch, dtype=np.uint64)
+        ok = lo != hi
+        key = (lo[ok] << np.uint64(id_bits)) | hi[ok]
+        packed = np.sort((key << np.uint64(batch_bits)) | local[ok])
+        k_sorted = packed >> np.uint64(batch_bits)
+        first = np.ones(k_sorted.size, dtype=bool)
+        first[1:] = k_sorted[1:] != k_sorted[:-1]
+        cand = packed[first]                          # first occurrence per key
+        ck = cand >> np.uint64(batch_bits)
+        if accepted.size:
+            pos = np.searchsorted(accepted, ck)
+            pos = np.minimum(pos, accepted.size - 1)
+            cand = cand[accepted[pos] != ck]
+        # back to generation order: repack as (local index, key) and sort
+        gen = np.sort(((cand & np.uint64(batch - 1)) << np.uint64(key_bits))
+                      | (cand >> np.uint64(batch_bits)))
+        take = gen[: m - n_kept] & np.uint64((1 << key_bits) - 1)
+        kept.append(take)
+        n_kept += take.size
+        accepted = np.sort(np.concatenate([accepted, take]))
+    chosen = np.concatenate(kept)
+    u = (chosen >> np.uint64(id_bits)).astype(np.int64)
+    v = (chosen & np.uint64((1 << id_bits) - 1)).astype(np.int64)
+    src = np.concatenate([u, v])
+    dst = np.concatenate([v, u])
+    nrow = src.size
+    idx_bits = _bits(nrow - 1)
+    rnd = splitmix64(seed ^ SHUFFLE_SALT, 0, nrow) >> np.uint64(idx_bits)
+    order = (np.sort((rnd << np.uint64(idx_bits)) | np.arange(nrow, dtype=np.uint64))
+             & np.uint64((1 << idx_bits) - 1)).astype(np.int64)
+    return np.stack([src[order], dst[order]], axis=1).astype(np.int32)
+
+
+def erdos_renyi(n: int, m: int, seed: int) -> np.ndarray:
+    """Uniform endpoints; ``n`` must be a power of two.  Candidate i uses draws 2i, 2i+1."""
+    assert n & (n - 1) == 0 and n >= 2
+    shift = np.uint64(64 - (n.bit_length() - 1))
+
+    def draw(start, count):
+        r = splitmix64(seed, 2 * start, 2 * count)
+        return (r[0::2] >> shift).astype(np.int64), (r[1::2] >> shift).astype(np.int64)
+
+    return _draw_until(m, seed, _bits(n - 1), draw)
+
+
+def rmat(scale: int, m: int, seed: int, a=0.57, b=0.19, c=0.19) -> np.ndarray:
+    """R-MAT (Chakrabarti, Zhan, Faloutsos 2004): ``scale`` recursive quadrant draws
+    per edge, most significant bit first, no noise and no vertex permutation.
+    Candidate i uses the 64-bit draws d = ceil(scale/2)*i ..; level l takes the
+    high 32 bits of draw l//2 when l is even and the low 32 bits when l is odd,
+    and compares them with the cumulative quadrant thresholds (a, a+b, a+b+c)*2^32."""
+    ta = np.uint32(int(round(a * 2**32)))
+    tb = np.uint32(int(round((a + b) * 2**32)))
+    tc = np.uint32(int(round((a + b + c) * 2**32)))
+    nd = (scale + 1) // 2
+
+    def draw(start, count):
+        r = np.ascontiguousarray(splitmix64(seed, nd * start, nd * count).reshape(count, nd).T)
+        u = np.zeros(count, dtype=np.uint32)
+        v = np.zeros(count, dtype=np.uint32)
+        for lvl in range(scale):
+            w = r[lvl // 2]
+            q = (w >> np.uint64(32)).astype(np.uint32) if lvl % 2 == 0 else w.astype(np.uint32)
+            ubit = q >= tb
+            vbit = ((q >= ta) & ~ubit) | (q >= tc)
+            u = (u << np.uint32(1)) | ubit
+            v = (v << np.uint32(1)) | vbit
+        return u.astype(np.int64), v.astype(np.int64)
+
+    return _draw_until(m, seed, scale, draw)
+
+
+def chung_lu(n: int, m: int, seed: int, beta: float = 2.1) -> np.ndarray:
+    """Chung-Lu power-law graph: weights w_i = (i+1)^(-1/(beta-1)); each endpoint
+    is drawn with probability proportional to w by inverse CDF in double.
+    Candidate i uses draws 2i, 2i+1."""
+    w = np.arange(1, n + 1, dtype=np.float64) ** (-1.0 / (beta - 1.0))
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+
+    def draw(start, count):
+        r = splitmix64(seed, 2 * start, 2 * count)
+        uu = _unit_double(r)
+        idx = np.searchsorted(cdf, uu, side="right")
+        np.minimum(idx, n - 1, out=idx)
+        return idx[0::2].astype(np.int64), idx[1::2].astype(np.int64)
+
+    return _draw_until(m, seed, _bits(n - 1), draw)
+
+
+def complete_graph(n: int) -> np.ndarray:
+    """Symmetric edge set of K_n without self-loops (unshuffled)."""
+    u, v = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    keep = u != v
+    return np.stack([u[keep], v[keep]], axis=1).astype(np.int32)
+
+
+def complete_bipartite(s: int, t: int) -> np.ndarray:
+    """Symmetric edge set of K_{s,t}: left ids 0..s-1, right ids s..s+t-1."""
+    u, v = np.meshgrid(np.arange(s), np.arange(s, s + t), indexing="ij")
+    u, v = u.ravel(), v.ravel()
+    return np.stack([np.concatenate([u, v]), np.concatenate([v, u])], axis=1).astype(np.int32)
+
+
+def random_relation(n_rows: int, domain: int, seed: int, arity: int = 2) -> np.ndarray:
+    """Tiny random relation with possible duplicates (for set-semantics tests)."""
+    r = splitmix64(seed, 0, n_rows * arity)
+    return ((r >> np.uint64(33)) % np.uint64(domain)).astype(np.int32).reshape(n_rows, arity)
+
+
+# The three single-GPU workloads (sizes from the workload table).
+CONFIGS = {
+    1: dict(kind="er", n=1 << 12, m=1 << 15, query="triangle"),
+    2: dict(kind="rmat", scale=20, m=1 << 24, query="triangle"),
+    3: dict(kind="chung_lu", n=1 << 18, m=1 << 22, query="clique4"),
+}
+
+
+def config_graph(cfg: int, scale_down: int = 0) -> np.ndarray:
+    """Directed symmetric tuples of workload ``cfg``.  ``scale_down`` divides the
+    vertex and edge counts by 2**scale_down (same recipe, smaller instance)."""
+    spec = CONFIGS[cfg]
+    seed = SEED_CONFIG + cfg
+    if spec["kind"] == "er":
+        return erdos_renyi(spec["n"] >> scale_down, spec["m"] >> scale_down, seed)
+    if spec["kind"] == "rmat":
+        return rmat(spec["scale"] - scale_down, spec["m"] >> scale_down, seed)
+    return chung_lu(spec["n"] >> scale_down, spec["m"] >> scale_down, seed)
+
+
+# Query shapes (head variables are 0..n_vars-1; each atom lists its variables).
+# Names follow the query table of Section 7.1 (Q1, Q2, Q4, Q6, Q8) and the
+# 4-cycle R(a,b), S(b,c), T(c,d), U(d,a) of the served workload.
+QUERIES = {
+    "triangle": (3, [(0, 1), (1, 2), (0, 2)]),                                  # Q1
+    "loop4": (4, [(0, 1), (0, 2), (1, 3), (2, 3)]),                              # Q2
+    "cycle4": (4, [(0, 1), (1, 2), (2, 3), (3, 0)]),
+    "diamond4": (4, [(0, 1), (0, 2), (1, 3), (2, 3), (1, 2)]),                   # Q4
+    "clique4": (4, [(0, 1), (0, 2), (1, 3), (2, 3), (1, 2), (0, 3)]),            # Q6
+    "twotriangle": (5, [(0, 1), (0, 2), (1, 2), (2, 3), (2, 4), (3, 4)]),        # Q8
+}

@@ -1,0 +1,75 @@
+"""Writes tests/golden/workloads.json: expected results of the three single-GPU
+workloads, computed by the CPU oracle only (Generic Join over sorted arrays),
+each cross-checked against an independent textbook counter before it is stored.
+
+    python tests/golden/make_golden.py [--threads N]
+
+Workload 1: ER graph (2^12 vertices, 2^15 undirected edges), triangle query,
+  count + digest of the full output.
+Workload 2: R-MAT scale 20, 2^24 undirected edges, triangle query, count +
+  galloping work counter (shares = 1, order a,b,c).
+Workload 3: Chung-Lu beta = 2.1, 2^18 vertices, 2^22 undirected edges, 4-clique
+  query, count + digest, plus range-restricted chunks on variable 0.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from paper_2502_06715_amd import inputs  # noqa: E402
+from oracle import oracle  # noqa: E402
+
+# chunks of workload 3 on variable 0 (raw ids): small enough for oracle emission
+CHUNKS3 = [(200000, 200400), (131072, 131200), (1000, 1001)]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--only", type=int, default=0)
+    args = ap.parse_args()
+    path = os.path.join(HERE, "workloads.json")
+    out = json.load(open(path)) if os.path.exists(path) else {}
+    for cfg in [1, 2, 3]:
+        if args.only and cfg != args.only:
+            continue
+        t0 = time.time()
+        E = inputs.config_graph(cfg)
+        q = inputs.CONFIGS[cfg]["query"]
+        n, atoms = inputs.QUERIES[q]
+        rels = [E] * len(atoms)
+        rec = {"query": q, "rows": int(E.shape[0])}
+        if cfg == 3:
+            r = oracle.gj(n, atoms, rels, digest=True, threads=args.threads)
+            tb = oracle.textbook_4cliques(E, threads=args.threads)
+            assert r.count == 24 * tb, (r.count, tb)
+            rec["textbook_4cliques"] = tb
+            rec["chunks"] = []
+            for lo, hi in CHUNKS3:
+                big = 1 << 31
+                c = oracle.gj(n, atoms, rels, lo=[lo, 0, 0, 0], hi=[hi, big, big, big], digest=True,
+                              threads=args.threads)
+                rec["chunks"].append({"var": 0, "lo": lo, "hi": hi, "count": c.count,
+                                      "digest": [str(c.digest[0]), str(c.digest[1])]})
+        else:
+            r = oracle.gj(n, atoms, rels, digest=True, work=(cfg == 2), threads=args.threads)
+            tb = oracle.textbook_triangles(E, threads=args.threads)
+            assert r.count == 6 * tb, (r.count, tb)
+            rec["textbook_triangles"] = tb
+            if r.work is not None:
+                rec["work_gallop_order_abc"] = r.work
+        rec["count"] = r.count
+        rec["digest"] = [str(r.digest[0]), str(r.digest[1])]
+        rec["oracle_seconds"] = round(time.time() - t0, 1)
+        out[str(cfg)] = rec
+        print(cfg, rec, flush=True)
+        json.dump(out, open(path, "w"), indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    main()
