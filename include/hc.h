@@ -1,0 +1,250 @@
+/*
+ * hc.h -- C-ABI of the MI355X (gfx950) Generic Join library.
+ *
+ * The library evaluates a full conjunctive query (Section 2, Eq. (1)):
+ *     Q(X_1..X_n) <- R_1(X_1) AND ... AND R_m(X_m)
+ * under set semantics, by Generic Join (Section 2, "Generic Join Algorithm")
+ * over the CoCo index (Section 4), with the domain of every variable
+ * HyperCube-partitioned by power-of-two shares (Section 2, "HyperCube
+ * Algorithm"; Section 5), and with the lifted-intersection rewriting of
+ * Section 6.1.  Shares and the variable order can be chosen by the cost model
+ * of Sections 6.2-6.3.
+ *
+ * Conventions shared by every call
+ *  - Device pointers point to memory of the context's device; host pointers to
+ *    ordinary host memory.  Every call names which one each argument is.
+ *  - Calls are ordered on the context's HIP stream and return after the work
+ *    they launched has completed, so results are valid on return.
+ *  - No call aborts or throws across the ABI.  A non-HC_OK status leaves a
+ *    message retrievable with hc_last_error(ctx); outputs are then unspecified
+ *    unless stated otherwise.
+ *  - Ids are non-negative integers.  Values are mapped to b-bit keys by a
+ *    bijective mixer H_b (b = key_bits) fixed per CoCo; a share 2^k of a
+ *    variable selects the top k bits of H_b(x) (the paper leaves the hash open;
+ *    any deterministic map partitions the output correctly).  All CoCos used
+ *    by one join must share b and the mixer seed.
+ *  - Scratch device memory comes from the allocator given to hc_ctx_create.
+ *  - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef HC_H
+#define HC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HC_OK = 0,
+    HC_ERR_INVALID = 1,      /* malformed argument or query */
+    HC_ERR_OOM = 2,          /* the allocator refused a request */
+    HC_ERR_OVERFLOW = 3,     /* emit: more result rows than the capacity */
+    HC_ERR_DEVICE = 4,       /* a HIP runtime call or a device-side check failed */
+    HC_ERR_UNSUPPORTED = 5   /* valid but outside what this build implements */
+} hc_status;
+
+typedef enum { HC_I32 = 0, HC_I64 = 1 } hc_dtype;
+
+typedef struct hc_ctx hc_ctx;
+typedef struct hc_coco hc_coco;
+
+/*
+ * A full conjunctive query (Section 2, Eq. (1)).  Variables are 0..n_vars-1,
+ * which is also the head (output column) order.  Atom j has atom_arity[j]
+ * variables, listed consecutively in atom_vars.  Every variable must occur in
+ * some atom (Section 2).  A variable repeated inside one atom is unsupported.
+ * var_lo/var_hi (host, nullable, both or neither): a range predicate
+ * var_lo[v] <= x_v < var_hi[v] on raw ids pushed down into the atoms
+ * (Section 2 treats predicates this way); used to emit outputs in chunks.
+ */
+typedef struct {
+    int32_t n_vars;
+    int32_t n_atoms;
+    const int32_t* atom_arity;   /* host, [n_atoms] */
+    const int32_t* atom_vars;    /* host, [sum of arities] */
+    const int64_t* var_lo;       /* host, [n_vars] or NULL */
+    const int64_t* var_hi;       /* host, [n_vars] or NULL */
+} hc_query;
+
+typedef void* (*hc_alloc_fn)(size_t bytes, void* user);
+typedef void (*hc_free_fn)(void* ptr, void* user);
+
+/* Flags of hc_build_coco */
+#define HC_BUILD_SYMMETRIC 0x1u   /* binary relation claimed symmetric: verified on the
+                                     device; the CoCo then serves both column orders */
+
+/* Flags of hc_compute_shares / hc_join_count / hc_join_emit */
+#define HC_NO_REWRITE     0x1u    /* disable the Section 6.1 lift */
+#define HC_FORCE_MERGE    0x2u    /* reserved: search method selection */
+#define HC_FORCE_GALLOP   0x4u    /* reserved: search method selection */
+#define HC_KEEP_ORDER     0x8u    /* hc_compute_shares: use var_order_inout as given */
+
+/*
+ * Create a context on HIP device `device`, ordering work on `hip_stream` (a
+ * hipStream_t; NULL = the default stream).  alloc/free_ (nullable, both or
+ * neither) supply device memory, e.g. from a framework's caching allocator;
+ * alloc returns NULL to refuse (reported as HC_ERR_OOM).  Without them the
+ * library uses stream-ordered hipMallocAsync/hipFreeAsync.
+ * Errors: HC_ERR_INVALID (bad device, out == NULL), HC_ERR_DEVICE.
+ */
+hc_status hc_ctx_create(int device, void* hip_stream, hc_alloc_fn alloc, hc_free_fn free_,
+                        void* user, hc_ctx** out);
+void hc_ctx_destroy(hc_ctx* ctx);
+/* Message of the last failing call on ctx ("" if none).  Owned by ctx. */
+const char* hc_last_error(const hc_ctx* ctx);
+
+/*
+ * Build the CoCo index of one relation (Section 4, "Compressed Column
+ * layout"): the tuples are mapped to mixed keys, sorted lexicographically in
+ * column order col_order (the order of the atom's variables in the variable
+ * order), deduplicated (set semantics: the last level keeps no offsets), and
+ * split into levels V_r (values, one per distinct prefix) and O_r (offsets of
+ * each entry's children in level r+1; l_r + 1 entries).
+ *   tuples     device, row-major [n][arity] of dtype; borrowed for the call
+ *   n          rows, 0 <= n < 2^31
+ *   arity      1..4 (the join engine currently accepts arity <= 2)
+ *   col_order  host, permutation of 0..arity-1
+ *   key_bits   b in 1..32, or 0 = smallest b covering the largest id;
+ *              arity * b <= 64 is required
+ *   mix_seed   seed of the mixer (its low b bits are used)
+ *   flags      HC_BUILD_SYMMETRIC or 0
+ *   out        receives a library-owned handle (free with hc_coco_free, not
+ *              while a join that uses it runs)
+ * Errors: HC_ERR_INVALID (negative id, id >= 2^b, bad col_order, symmetry claim
+ * false), HC_ERR_UNSUPPORTED (arity*b > 64), HC_ERR_OOM, HC_ERR_DEVICE.
+ */
+hc_status hc_build_coco(hc_ctx* ctx, const void* tuples, int64_t n, int32_t arity, hc_dtype dtype,
+                        const int32_t* col_order, int32_t key_bits, uint64_t mix_seed,
+                        uint32_t flags, hc_coco** out);
+void hc_coco_free(hc_coco* coco);
+
+/* Statistics of a built CoCo (host struct, filled by hc_coco_get_info). */
+typedef struct {
+    int64_t n_input;            /* rows given */
+    int64_t n_unique;           /* rows after deduplication */
+    int32_t arity;
+    int32_t key_bits;
+    uint64_t mix_seed;
+    int32_t col_order[4];
+    int64_t level_len[4];       /* l_r: entries of level r */
+    int64_t max_children[4];    /* largest child list below level r (r < arity-1) */
+    int64_t distinct[4];        /* distinct values of input column c (original order) */
+    int32_t symmetric;          /* verified symmetric binary relation */
+    int32_t dtype;              /* hc_dtype of the input ids (also of emitted rows) */
+    int64_t bytes;              /* device bytes held by the index */
+} hc_coco_info;
+
+hc_status hc_coco_get_info(const hc_coco* coco, hc_coco_info* info);
+
+/*
+ * Copy level r of a CoCo to host memory: values (uint32 mixed keys,
+ * level_len[r] entries) and, for r < arity-1, offsets (int32, level_len[r]+1
+ * entries).  Either pointer may be NULL to skip it.
+ */
+hc_status hc_coco_copy_level(hc_ctx* ctx, const hc_coco* coco, int32_t level,
+                             uint32_t* values_host, int32_t* offsets_host);
+
+/*
+ * Partition sizes of a relation under per-column shares (Section 4): tuple
+ * (x_1..x_k) belongs to partition (s_1..s_k), s_c = top log2_shares[c] bits of
+ * H_b(x_c) (columns in the relation's original order).  B[s] counts the unique
+ * tuples of partition s and Bpref[s] is the exclusive prefix sum of B in
+ * lexicographic order of s, i.e. the start of partition s in the partitioned
+ * array.  B_host/Bpref_host: host, 2^(sum log2_shares) entries each.
+ * Errors: HC_ERR_INVALID if a share exceeds b or the total exceeds 2^24.
+ */
+hc_status hc_partition_sizes(hc_ctx* ctx, const hc_coco* coco, const int32_t* log2_shares,
+                             int64_t* B_host, int64_t* Bpref_host);
+
+/*
+ * Choose the variable order and the shares (Sections 6.2-6.3).  P = 2^K cells
+ * (K = log2_total_P, 0..24) are split as P = prod 2^k_v.  The cost of an order
+ * sums, over the levels, |S| * min N * log2(1 + max N / min N) bounded with the
+ * statistics of the CoCos (Lemma of Section 6.2), the rewriting moving lifted
+ * operands to their lift level; a share vector costs sum_i (prod_{j>i} P_j) *
+ * C_i (Eq. (total cost)).  Vectors costing more than twice the unpartitioned
+ * cost, or with a share P_v such that |Dom(X_v)| < 3 P_v ln P_v, are pruned;
+ * the minimum evenness E = sum_i P_sigma(i) * max(1 - i/100, 3/4) wins.
+ *   atom_index       host array of n_atoms CoCo handles (may repeat)
+ *   var_order_inout  host [n_vars]; if HC_KEEP_ORDER is set it is the order to
+ *                    use, else it receives the chosen order
+ *   log2_shares_out  host [n_vars], indexed by variable id
+ * Host-only: launches nothing.  Errors: HC_ERR_INVALID.
+ */
+hc_status hc_compute_shares(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
+                            int32_t log2_total_P, uint32_t flags, int32_t* var_order_inout,
+                            int32_t* log2_shares_out);
+
+/*
+ * Same decision from statistics only (host-only, needs no context or GPU):
+ * infos[j] describes the CoCo of atom j as hc_coco_get_info would.
+ */
+hc_status hc_compute_shares_from_info(const hc_query* q, const hc_coco_info* infos, int32_t log2_total_P,
+                                      uint32_t flags, int32_t* var_order_inout, int32_t* log2_shares_out);
+
+/*
+ * Count |Q(D)| (Section 5): every HyperCube cell (s_1..s_n), s_v in
+ * [0, 2^log2_shares[v]), runs Generic Join restricted to the key ranges of its
+ * coordinates; cells have disjoint outputs whose union is Q(D), so the count
+ * does not depend on the shares, the order or the rewriting.
+ *   atom_index   host array of n_atoms CoCo handles; the CoCo of atom j must
+ *                have its columns ordered by the positions of atom j's
+ *                variables in var_order (or be symmetric, for binary atoms)
+ *   var_order    host [n_vars], a permutation of the variables
+ *   log2_shares  host [n_vars] indexed by variable id, each 0..b, sum <= 24;
+ *                NULL = all zero
+ *   count_out    host, receives the count
+ *   digest_out   host [2] or NULL: order-independent digest of the output set
+ *                (sum and xor over the rows t, in head order with raw ids, of
+ *                h(t) = F(...F(F(c ^ (t_0 + G)) ^ (t_1 + 2G))...), F the
+ *                SplitMix64 finaliser, c = 0x6A09E667F3BCC909, G = 0x9E3779B97F4A7C15)
+ * Errors: HC_ERR_INVALID (bad query, order, shares, or CoCos that do not
+ * match), HC_ERR_UNSUPPORTED (atom arity > 2), HC_ERR_OOM, HC_ERR_DEVICE.
+ */
+hc_status hc_join_count(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
+                        const int32_t* var_order, const int32_t* log2_shares, uint32_t flags,
+                        uint64_t* count_out, uint64_t* digest_out);
+
+/*
+ * Materialise Q(D) (Section 5: each cell writes its own outputs, then they are
+ * concatenated).  out: device, row-major [capacity][n_vars] in head order,
+ * raw ids, same dtype as the CoCos' input.  n_out (host) always receives the
+ * exact number of result rows; if it exceeds capacity the call returns
+ * HC_ERR_OVERFLOW and the contents of out are unspecified.  Row order is
+ * deterministic for given inputs, order and shares, but otherwise unspecified.
+ * Other arguments and errors as hc_join_count.
+ */
+hc_status hc_join_emit(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
+                       const int32_t* var_order, const int32_t* log2_shares, uint32_t flags,
+                       void* out, int64_t capacity, int64_t* n_out);
+
+/*
+ * Describe the compiled Generic Join plan (per level: operands and the lifted
+ * intersections of Section 6.1) as JSON text into buf (host, cap bytes,
+ * NUL-terminated).  Host-only.  Errors: HC_ERR_INVALID, HC_ERR_OVERFLOW if
+ * cap is too small.
+ */
+hc_status hc_plan_describe(const hc_query* q, const int32_t* var_order, uint32_t flags,
+                           char* buf, size_t cap);
+
+/*
+ * Timing of the most recent join call on ctx, measured with HIP events on the
+ * context stream when profiling is on (hc_ctx_set_profiling): total
+ * milliseconds and launch count of the kernel that runs the deepest level of
+ * Generic Join, and of the whole call.
+ */
+typedef struct {
+    double leaf_ms;
+    int64_t leaf_launches;
+    double total_ms;
+    uint64_t leaf_items;        /* smallest-operand elements visited at the deepest level */
+} hc_timing;
+hc_status hc_ctx_set_profiling(hc_ctx* ctx, int on);
+hc_status hc_ctx_get_timing(const hc_ctx* ctx, hc_timing* t);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HC_H */

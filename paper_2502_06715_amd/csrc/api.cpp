@@ -1,0 +1,299 @@
+// C-ABI entry points: argument validation, error capture, allocation.
+#include <cstring>
+#include <exception>
+#include <new>
+
+#include "hc_internal.h"
+
+namespace hc {
+
+void fail(hc_status st, const std::string& msg) { throw Error{st, msg}; }
+
+void* Alloc::get(size_t bytes) const {
+    void* p = nullptr;
+    if (alloc) {
+        p = alloc(bytes, user);
+        if (!p) fail(HC_ERR_OOM, "allocator refused " + std::to_string(bytes) + " bytes");
+        return p;
+    }
+    hipError_t e = hipMallocAsync(&p, bytes, stream);
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        fail(HC_ERR_OOM, "hipMallocAsync of " + std::to_string(bytes) + " bytes failed");
+    }
+    return p;
+}
+
+void Alloc::put(void* p) const {
+    if (!p) return;
+    if (free_) free_(p, user);
+    else (void)hipFreeAsync(p, stream);
+}
+
+}  // namespace hc
+
+namespace {
+
+template <class F>
+hc_status guarded(hc_ctx* ctx, F&& f) {
+    try {
+        if (ctx) {
+            ctx->err.clear();
+            HC_HIP(hipSetDevice(ctx->device));
+        }
+        f();
+        return HC_OK;
+    } catch (const hc::Error& e) {
+        if (ctx) ctx->err = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        if (ctx) ctx->err = "host allocation failed";
+        return HC_ERR_OOM;
+    } catch (const std::exception& e) {
+        if (ctx) ctx->err = e.what();
+        return HC_ERR_DEVICE;
+    } catch (...) {
+        if (ctx) ctx->err = "unknown error";
+        return HC_ERR_DEVICE;
+    }
+}
+
+void check_query_ptrs(const hc_query* q) {
+    HC_REQUIRE(q != nullptr, HC_ERR_INVALID, "query is NULL");
+    HC_REQUIRE(q->n_vars >= 1 && q->n_vars <= hc::kMaxVars, HC_ERR_INVALID, "n_vars must be 1..8");
+    HC_REQUIRE(q->n_atoms >= 1 && q->n_atoms <= hc::kMaxAtoms, HC_ERR_INVALID, "n_atoms must be 1..16");
+    HC_REQUIRE(q->atom_arity && q->atom_vars, HC_ERR_INVALID, "query arrays are NULL");
+    HC_REQUIRE((q->var_lo == nullptr) == (q->var_hi == nullptr), HC_ERR_INVALID, "var_lo/var_hi: both or neither");
+}
+
+}  // namespace
+
+extern "C" {
+
+hc_status hc_ctx_create(int device, void* hip_stream, hc_alloc_fn alloc, hc_free_fn free_, void* user,
+                        hc_ctx** out) {
+    if (!out) return HC_ERR_INVALID;
+    *out = nullptr;
+    if ((alloc == nullptr) != (free_ == nullptr)) return HC_ERR_INVALID;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return HC_ERR_DEVICE;
+    if (device < 0 || device >= n) return HC_ERR_INVALID;
+    hc_ctx* c = new (std::nothrow) hc_ctx();
+    if (!c) return HC_ERR_OOM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->alloc.alloc = alloc;
+    c->alloc.free_ = free_;
+    c->alloc.user = user;
+    c->alloc.stream = c->stream;
+    hipDeviceProp_t prop;
+    if (hipSetDevice(device) != hipSuccess || hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete c;
+        return HC_ERR_DEVICE;
+    }
+    c->num_cus = prop.multiProcessorCount;
+    *out = c;
+    return HC_OK;
+}
+
+void hc_ctx_destroy(hc_ctx* ctx) { delete ctx; }
+
+const char* hc_last_error(const hc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+hc_status hc_build_coco(hc_ctx* ctx, const void* tuples, int64_t n, int32_t arity, hc_dtype dtype,
+                        const int32_t* col_order, int32_t key_bits, uint64_t mix_seed, uint32_t flags,
+                        hc_coco** out) {
+    if (!ctx) return HC_ERR_INVALID;
+    return guarded(ctx, [&] {
+        HC_REQUIRE(out != nullptr, HC_ERR_INVALID, "out is NULL");
+        *out = nullptr;
+        HC_REQUIRE(arity >= 1 && arity <= 4, HC_ERR_INVALID, "arity must be 1..4");
+        HC_REQUIRE(n >= 0 && n < ((int64_t)1 << 31), HC_ERR_INVALID, "n must be in [0, 2^31)");
+        HC_REQUIRE(n == 0 || tuples != nullptr, HC_ERR_INVALID, "tuples is NULL");
+        HC_REQUIRE(dtype == HC_I32 || dtype == HC_I64, HC_ERR_INVALID, "bad dtype");
+        HC_REQUIRE(col_order != nullptr, HC_ERR_INVALID, "col_order is NULL");
+        HC_REQUIRE(key_bits >= 0 && key_bits <= 32, HC_ERR_INVALID, "key_bits must be 0..32");
+        HC_REQUIRE((flags & ~HC_BUILD_SYMMETRIC) == 0, HC_ERR_INVALID, "unknown build flag");
+        int seen[4] = {0, 0, 0, 0};
+        for (int c = 0; c < arity; ++c) {
+            HC_REQUIRE(col_order[c] >= 0 && col_order[c] < arity && !seen[col_order[c]], HC_ERR_INVALID,
+                       "col_order must be a permutation of 0..arity-1");
+            seen[col_order[c]] = 1;
+        }
+        hc_coco* c = new hc_coco();
+        try {
+            hc::build_coco(ctx, tuples, n, arity, dtype, col_order, key_bits, mix_seed, flags, c);
+        } catch (...) {
+            hc_coco_free(c);
+            throw;
+        }
+        *out = c;
+    });
+}
+
+void hc_coco_free(hc_coco* c) {
+    if (!c) return;
+    for (int r = 0; r < 4; ++r) {
+        c->alloc.put(c->V[r]);
+        c->alloc.put(c->O[r]);
+    }
+    delete c;
+}
+
+hc_status hc_coco_get_info(const hc_coco* c, hc_coco_info* info) {
+    if (!c || !info) return HC_ERR_INVALID;
+    std::memset(info, 0, sizeof(*info));
+    info->n_input = c->n_input;
+    info->n_unique = c->n_unique;
+    info->arity = c->arity;
+    info->key_bits = c->key_bits;
+    info->mix_seed = c->mix_seed;
+    for (int r = 0; r < 4; ++r) {
+        info->col_order[r] = c->col_order[r];
+        info->level_len[r] = c->level_len[r];
+        info->max_children[r] = c->max_children[r];
+        info->distinct[r] = c->distinct[r];
+    }
+    info->symmetric = c->symmetric;
+    info->dtype = c->dtype;
+    info->bytes = c->bytes;
+    return HC_OK;
+}
+
+hc_status hc_coco_copy_level(hc_ctx* ctx, const hc_coco* c, int32_t level, uint32_t* values_host,
+                             int32_t* offsets_host) {
+    if (!ctx) return HC_ERR_INVALID;
+    return guarded(ctx, [&] {
+        HC_REQUIRE(c != nullptr, HC_ERR_INVALID, "coco is NULL");
+        HC_REQUIRE(level >= 0 && level < c->arity, HC_ERR_INVALID, "level out of range");
+        const int64_t l = c->level_len[level];
+        if (values_host && l > 0)
+            HC_HIP(hipMemcpyAsync(values_host, c->V[level], sizeof(uint32_t) * l, hipMemcpyDeviceToHost, ctx->stream));
+        if (offsets_host && level + 1 < c->arity)
+            HC_HIP(hipMemcpyAsync(offsets_host, c->O[level], sizeof(int32_t) * (l + 1), hipMemcpyDeviceToHost,
+                                  ctx->stream));
+        HC_HIP(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+hc_status hc_partition_sizes(hc_ctx* ctx, const hc_coco* c, const int32_t* log2_shares, int64_t* B_host,
+                             int64_t* Bpref_host) {
+    if (!ctx) return HC_ERR_INVALID;
+    return guarded(ctx, [&] {
+        HC_REQUIRE(c && log2_shares && B_host && Bpref_host, HC_ERR_INVALID, "NULL argument");
+        hc::partition_sizes(ctx, c, log2_shares, B_host, Bpref_host);
+    });
+}
+
+static std::vector<hc::AtomStats> stats_of(const hc_query* q, const hc_coco* const* atoms) {
+    std::vector<hc::AtomStats> st((size_t)q->n_atoms);
+    for (int j = 0; j < q->n_atoms; ++j) {
+        HC_REQUIRE(atoms[j] != nullptr, HC_ERR_INVALID, "atom CoCo handle is NULL");
+        const hc_coco* c = atoms[j];
+        HC_REQUIRE(c->arity == q->atom_arity[j], HC_ERR_INVALID, "CoCo arity does not match its atom");
+        st[j].rows = (double)c->n_unique;
+        st[j].arity = c->arity;
+        st[j].dom_bits = c->key_bits;
+        for (int k = 0; k < 4; ++k) st[j].distinct[k] = (double)c->distinct[k];
+    }
+    return st;
+}
+
+hc_status hc_compute_shares(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
+                            int32_t log2_total_P, uint32_t flags, int32_t* var_order_inout,
+                            int32_t* log2_shares_out) {
+    if (!ctx) return HC_ERR_INVALID;
+    return guarded(ctx, [&] {
+        check_query_ptrs(q);
+        HC_REQUIRE(atom_index && var_order_inout && log2_shares_out, HC_ERR_INVALID, "NULL argument");
+        HC_REQUIRE(log2_total_P >= 0 && log2_total_P <= 24, HC_ERR_INVALID, "log2_total_P must be 0..24");
+        hc::validate_query(q, 4);
+        auto st = stats_of(q, atom_index);
+        hc::choose_shares(q, st, log2_total_P, flags, var_order_inout, log2_shares_out);
+    });
+}
+
+hc_status hc_compute_shares_from_info(const hc_query* q, const hc_coco_info* infos, int32_t log2_total_P,
+                                      uint32_t flags, int32_t* var_order_inout, int32_t* log2_shares_out) {
+    try {
+        check_query_ptrs(q);
+        HC_REQUIRE(infos && var_order_inout && log2_shares_out, HC_ERR_INVALID, "NULL argument");
+        HC_REQUIRE(log2_total_P >= 0 && log2_total_P <= 24, HC_ERR_INVALID, "log2_total_P must be 0..24");
+        hc::validate_query(q, 4);
+        std::vector<hc::AtomStats> st((size_t)q->n_atoms);
+        for (int j = 0; j < q->n_atoms; ++j) {
+            HC_REQUIRE(infos[j].arity == q->atom_arity[j], HC_ERR_INVALID, "info arity does not match its atom");
+            st[j].rows = (double)infos[j].n_unique;
+            st[j].arity = infos[j].arity;
+            st[j].dom_bits = infos[j].key_bits;
+            for (int k = 0; k < 4; ++k) st[j].distinct[k] = (double)infos[j].distinct[k];
+        }
+        hc::choose_shares(q, st, log2_total_P, flags, var_order_inout, log2_shares_out);
+        return HC_OK;
+    } catch (const hc::Error& e) {
+        return e.st;
+    } catch (...) {
+        return HC_ERR_INVALID;
+    }
+}
+
+hc_status hc_join_count(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
+                        const int32_t* var_order, const int32_t* log2_shares, uint32_t flags,
+                        uint64_t* count_out, uint64_t* digest_out) {
+    if (!ctx) return HC_ERR_INVALID;
+    return guarded(ctx, [&] {
+        check_query_ptrs(q);
+        HC_REQUIRE(atom_index && var_order && count_out, HC_ERR_INVALID, "NULL argument");
+        hc::join_run(ctx, q, atom_index, var_order, log2_shares, flags, false, count_out, digest_out, nullptr, 0,
+                     nullptr);
+    });
+}
+
+hc_status hc_join_emit(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
+                       const int32_t* var_order, const int32_t* log2_shares, uint32_t flags, void* out,
+                       int64_t capacity, int64_t* n_out) {
+    if (!ctx) return HC_ERR_INVALID;
+    return guarded(ctx, [&] {
+        check_query_ptrs(q);
+        HC_REQUIRE(atom_index && var_order && n_out, HC_ERR_INVALID, "NULL argument");
+        HC_REQUIRE(capacity >= 0, HC_ERR_INVALID, "capacity must be >= 0");
+        HC_REQUIRE(capacity == 0 || out != nullptr, HC_ERR_INVALID, "out is NULL");
+        uint64_t count = 0;
+        hc::join_run(ctx, q, atom_index, var_order, log2_shares, flags, true, &count, nullptr, out, capacity,
+                     n_out);
+        *n_out = (int64_t)count;
+        if ((int64_t)count > capacity)
+            hc::fail(HC_ERR_OVERFLOW, "hc_join_emit: " + std::to_string(count) + " rows exceed capacity " +
+                                          std::to_string(capacity));
+    });
+}
+
+hc_status hc_plan_describe(const hc_query* q, const int32_t* var_order, uint32_t flags, char* buf, size_t cap) {
+    try {
+        check_query_ptrs(q);
+        HC_REQUIRE(var_order && buf, HC_ERR_INVALID, "NULL argument");
+        hc::Plan p = hc::compile_plan(q, var_order, !(flags & HC_NO_REWRITE));
+        std::string s = hc::describe_plan(p);
+        if (s.size() + 1 > cap) return HC_ERR_OVERFLOW;
+        std::memcpy(buf, s.c_str(), s.size() + 1);
+        return HC_OK;
+    } catch (const hc::Error& e) {
+        return e.st;
+    } catch (...) {
+        return HC_ERR_INVALID;
+    }
+}
+
+hc_status hc_ctx_set_profiling(hc_ctx* ctx, int on) {
+    if (!ctx) return HC_ERR_INVALID;
+    ctx->profiling = on ? 1 : 0;
+    return HC_OK;
+}
+
+hc_status hc_ctx_get_timing(const hc_ctx* ctx, hc_timing* t) {
+    if (!ctx || !t) return HC_ERR_INVALID;
+    *t = ctx->timing;
+    return HC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,210 @@
+// Internal declarations of the gfx950 Generic Join library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hc.h"
+
+namespace hc {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+    hc_status st;
+    std::string msg;
+};
+[[noreturn]] void fail(hc_status st, const std::string& msg);
+#define HC_HIP(call)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            ::hc::fail(HC_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+#define HC_REQUIRE(cond, st, msg) \
+    do {                          \
+        if (!(cond)) ::hc::fail((st), (msg)); \
+    } while (0)
+
+// ---------------------------------------------------------------- bijective b-bit mixer
+// H_b: Wellons' lowbias32 (xorshift, odd multiply, xorshift, odd multiply, xorshift)
+// restricted to b-bit words; shifts ceil(b/2), max(1, ceil(b/2)-1), ceil(b/2).
+struct Mixer {
+    uint32_t mask, seed;
+    uint32_t s1, s2, s3;
+    uint32_t c1, c2, c1inv, c2inv;
+    int32_t b;
+};
+Mixer make_mixer(int b, uint64_t seed);
+
+__host__ __device__ inline uint32_t mix_key(uint32_t x, const Mixer& m) {
+    x = (x ^ m.seed) & m.mask;
+    x ^= x >> m.s1;
+    x = (x * m.c1) & m.mask;
+    x ^= x >> m.s2;
+    x = (x * m.c2) & m.mask;
+    x ^= x >> m.s3;
+    return x;
+}
+__host__ __device__ inline uint32_t unxorshift(uint32_t y, uint32_t s, int b) {
+    uint32_t x = y;
+    for (int k = (int)s; k < b; k += (int)s) x ^= y >> k;
+    return x;
+}
+__host__ __device__ inline uint32_t unmix_key(uint32_t y, const Mixer& m) {
+    uint32_t x = unxorshift(y, m.s3, m.b);
+    x = (x * m.c2inv) & m.mask;
+    x = unxorshift(x, m.s2, m.b);
+    x = (x * m.c1inv) & m.mask;
+    x = unxorshift(x, m.s1, m.b);
+    return (x ^ m.seed) & m.mask;
+}
+
+// ---------------------------------------------------------------- memory
+struct Alloc {
+    hc_alloc_fn alloc = nullptr;
+    hc_free_fn free_ = nullptr;
+    void* user = nullptr;
+    hipStream_t stream = nullptr;
+    void* get(size_t bytes) const;
+    void put(void* p) const;
+};
+
+template <class T>
+struct DevBuf {
+    const Alloc* a = nullptr;
+    T* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const Alloc& al, size_t count) : a(&al), n(count) {
+        p = static_cast<T*>(al.get(sizeof(T) * (count ? count : 1)));
+    }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : a(o.a), p(o.p), n(o.n) { o.p = nullptr; }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        reset();
+        a = o.a; p = o.p; n = o.n; o.p = nullptr;
+        return *this;
+    }
+    void reset() {
+        if (p && a) a->put(p);
+        p = nullptr;
+        n = 0;
+    }
+    ~DevBuf() { reset(); }
+};
+
+}  // namespace hc
+
+// ---------------------------------------------------------------- handles
+struct hc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hc::Alloc alloc;
+    std::string err;
+    int profiling = 0;
+    hc_timing timing{};
+    int num_cus = 256;
+};
+
+struct hc_coco {
+    hc::Alloc alloc;
+    int32_t arity = 0;
+    int32_t key_bits = 0;
+    uint64_t mix_seed = 0;
+    int32_t col_order[4] = {0, 1, 2, 3};
+    hc_dtype dtype = HC_I32;
+    int64_t n_input = 0, n_unique = 0;
+    int64_t level_len[4] = {0, 0, 0, 0};
+    int64_t max_children[4] = {0, 0, 0, 0};
+    int64_t distinct[4] = {0, 0, 0, 0};
+    int32_t symmetric = 0;
+    uint32_t* V[4] = {nullptr, nullptr, nullptr, nullptr};
+    int32_t* O[4] = {nullptr, nullptr, nullptr, nullptr};
+    int64_t bytes = 0;
+};
+
+namespace hc {
+
+// ---------------------------------------------------------------- primitives (prim.hip)
+// Exclusive prefix sum of u32 counts into u64 (out has n+1 entries; out[n] = total).
+void scan_u32_to_u64(const Alloc& a, const uint32_t* in, uint64_t* out, int64_t n, hipStream_t s);
+void scan_u64(const Alloc& a, const uint64_t* in, uint64_t* out, int64_t n, hipStream_t s);
+// Exclusive prefix of popcounts of 64-bit words (out has n+1 entries).
+void scan_popc(const Alloc& a, const uint64_t* words, uint64_t* out, int64_t n, hipStream_t s);
+// LSD radix sort of u64 keys over their low `bits` bits; result in *keys (buffers swapped).
+void radix_sort_u64(const Alloc& a, DevBuf<uint64_t>& keys, DevBuf<uint64_t>& tmp, int64_t n, int bits,
+                    hipStream_t s);
+
+// ---------------------------------------------------------------- build (build.hip)
+void build_coco(hc_ctx* ctx, const void* tuples, int64_t n, int arity, hc_dtype dtype,
+                const int32_t* col_order, int key_bits, uint64_t seed, uint32_t flags, hc_coco* out);
+void partition_sizes(hc_ctx* ctx, const hc_coco* c, const int32_t* log2_shares, int64_t* B,
+                     int64_t* Bpref);
+
+// ---------------------------------------------------------------- plan (plan.cpp)
+constexpr int kMaxVars = 8;
+constexpr int kMaxAtoms = 16;
+constexpr int kMaxOps = 8;      // operands of one level intersection
+constexpr int kMaxGroups = 8;
+
+enum OpKind : int32_t { OP_V0 = 0, OP_CHILD = 1, OP_TMP = 2 };
+
+struct PlanOp {
+    int32_t kind;
+    int32_t atom;     // atom index (V0 / CHILD)
+    int32_t group;    // lifted group (TMP)
+};
+
+struct PlanGroup {           // a lifted intersection (Section 6.1)
+    int32_t var;
+    int32_t consumer;        // level (0-based) whose loop consumes it
+    int32_t lift;            // computed on frontier F_lift (lift vars bound)
+    int32_t n_ops;
+    PlanOp ops[kMaxOps];     // V0 / CHILD operands only
+};
+
+struct PlanLevel {
+    int32_t var;
+    int32_t n_ops;
+    PlanOp ops[kMaxOps];     // after lifting: V0 / CHILD / TMP
+    int32_t n_new_nodes;     // atoms whose first variable is bound here and which have a child level
+    int32_t new_node_atom[kMaxAtoms];
+};
+
+struct Plan {
+    int32_t n_vars = 0, n_atoms = 0;
+    int32_t order[kMaxVars];
+    int32_t pos[kMaxVars];           // level of each variable
+    int32_t atom_arity[kMaxAtoms];
+    int32_t atom_first[kMaxAtoms];   // variable at CoCo level 0
+    int32_t atom_second[kMaxAtoms];  // variable at CoCo level 1 (-1 for unary)
+    int32_t n_groups = 0;
+    PlanGroup groups[kMaxGroups];
+    PlanLevel levels[kMaxVars];
+};
+
+// Validates q and order; builds the per-level plan with (optionally) the lift rule.
+Plan compile_plan(const hc_query* q, const int32_t* order, bool rewrite);
+std::string describe_plan(const Plan& p);
+// Validate the query alone (variables covered, arities, repeated variables).
+void validate_query(const hc_query* q, int max_arity);
+
+struct AtomStats {
+    double rows;           // |R_j| (unique)
+    double distinct[4];    // distinct values per original column
+    int32_t arity;
+    int32_t dom_bits;
+};
+void choose_shares(const hc_query* q, const std::vector<AtomStats>& st, int K, uint32_t flags,
+                   int32_t* order_inout, int32_t* shares_out);
+
+// ---------------------------------------------------------------- join (join.hip)
+void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
+              const int32_t* shares, uint32_t flags, bool emit, uint64_t* count, uint64_t* digest,
+              void* out, int64_t capacity, int64_t* n_out);
+
+}  // namespace hc

@@ -1,0 +1,881 @@
+// Generic Join over CoCo with HyperCube cells (Sections 2, 5, 6.1).
+//
+// Execution model.  A frontier F_i holds one entry per binding of the first i
+// variables of the order, tagged with the HyperCube cell it belongs to:
+//   word 0          cell id (coordinates of every variable packed together)
+//   words 1..i      the bound values (mixed keys)
+//   node words      for every binary atom whose first variable is bound and
+//                   whose second is not: the index of the bound value in the
+//                   atom's top level (its child list is O0[node]..O0[node+1])
+//   tmp words       (offset, length) of the lifted intersections that are live
+// F_0 holds one entry per cell, so every cell runs its own Generic Join
+// restricted to the key range of its coordinates (Section 5); the key range of
+// coordinate s of a variable with share 2^k is [s << (b-k), (s+1) << (b-k)),
+// which is a contiguous sub-range of every sorted CoCo array.
+//
+// Level i expands F_i into F_{i+1}: for every entry it intersects the level's
+// operands (Section 5, "multiway intersection"; Section 2: iterate the
+// smallest set, probe the others).  On the GPU the iteration elements of all
+// entries are flattened into one index space by a prefix sum over the
+// per-entry sizes, so every wave64 gets 64 consecutive elements whatever the
+// skew (the load balancing the paper gets from work stealing); each lane
+// probes the other operands by binary search, and a ballot gives one 64-bit
+// match word per wave.  A scan over the match words' popcounts gives every
+// match its output slot, so frontiers, temporary results and emitted rows are
+// compact, ordered and deterministic.  The deepest level only counts (or
+// digests, or writes rows).
+//
+// Lifted intersections (Section 6.1) are computed the same way on the frontier
+// where they are lifted to, stored as sorted arrays in a pool together with
+// the top-level positions of their sources, and referenced by (offset, length)
+// from the entries until the consuming level.
+#include <algorithm>
+
+#include "prim_dev.h"
+
+namespace hc {
+
+constexpr int kMaxW = 32;   // words per frontier entry
+
+struct DAtom {
+    const uint32_t* V0;
+    const int32_t* O0;
+    const uint32_t* V1;
+    int64_t l0;
+};
+
+struct KData {
+    DAtom atoms[kMaxAtoms];
+    const uint32_t* tmp_val[kMaxGroups];
+    const int32_t* tmp_src[kMaxGroups][kMaxOps];
+    Mixer mix;
+    int32_t b;
+    int32_t dtype64;
+};
+
+struct KOp {
+    int32_t kind;
+    int32_t atom;
+    int32_t word;     // CHILD: entry word of the parent node; TMP: entry word of (offset, length)
+    int32_t group;    // TMP
+    const int2* v0_range;   // V0 restricted by the cell: table indexed by the coordinate (or null)
+};
+
+struct KStep {
+    int32_t n_ops;
+    KOp ops[kMaxOps];
+    int32_t W_in;
+    int32_t k_share;          // log2 share of the variable bound by this step
+    int32_t cell_shift;       // bit position of its coordinate in the cell id
+    int32_t has_pred;
+    int64_t pred_lo, pred_hi;
+    // EXPAND output
+    int32_t W_out;
+    int32_t n_copy;
+    int8_t copy_from[kMaxW], copy_to[kMaxW];
+    int32_t val_word;
+    int32_t n_new;
+    int8_t new_word[kMaxAtoms], new_op[kMaxAtoms], new_src[kMaxAtoms];
+    int32_t n_zero;
+    int8_t zero_word[kMaxW];
+    // TMP output
+    int32_t group;
+    int32_t n_src;
+    int8_t src_op[kMaxOps];
+    // EMIT / DIGEST
+    int32_t n_vars;
+    int8_t head_word[kMaxVars];   // entry word of each head variable, -1 = the value bound here
+};
+
+enum Mode { M_COUNT = 0, M_DIGEST = 1, M_BITMAP = 2 };
+enum MatMode { MAT_EXPAND = 0, MAT_TMP = 1, MAT_EMIT = 2 };
+
+struct Seg {
+    int32_t* seg;      // [2*n_ops][stride]: begin, end per operand
+    uint8_t* iter;     // operand iterated
+    uint32_t* m;       // its length (0 if any operand is empty)
+    int64_t stride;
+};
+
+__device__ inline const uint32_t* op_array(const KData& D, const KOp& o) {
+    if (o.kind == OP_V0) return D.atoms[o.atom].V0;
+    if (o.kind == OP_CHILD) return D.atoms[o.atom].V1;
+    return D.tmp_val[o.group];
+}
+
+__global__ void k_init_cells(int32_t* F, int64_t n, int W) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        F[e * W] = (int32_t)e;
+        for (int w = 1; w < W; ++w) F[e * W + w] = 0;
+    }
+}
+
+// Key ranges of a top level, one per coordinate value of a share 2^k.
+__global__ void k_v0_ranges(const uint32_t* V0, int64_t l0, int b, int k, int2* out) {
+    const int64_t ncoord = (int64_t)1 << k;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < ncoord; s += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t lo = (uint64_t)s << (b - k), hi = (uint64_t)(s + 1) << (b - k);
+        const int64_t a = lower_bound_u32(V0, 0, l0, (uint32_t)lo);
+        const int64_t z = hi >= (1ull << 32) ? l0 : lower_bound_u32(V0, a, l0, (uint32_t)hi);
+        out[s] = make_int2((int)a, (int)z);
+    }
+}
+
+// Resolve every operand of every entry to a [begin, end) range, restricted to the cell.
+__global__ __launch_bounds__(kBlock) void k_prep(KData D, KStep S, const int32_t* __restrict__ F, int64_t e0,
+                                                 int64_t n, Seg G) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = e0 + t;
+        const int32_t* ent = F + e * S.W_in;
+        const uint32_t cell = (uint32_t)ent[0];
+        const bool restrict_ = S.k_share > 0;
+        const uint32_t coord = restrict_ ? (cell >> S.cell_shift) & ((1u << S.k_share) - 1u) : 0u;
+        const uint64_t lo = (uint64_t)coord << (D.b - S.k_share);
+        const uint64_t hi = (uint64_t)(coord + 1) << (D.b - S.k_share);
+        uint32_t best_len = 0xFFFFFFFFu;
+        int best = 0;
+        bool empty = false;
+        for (int o = 0; o < S.n_ops; ++o) {
+            const KOp& op = S.ops[o];
+            int64_t beg, end;
+            if (op.kind == OP_V0) {
+                if (restrict_ && op.v0_range) {
+                    const int2 r = op.v0_range[coord];
+                    beg = r.x;
+                    end = r.y;
+                } else {
+                    beg = 0;
+                    end = D.atoms[op.atom].l0;
+                }
+            } else if (op.kind == OP_CHILD) {
+                const int32_t node = ent[op.word];
+                const int32_t* O = D.atoms[op.atom].O0;
+                beg = O[node];
+                end = O[node + 1];
+                if (restrict_) {
+                    const uint32_t* A = D.atoms[op.atom].V1;
+                    const int64_t b2 = lower_bound_u32(A, beg, end, (uint32_t)lo);
+                    end = hi >= (1ull << 32) ? end : lower_bound_u32(A, b2, end, (uint32_t)hi);
+                    beg = b2;
+                }
+            } else {
+                beg = ent[op.word];
+                end = beg + ent[op.word + 1];
+            }
+            G.seg[(2 * o) * G.stride + e] = (int32_t)beg;
+            G.seg[(2 * o + 1) * G.stride + e] = (int32_t)end;
+            const uint32_t len = (uint32_t)(end - beg);
+            if (len == 0) empty = true;
+            if (len < best_len) {
+                best_len = len;
+                best = o;
+            }
+        }
+        G.iter[e] = (uint8_t)best;
+        G.m[e] = empty ? 0u : best_len;
+    }
+}
+
+// Largest e in [lo, hi) with prefix[e] <= g (prefix[lo] <= g is required).
+__device__ inline int64_t find_entry(const uint64_t* __restrict__ prefix, int64_t lo, int64_t hi, uint64_t g) {
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline uint64_t fmix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+struct Probe {
+    bool found;
+    uint32_t a;
+    int64_t e;
+    int64_t pos[kMaxOps];
+};
+
+// Evaluate flattened element g: entry, value, and whether every operand holds it.
+__device__ inline void probe_item(const KData& D, const KStep& S, const Seg& G, const uint64_t* prefix, int64_t e,
+                                  uint64_t g, Probe& P) {
+    P.e = e;
+    const int it = G.iter[e];
+    const int64_t ib = G.seg[(2 * it) * G.stride + e];
+    const int64_t ipos = ib + (int64_t)(g - prefix[e]);
+    const uint32_t a = op_array(D, S.ops[it])[ipos];
+    P.a = a;
+    bool found = true;
+#pragma unroll
+    for (int o = 0; o < kMaxOps; ++o) {
+        if (o >= S.n_ops) break;
+        if (o == it) {
+            P.pos[o] = ipos;
+            continue;
+        }
+        if (!found) continue;
+        const uint32_t* arr = op_array(D, S.ops[o]);
+        const int64_t beg = G.seg[(2 * o) * G.stride + e];
+        const int64_t end = G.seg[(2 * o + 1) * G.stride + e];
+        const int64_t p = lower_bound_u32(arr, beg, end, a);
+        P.pos[o] = p;
+        found = p < end && arr[p] == a;
+    }
+    if (found && S.has_pred) {
+        const int64_t raw = (int64_t)unmix_key(a, D.mix);
+        found = raw >= S.pred_lo && raw < S.pred_hi;
+    }
+    P.found = found;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_probe(KData D, KStep S, const int32_t* __restrict__ F, Seg G,
+                                                  const uint64_t* __restrict__ prefix, int64_t e_begin,
+                                                  int64_t e_end, uint64_t item_begin, uint64_t n_items,
+                                                  uint64_t* __restrict__ words, unsigned long long* acc) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t n_words = (int64_t)((n_items + 63) / 64);
+    uint64_t cnt = 0, dsum = 0, dxor = 0;
+    for (int64_t w = wave; w < n_words; w += nwaves) {
+        const uint64_t rel = (uint64_t)w * 64 + lane;
+        const bool valid = rel < n_items;
+        const uint64_t g_first = item_begin + (uint64_t)w * 64;
+        const uint64_t last_rel = ((uint64_t)w * 64 + 63 < n_items) ? (uint64_t)w * 64 + 63 : n_items - 1;
+        const int64_t e_lo = find_entry(prefix, e_begin, e_end, g_first);
+        const int64_t e_hi = find_entry(prefix, e_lo, e_end, item_begin + last_rel);
+        Probe P;
+        P.found = false;
+        if (valid) {
+            const uint64_t g = item_begin + rel;
+            probe_item(D, S, G, prefix, find_entry(prefix, e_lo, e_hi + 1, g), g, P);
+        }
+        const uint64_t bal = __ballot(P.found);
+        if (MODE == M_BITMAP) {
+            if (lane == 0) words[w] = bal;
+        } else {
+            cnt += (uint64_t)__popcll(bal);
+            if (MODE == M_DIGEST && P.found) {
+                const int32_t* ent = F + P.e * S.W_in;
+                uint64_t h = 0x6A09E667F3BCC909ull;
+                for (int v = 0; v < S.n_vars; ++v) {
+                    const int hw = S.head_word[v];
+                    const uint32_t key = hw < 0 ? P.a : (uint32_t)ent[hw];
+                    const uint64_t raw = (uint64_t)unmix_key(key, D.mix);
+                    h = fmix64(h ^ (raw + (uint64_t)(v + 1) * 0x9E3779B97F4A7C15ull));
+                }
+                dsum += h;
+                dxor ^= h;
+            }
+        }
+    }
+    if (MODE != M_BITMAP) {
+        // cnt is wave-uniform (sum of ballots); digest terms are per lane
+        if (MODE == M_DIGEST) {
+            dsum = wave_sum(dsum);
+            dxor = wave_xor(dxor);
+        }
+        if (lane == 0) {
+            if (cnt) atomicAdd(&acc[0], (unsigned long long)cnt);
+            if (MODE == M_DIGEST) {
+                atomicAdd(&acc[1], (unsigned long long)dsum);
+                atomicXor(&acc[2], (unsigned long long)dxor);
+            }
+        }
+    }
+}
+
+struct MatOut {
+    int32_t* F;            // EXPAND
+    uint32_t* tval;        // TMP
+    int32_t* tsrc[kMaxOps];
+    void* rows;            // EMIT
+    int64_t row_base, row_cap;
+};
+
+template <int MAT>
+__global__ __launch_bounds__(kBlock) void k_materialize(KData D, KStep S, const int32_t* __restrict__ F, Seg G,
+                                                        const uint64_t* __restrict__ prefix, int64_t e_begin,
+                                                        int64_t e_end, uint64_t item_begin, uint64_t n_items,
+                                                        const uint64_t* __restrict__ words,
+                                                        const uint64_t* __restrict__ wprefix, MatOut out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t n_words = (int64_t)((n_items + 63) / 64);
+    for (int64_t w = wave; w < n_words; w += nwaves) {
+        const uint64_t bal = words[w];
+        if (bal == 0) continue;
+        const uint64_t rel = (uint64_t)w * 64 + lane;
+        const uint64_t g_first = item_begin + (uint64_t)w * 64;
+        const uint64_t last_rel = ((uint64_t)w * 64 + 63 < n_items) ? (uint64_t)w * 64 + 63 : n_items - 1;
+        const int64_t e_lo = find_entry(prefix, e_begin, e_end, g_first);
+        const int64_t e_hi = find_entry(prefix, e_lo, e_end, item_begin + last_rel);
+        if (!((bal >> lane) & 1ull)) continue;
+        const uint64_t g = item_begin + rel;
+        Probe P;
+        probe_item(D, S, G, prefix, find_entry(prefix, e_lo, e_hi + 1, g), g, P);
+        const int64_t rank = (int64_t)(wprefix[w] + (uint64_t)__popcll(bal & lanemask_lt()));
+        const int32_t* ent = F + P.e * S.W_in;
+        if (MAT == MAT_EXPAND) {
+            int32_t* o = out.F + rank * S.W_out;
+            for (int c = 0; c < S.n_copy; ++c) o[S.copy_to[c]] = ent[S.copy_from[c]];
+            o[S.val_word] = (int32_t)P.a;
+            for (int t = 0; t < S.n_new; ++t) {
+                const int op = S.new_op[t];
+                const int64_t p = P.pos[op];
+                o[S.new_word[t]] = S.ops[op].kind == OP_TMP ? D.tmp_src[S.ops[op].group][S.new_src[t]][p] : (int32_t)p;
+            }
+            for (int z = 0; z < S.n_zero; ++z) o[S.zero_word[z]] = 0;
+        } else if (MAT == MAT_TMP) {
+            out.tval[rank] = P.a;
+            for (int t = 0; t < S.n_src; ++t) out.tsrc[t][rank] = (int32_t)P.pos[S.src_op[t]];
+        } else {
+            const int64_t row = out.row_base + rank;
+            if (row < out.row_cap) {
+                for (int v = 0; v < S.n_vars; ++v) {
+                    const int hw = S.head_word[v];
+                    const uint32_t key = hw < 0 ? P.a : (uint32_t)ent[hw];
+                    const uint32_t raw = unmix_key(key, D.mix);
+                    if (D.dtype64) ((int64_t*)out.rows)[row * S.n_vars + v] = (int64_t)raw;
+                    else ((int32_t*)out.rows)[row * S.n_vars + v] = (int32_t)raw;
+                }
+            }
+        }
+    }
+}
+
+// (offset, length) of every entry's temporary result, from the match words.
+__global__ void k_tmp_refs(int32_t* F, int W, int word, const uint64_t* __restrict__ prefix, int64_t e_begin,
+                           int64_t e_end, uint64_t item_begin, const uint64_t* __restrict__ words,
+                           const uint64_t* __restrict__ wprefix, int64_t pool_base) {
+    auto rank = [&](uint64_t g) -> uint64_t {
+        const uint64_t rel = g - item_begin;
+        const uint64_t w = rel >> 6, bit = rel & 63;
+        uint64_t r = wprefix[w];
+        if (bit) r += (uint64_t)__popcll(words[w] & ((1ull << bit) - 1ull));
+        return r;
+    };
+    for (int64_t e = e_begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e_end;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t r0 = rank(prefix[e]), r1 = rank(prefix[e + 1]);
+        F[e * W + word] = (int32_t)(pool_base + (int64_t)r0);
+        F[e * W + word + 1] = (int32_t)(r1 - r0);
+    }
+}
+
+// Largest e in [lo, hi] with prefix[e] - prefix[lo] <= budget (at least lo+1 when possible).
+__global__ void k_split(const uint64_t* prefix, int64_t lo, int64_t hi, uint64_t budget, int64_t* out) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const uint64_t base = prefix[lo];
+    int64_t a = lo, z = hi;   // invariant: prefix[a] - base <= budget
+    while (a < z) {
+        const int64_t mid = (a + z + 1) >> 1;
+        if (prefix[mid] - base <= budget) a = mid; else z = mid - 1;
+    }
+    if (a == lo && lo < hi) a = lo + 1;   // a single entry always makes progress
+    *out = a;
+}
+
+// ---------------------------------------------------------------- host driver
+static unsigned grid_for(int64_t n, int64_t cap = 16384) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+static unsigned grid_waves(int64_t n_words, int64_t cap = 8192) {
+    int64_t g = (n_words + kWaves - 1) / kWaves;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+struct Layout {
+    int W;
+    int node_word[kMaxAtoms];
+    int tmp_word[kMaxGroups];
+};
+
+struct Runner {
+    hc_ctx* ctx;
+    const Alloc& A;
+    hipStream_t s;
+    Plan P;
+    KData D;
+    Layout lay[kMaxVars + 1];
+    KStep level_step[kMaxVars];
+    KStep group_step[kMaxGroups];
+    int shares[kMaxVars];
+    int cell_shift[kMaxVars];
+    int K;
+    bool emit, digest;
+    int64_t cap_entries;
+    DevBuf<unsigned long long> acc;
+    DevBuf<int64_t> split;
+    std::vector<DevBuf<int2>> ranges;
+    DevBuf<uint32_t> tmp_val[kMaxGroups];
+    DevBuf<int32_t> tmp_src[kMaxGroups][kMaxOps];
+    int64_t tmp_cap = 0;
+    // emit
+    void* out_rows = nullptr;
+    int64_t out_cap = 0, out_count = 0;
+    // profiling
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double leaf_ms = 0;
+    int64_t leaf_launches = 0;
+    uint64_t leaf_items = 0;
+
+    Runner(hc_ctx* c) : ctx(c), A(c->alloc), s(c->stream) {}
+    ~Runner() {
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+    }
+
+    uint64_t read_u64(const uint64_t* p) {
+        uint64_t v = 0;
+        HC_HIP(hipMemcpyAsync(&v, p, sizeof(v), hipMemcpyDeviceToHost, s));
+        HC_HIP(hipStreamSynchronize(s));
+        return v;
+    }
+
+    void setup_layouts() {
+        const int n = P.n_vars;
+        for (int i = 0; i <= n; ++i) {
+            Layout& L = lay[i];
+            int w = 1 + i;
+            for (int j = 0; j < kMaxAtoms; ++j) L.node_word[j] = -1;
+            for (int g = 0; g < kMaxGroups; ++g) L.tmp_word[g] = -1;
+            for (int j = 0; j < P.n_atoms; ++j) {
+                if (P.atom_second[j] < 0) continue;
+                const int pf = P.pos[P.atom_first[j]], ps = P.pos[P.atom_second[j]];
+                if (pf < i && i <= ps) L.node_word[j] = w++;
+            }
+            for (int g = 0; g < P.n_groups; ++g)
+                if (P.groups[g].lift <= i && i <= P.groups[g].consumer) {
+                    L.tmp_word[g] = w;
+                    w += 2;
+                }
+            HC_REQUIRE(w <= kMaxW, HC_ERR_UNSUPPORTED, "frontier entry too wide");
+            L.W = w;
+        }
+    }
+
+    KOp make_op(const PlanOp& po, const Layout& L, int var) {
+        KOp o{};
+        o.kind = po.kind;
+        o.atom = po.atom;
+        o.group = po.group;
+        o.word = -1;
+        o.v0_range = nullptr;
+        if (po.kind == OP_CHILD) o.word = L.node_word[po.atom];
+        if (po.kind == OP_TMP) o.word = L.tmp_word[po.group];
+        if (po.kind == OP_V0 && shares[var] > 0) {
+            const int k = shares[var];
+            ranges.emplace_back(A, (size_t)1 << k);
+            const DAtom& a = D.atoms[po.atom];
+            k_v0_ranges<<<grid_for((int64_t)1 << k), kBlock, 0, s>>>(a.V0, a.l0, D.b, k, ranges.back().p);
+            HC_HIP(hipGetLastError());
+            o.v0_range = ranges.back().p;
+        }
+        return o;
+    }
+
+    void setup_steps(const hc_query* q) {
+        const int n = P.n_vars;
+        for (int i = 0; i < n; ++i) {
+            const PlanLevel& PL = P.levels[i];
+            KStep& S = level_step[i];
+            S = KStep{};
+            const Layout& Li = lay[i];
+            const Layout& Lo = lay[i + 1];
+            S.n_ops = PL.n_ops;
+            for (int t = 0; t < PL.n_ops; ++t) S.ops[t] = make_op(PL.ops[t], Li, PL.var);
+            S.W_in = Li.W;
+            S.k_share = shares[PL.var];
+            S.cell_shift = cell_shift[PL.var];
+            S.has_pred = q->var_lo != nullptr;
+            if (S.has_pred) {
+                S.pred_lo = q->var_lo[PL.var];
+                S.pred_hi = q->var_hi[PL.var];
+            }
+            S.W_out = Lo.W;
+            S.n_copy = 0;
+            auto copy = [&](int from, int to) {
+                S.copy_from[S.n_copy] = (int8_t)from;
+                S.copy_to[S.n_copy] = (int8_t)to;
+                ++S.n_copy;
+            };
+            for (int w = 0; w <= i; ++w) copy(w, w);   // cell and bound values
+            S.val_word = i + 1;
+            S.n_new = 0;
+            S.n_zero = 0;
+            for (int j = 0; j < P.n_atoms; ++j) {
+                if (Lo.node_word[j] < 0) continue;
+                if (Li.node_word[j] >= 0) {
+                    copy(Li.node_word[j], Lo.node_word[j]);
+                    continue;
+                }
+                // new node: the atom's first variable is bound at this level
+                int op = -1, src = -1;
+                for (int t = 0; t < PL.n_ops; ++t)
+                    if (PL.ops[t].kind == OP_V0 && PL.ops[t].atom == j) op = t;
+                if (op < 0) {
+                    for (int t = 0; t < PL.n_ops; ++t)
+                        if (PL.ops[t].kind == OP_TMP) {
+                            const PlanGroup& g = P.groups[PL.ops[t].group];
+                            int sidx = 0;
+                            for (int u = 0; u < g.n_ops; ++u) {
+                                if (g.ops[u].kind != OP_V0) continue;
+                                if (g.ops[u].atom == j) {
+                                    op = t;
+                                    src = sidx;
+                                }
+                                ++sidx;
+                            }
+                        }
+                }
+                HC_REQUIRE(op >= 0, HC_ERR_DEVICE, "plan: no source for a node");
+                S.new_word[S.n_new] = (int8_t)Lo.node_word[j];
+                S.new_op[S.n_new] = (int8_t)op;
+                S.new_src[S.n_new] = (int8_t)(src < 0 ? 0 : src);
+                ++S.n_new;
+            }
+            for (int g = 0; g < P.n_groups; ++g) {
+                if (Lo.tmp_word[g] < 0) continue;
+                if (Li.tmp_word[g] >= 0) {
+                    copy(Li.tmp_word[g], Lo.tmp_word[g]);
+                    copy(Li.tmp_word[g] + 1, Lo.tmp_word[g] + 1);
+                } else {
+                    S.zero_word[S.n_zero++] = (int8_t)Lo.tmp_word[g];
+                    S.zero_word[S.n_zero++] = (int8_t)(Lo.tmp_word[g] + 1);
+                }
+            }
+            S.n_vars = n;
+            for (int v = 0; v < n; ++v) S.head_word[v] = (int8_t)(P.pos[v] < i ? 1 + P.pos[v] : -1);
+        }
+        for (int g = 0; g < P.n_groups; ++g) {
+            const PlanGroup& PG = P.groups[g];
+            KStep& S = group_step[g];
+            S = KStep{};
+            const Layout& L = lay[PG.lift];
+            S.n_ops = PG.n_ops;
+            for (int t = 0; t < PG.n_ops; ++t) S.ops[t] = make_op(PG.ops[t], L, PG.var);
+            S.W_in = L.W;
+            S.k_share = shares[PG.var];
+            S.cell_shift = cell_shift[PG.var];
+            S.has_pred = 0;   // the predicate is applied where the variable is bound
+            S.group = g;
+            S.n_src = 0;
+            for (int t = 0; t < PG.n_ops; ++t)
+                if (PG.ops[t].kind == OP_V0) S.src_op[S.n_src++] = (int8_t)t;
+        }
+    }
+
+    struct StepBufs {
+        DevBuf<int32_t> seg;
+        DevBuf<uint8_t> iter;
+        DevBuf<uint32_t> m;
+        DevBuf<uint64_t> prefix;
+        Seg G;
+    };
+
+    void prep(const KStep& S, const int32_t* F, int64_t e0, int64_t n, StepBufs& B) {
+        B.seg = DevBuf<int32_t>(A, (size_t)(2 * S.n_ops) * (size_t)n);
+        B.iter = DevBuf<uint8_t>(A, (size_t)n);
+        B.m = DevBuf<uint32_t>(A, (size_t)n);
+        B.prefix = DevBuf<uint64_t>(A, (size_t)n + 1);
+        // index arrays by absolute entry e: shift the base pointers by -e0
+        B.G.stride = n;
+        B.G.seg = B.seg.p - e0;
+        B.G.iter = B.iter.p - e0;
+        B.G.m = B.m.p - e0;
+        k_prep<<<grid_for(n), kBlock, 0, s>>>(D, S, F, e0, n, B.G);
+        HC_HIP(hipGetLastError());
+        scan_exclusive(A, LoadU32{B.m.p}, B.prefix.p, n, s);
+    }
+
+    // Items [prefix[ea], prefix[eb]) of a prepared step into match words + their scan.
+    uint64_t match_words(const KStep& S, const int32_t* F, StepBufs& B, const uint64_t* prefix_abs, int64_t ea,
+                         int64_t eb, uint64_t ib, uint64_t ni, DevBuf<uint64_t>& words, DevBuf<uint64_t>& wpre) {
+        const int64_t nw = (int64_t)((ni + 63) / 64);
+        words = DevBuf<uint64_t>(A, (size_t)nw + 1);
+        wpre = DevBuf<uint64_t>(A, (size_t)nw + 1);
+        if (nw > 0) {
+            k_probe<M_BITMAP><<<grid_waves(nw), kBlock, 0, s>>>(D, S, F, B.G, prefix_abs, ea, eb, ib, ni, words.p,
+                                                                  nullptr);
+            HC_HIP(hipGetLastError());
+        }
+        scan_popc(A, words.p, wpre.p, nw, s);
+        return read_u64(wpre.p + nw);
+    }
+
+    void refresh_tmp_ptrs() {
+        for (int g = 0; g < kMaxGroups; ++g) {
+            D.tmp_val[g] = tmp_val[g].p;
+            for (int u = 0; u < kMaxOps; ++u) D.tmp_src[g][u] = tmp_src[g][u].p;
+        }
+    }
+
+    void run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n);
+};
+
+void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
+    if (n <= 0) return;
+    const int nv = P.n_vars;
+    // 1. lifted intersections whose lift level is i, chunked by the tmp pool
+    std::vector<int> groups;
+    for (int g = 0; g < P.n_groups; ++g)
+        if (P.groups[g].lift == i) groups.push_back(g);
+    std::vector<StepBufs> gb(groups.size());
+    for (size_t t = 0; t < groups.size(); ++t) prep(group_step[groups[t]], F, 0, n, gb[t]);
+    int64_t ea = 0;
+    while (ea < n) {
+        int64_t eb = n;
+        for (size_t t = 0; t < groups.size(); ++t) {
+            k_split<<<1, 1, 0, s>>>(gb[t].prefix.p, ea, eb, (uint64_t)tmp_cap, split.p);
+            HC_HIP(hipGetLastError());
+            int64_t e2 = 0;
+            HC_HIP(hipMemcpyAsync(&e2, split.p, sizeof(e2), hipMemcpyDeviceToHost, s));
+            HC_HIP(hipStreamSynchronize(s));
+            eb = std::min(eb, e2);
+        }
+        for (size_t t = 0; t < groups.size(); ++t) {
+            const int g = groups[t];
+            const KStep& S = group_step[g];
+            uint64_t pr[2];
+            HC_HIP(hipMemcpyAsync(&pr[0], gb[t].prefix.p + ea, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+            HC_HIP(hipMemcpyAsync(&pr[1], gb[t].prefix.p + eb, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+            HC_HIP(hipStreamSynchronize(s));
+            const uint64_t ni = pr[1] - pr[0];
+            HC_REQUIRE(ni <= (uint64_t)tmp_cap || eb == ea + 1, HC_ERR_DEVICE, "tmp chunking failed");
+            if (ni > (uint64_t)tmp_cap) {
+                // one entry larger than the pool: grow the pool
+                tmp_cap = (int64_t)ni;
+                for (int gg = 0; gg < P.n_groups; ++gg) {
+                    tmp_val[gg] = DevBuf<uint32_t>(A, (size_t)tmp_cap);
+                    for (int u = 0; u < kMaxOps; ++u) tmp_src[gg][u] = DevBuf<int32_t>(A, (size_t)tmp_cap);
+                }
+                refresh_tmp_ptrs();
+            }
+            DevBuf<uint64_t> words, wpre;
+            match_words(S, F, gb[t], gb[t].prefix.p, ea, eb, pr[0], ni, words, wpre);
+            const int64_t nw = (int64_t)((ni + 63) / 64);
+            if (nw > 0) {
+                MatOut mo{};
+                mo.tval = tmp_val[g].p;
+                for (int u = 0; u < S.n_src; ++u) mo.tsrc[u] = tmp_src[g][u].p;
+                k_materialize<MAT_TMP><<<grid_waves(nw), kBlock, 0, s>>>(D, S, F, gb[t].G, gb[t].prefix.p, ea, eb,
+                                                                          pr[0], ni, words.p, wpre.p, mo);
+                HC_HIP(hipGetLastError());
+            }
+            k_tmp_refs<<<grid_for(eb - ea), kBlock, 0, s>>>(Fmut, lay[i].W, lay[i].tmp_word[g], gb[t].prefix.p, ea,
+                                                            eb, pr[0], words.p, wpre.p, 0);
+            HC_HIP(hipGetLastError());
+        }
+        // 2. the level's own intersection over entries [ea, eb)
+        const KStep& S = level_step[i];
+        StepBufs B;
+        prep(S, F, ea, eb - ea, B);
+        const uint64_t total = read_u64(B.prefix.p + (eb - ea));
+        // B.prefix is indexed relative to ea: present it as absolute
+        const uint64_t* prefix_abs = B.prefix.p - ea;
+        if (i == nv - 1) {
+            if (!emit) {
+                if (total > 0) {
+                    const int64_t nw = (int64_t)((total + 63) / 64);
+                    if (ctx->profiling) HC_HIP(hipEventRecord(ev0, s));
+                    if (digest)
+                        k_probe<M_DIGEST><<<grid_waves(nw, 16384), kBlock, 0, s>>>(D, S, F, B.G, prefix_abs, ea, eb, 0,
+                                                                                    total, nullptr, acc.p);
+                    else
+                        k_probe<M_COUNT><<<grid_waves(nw, 16384), kBlock, 0, s>>>(D, S, F, B.G, prefix_abs, ea, eb, 0,
+                                                                                   total, nullptr, acc.p);
+                    HC_HIP(hipGetLastError());
+                    if (ctx->profiling) {
+                        HC_HIP(hipEventRecord(ev1, s));
+                        HC_HIP(hipEventSynchronize(ev1));
+                        float ms = 0;
+                        HC_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+                        leaf_ms += ms;
+                        ++leaf_launches;
+                    }
+                    leaf_items += total;
+                }
+            } else {
+                // emit in chunks of at most cap_entries elements
+                uint64_t ib = 0;
+                while (ib < total) {
+                    const uint64_t ni = std::min<uint64_t>(total - ib, (uint64_t)cap_entries);
+                    DevBuf<uint64_t> words, wpre;
+                    const uint64_t got = match_words(S, F, B, prefix_abs, ea, eb, ib, ni, words, wpre);
+                    if (got > 0 && out_count < out_cap) {
+                        MatOut mo{};
+                        mo.rows = out_rows;
+                        mo.row_base = out_count;
+                        mo.row_cap = out_cap;
+                        const int64_t nw = (int64_t)((ni + 63) / 64);
+                        k_materialize<MAT_EMIT><<<grid_waves(nw), kBlock, 0, s>>>(D, S, F, B.G, prefix_abs, ea, eb,
+                                                                                   ib, ni, words.p, wpre.p, mo);
+                        HC_HIP(hipGetLastError());
+                    }
+                    out_count += (int64_t)got;
+                    ib += ni;
+                }
+            }
+        } else {
+            // expand in chunks of entries whose elements fit the next frontier
+            int64_t ca = ea;
+            while (ca < eb) {
+                k_split<<<1, 1, 0, s>>>(prefix_abs, ca, eb, (uint64_t)cap_entries, split.p);
+                HC_HIP(hipGetLastError());
+                int64_t cb = 0;
+                HC_HIP(hipMemcpyAsync(&cb, split.p, sizeof(cb), hipMemcpyDeviceToHost, s));
+                uint64_t pr[2];
+                HC_HIP(hipStreamSynchronize(s));
+                HC_HIP(hipMemcpyAsync(&pr[0], prefix_abs + ca, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+                HC_HIP(hipMemcpyAsync(&pr[1], prefix_abs + cb, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+                HC_HIP(hipStreamSynchronize(s));
+                const uint64_t ni = pr[1] - pr[0];
+                DevBuf<uint64_t> words, wpre;
+                const uint64_t got = match_words(S, F, B, prefix_abs, ca, cb, pr[0], ni, words, wpre);
+                if (got > 0) {
+                    DevBuf<int32_t> Fn(A, (size_t)got * (size_t)lay[i + 1].W);
+                    MatOut mo{};
+                    mo.F = Fn.p;
+                    const int64_t nw = (int64_t)((ni + 63) / 64);
+                    k_materialize<MAT_EXPAND><<<grid_waves(nw), kBlock, 0, s>>>(D, S, F, B.G, prefix_abs, ca, cb,
+                                                                                 pr[0], ni, words.p, wpre.p, mo);
+                    HC_HIP(hipGetLastError());
+                    words.reset();
+                    wpre.reset();
+                    run_level(i + 1, Fn.p, Fn.p, (int64_t)got);
+                }
+                ca = cb;
+            }
+        }
+        ea = eb;
+    }
+}
+
+void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order, const int32_t* shares,
+              uint32_t flags, bool emit, uint64_t* count, uint64_t* digest, void* out, int64_t capacity,
+              int64_t* n_out) {
+    Runner R(ctx);
+    R.P = compile_plan(q, order, !(flags & HC_NO_REWRITE));
+    const Plan& P = R.P;
+    // CoCos: same key width and mixer, columns ordered by the variable order
+    int b = -1;
+    uint64_t seed = 0;
+    int dtype64 = 0;
+    for (int j = 0; j < P.n_atoms; ++j) {
+        const hc_coco* c = atoms[j];
+        HC_REQUIRE(c != nullptr, HC_ERR_INVALID, "atom CoCo handle is NULL");
+        HC_REQUIRE(c->arity == P.atom_arity[j], HC_ERR_INVALID, "CoCo arity does not match its atom");
+        if (b < 0) {
+            b = c->key_bits;
+            seed = c->mix_seed;
+            dtype64 = c->dtype == HC_I64;
+        }
+        HC_REQUIRE(c->key_bits == b && c->mix_seed == seed, HC_ERR_INVALID,
+                   "all CoCos of a join must share key_bits and mix_seed");
+        if (c->arity == 2) {
+            int off = 0;
+            for (int t = 0; t < j; ++t) off += q->atom_arity[t];
+            const int first_col = q->atom_vars[off] == P.atom_first[j] ? 0 : 1;
+            HC_REQUIRE(c->symmetric || c->col_order[0] == first_col, HC_ERR_INVALID,
+                       "CoCo column order does not follow the variable order for atom " + std::to_string(j));
+        }
+    }
+    int K = 0;
+    for (int v = 0; v < P.n_vars; ++v) {
+        R.shares[v] = shares ? shares[v] : 0;
+        HC_REQUIRE(R.shares[v] >= 0 && R.shares[v] <= b, HC_ERR_INVALID, "log2 share out of range [0, key_bits]");
+        K += R.shares[v];
+    }
+    HC_REQUIRE(K <= 24, HC_ERR_INVALID, "more than 2^24 cells");
+    R.K = K;
+    {
+        int acc_shift = 0;
+        for (int v = P.n_vars - 1; v >= 0; --v) {
+            R.cell_shift[v] = acc_shift;
+            acc_shift += R.shares[v];
+        }
+    }
+    R.D = KData{};
+    for (int j = 0; j < P.n_atoms; ++j) {
+        const hc_coco* c = atoms[j];
+        R.D.atoms[j].V0 = c->V[0];
+        R.D.atoms[j].O0 = c->arity == 2 ? c->O[0] : nullptr;
+        R.D.atoms[j].V1 = c->arity == 2 ? c->V[1] : nullptr;
+        R.D.atoms[j].l0 = c->level_len[0];
+    }
+    R.D.mix = make_mixer(b, seed);
+    R.D.b = b;
+    R.D.dtype64 = dtype64;
+    R.emit = emit;
+    R.digest = digest != nullptr;
+    R.out_rows = out;
+    R.out_cap = capacity;
+    R.cap_entries = (int64_t)1 << 26;
+    R.tmp_cap = (int64_t)1 << 26;
+    R.acc = DevBuf<unsigned long long>(R.A, 4);
+    R.split = DevBuf<int64_t>(R.A, 2);
+    HC_HIP(hipMemsetAsync(R.acc.p, 0, sizeof(unsigned long long) * 4, R.s));
+    R.setup_layouts();
+    R.setup_steps(q);
+    for (int g = 0; g < P.n_groups; ++g) {
+        R.tmp_val[g] = DevBuf<uint32_t>(R.A, (size_t)R.tmp_cap);
+        for (int u = 0; u < R.group_step[g].n_src; ++u) R.tmp_src[g][u] = DevBuf<int32_t>(R.A, (size_t)R.tmp_cap);
+    }
+    R.refresh_tmp_ptrs();
+    if (ctx->profiling) {
+        HC_HIP(hipEventCreate(&R.ev0));
+        HC_HIP(hipEventCreate(&R.ev1));
+    }
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (ctx->profiling) {
+        HC_HIP(hipEventCreate(&t0));
+        HC_HIP(hipEventCreate(&t1));
+        HC_HIP(hipEventRecord(t0, R.s));
+    }
+    // F_0: one entry per cell
+    const int64_t ncell = (int64_t)1 << K;
+    DevBuf<int32_t> F0(R.A, (size_t)ncell * (size_t)R.lay[0].W);
+    k_init_cells<<<grid_for(ncell), kBlock, 0, R.s>>>(F0.p, ncell, R.lay[0].W);
+    HC_HIP(hipGetLastError());
+    R.run_level(0, F0.p, F0.p, ncell);
+    unsigned long long a[3] = {0, 0, 0};
+    HC_HIP(hipMemcpyAsync(a, R.acc.p, sizeof(a), hipMemcpyDeviceToHost, R.s));
+    HC_HIP(hipStreamSynchronize(R.s));
+    if (emit) {
+        *count = (uint64_t)R.out_count;
+        if (n_out) *n_out = R.out_count;
+    } else {
+        *count = a[0];
+        if (digest) {
+            digest[0] = a[1];
+            digest[1] = a[2];
+        }
+    }
+    if (ctx->profiling) {
+        HC_HIP(hipEventRecord(t1, R.s));
+        HC_HIP(hipEventSynchronize(t1));
+        float ms = 0;
+        HC_HIP(hipEventElapsedTime(&ms, t0, t1));
+        ctx->timing.total_ms = ms;
+        ctx->timing.leaf_ms = R.leaf_ms;
+        ctx->timing.leaf_launches = R.leaf_launches;
+        ctx->timing.leaf_items = R.leaf_items;
+        (void)hipEventDestroy(t0);
+        (void)hipEventDestroy(t1);
+    } else {
+        ctx->timing = hc_timing{};
+        ctx->timing.leaf_items = R.leaf_items;
+    }
+}
+
+}  // namespace hc

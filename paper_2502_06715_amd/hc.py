@@ -1,0 +1,314 @@
+"""Python binding of libhc.so (the gfx950 Generic Join library).
+
+Argument marshalling only: every step of the join runs in the library's HIP
+kernels.  PyTorch supplies device memory (its caching allocator, through the
+library's allocator callbacks) and the stream the library orders its work on.
+The names follow the C-ABI in include/hc.h.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhc.so")
+
+HC_OK, HC_ERR_INVALID, HC_ERR_OOM, HC_ERR_OVERFLOW, HC_ERR_DEVICE, HC_ERR_UNSUPPORTED = range(6)
+HC_I32, HC_I64 = 0, 1
+HC_BUILD_SYMMETRIC = 0x1
+HC_NO_REWRITE = 0x1
+HC_FORCE_MERGE = 0x2
+HC_FORCE_GALLOP = 0x4
+HC_KEEP_ORDER = 0x8
+
+_STATUS = {1: "HC_ERR_INVALID", 2: "HC_ERR_OOM", 3: "HC_ERR_OVERFLOW", 4: "HC_ERR_DEVICE", 5: "HC_ERR_UNSUPPORTED"}
+
+
+class HCError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_STATUS.get(status, str(status)), msg))
+        self.status = status
+
+
+class _Query(ctypes.Structure):
+    _fields_ = [("n_vars", ctypes.c_int32), ("n_atoms", ctypes.c_int32),
+                ("atom_arity", ctypes.c_void_p), ("atom_vars", ctypes.c_void_p),
+                ("var_lo", ctypes.c_void_p), ("var_hi", ctypes.c_void_p)]
+
+
+class CocoInfo(ctypes.Structure):
+    _fields_ = [("n_input", ctypes.c_int64), ("n_unique", ctypes.c_int64), ("arity", ctypes.c_int32),
+                ("key_bits", ctypes.c_int32), ("mix_seed", ctypes.c_uint64), ("col_order", ctypes.c_int32 * 4),
+                ("level_len", ctypes.c_int64 * 4), ("max_children", ctypes.c_int64 * 4),
+                ("distinct", ctypes.c_int64 * 4), ("symmetric", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("bytes", ctypes.c_int64)]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("leaf_ms", ctypes.c_double), ("leaf_launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("leaf_items", ctypes.c_uint64)]
+
+
+_ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+# exported symbols and their signatures
+P, I32, I64, U32, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+SIGNATURES = {
+    "hc_ctx_create": (ctypes.c_int, [ctypes.c_int, P, _ALLOC, _FREE, P, P]),
+    "hc_ctx_destroy": (None, [P]),
+    "hc_last_error": (ctypes.c_char_p, [P]),
+    "hc_build_coco": (ctypes.c_int, [P, P, I64, I32, ctypes.c_int, P, I32, U64, U32, P]),
+    "hc_coco_free": (None, [P]),
+    "hc_coco_get_info": (ctypes.c_int, [P, P]),
+    "hc_coco_copy_level": (ctypes.c_int, [P, P, I32, P, P]),
+    "hc_partition_sizes": (ctypes.c_int, [P, P, P, P, P]),
+    "hc_compute_shares": (ctypes.c_int, [P, P, P, I32, U32, P, P]),
+    "hc_compute_shares_from_info": (ctypes.c_int, [P, P, I32, U32, P, P]),
+    "hc_join_count": (ctypes.c_int, [P, P, P, P, P, U32, P, P]),
+    "hc_join_emit": (ctypes.c_int, [P, P, P, P, P, U32, P, I64, P]),
+    "hc_plan_describe": (ctypes.c_int, [P, P, U32, P, ctypes.c_size_t]),
+    "hc_ctx_set_profiling": (ctypes.c_int, [P, ctypes.c_int]),
+    "hc_ctx_get_timing": (ctypes.c_int, [P, P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libhc.so.  Raises if it has not been built: there is no fallback path."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libhc.so is not built; run `python -m paper_2502_06715_amd.build_lib`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+@dataclass
+class Query:
+    """Full conjunctive query: variables 0..n_vars-1 (head order), atoms as variable tuples."""
+    n_vars: int
+    atoms: Sequence[Sequence[int]]
+    var_lo: Optional[Sequence[int]] = None
+    var_hi: Optional[Sequence[int]] = None
+    _keep: list = field(default_factory=list, repr=False)
+
+    def c(self) -> _Query:
+        ar = np.array([len(a) for a in self.atoms], dtype=np.int32)
+        av = np.array([v for a in self.atoms for v in a], dtype=np.int32)
+        q = _Query(self.n_vars, len(self.atoms), ar.ctypes.data, av.ctypes.data, None, None)
+        keep = [ar, av]
+        if self.var_lo is not None:
+            lo = np.array(self.var_lo, dtype=np.int64)
+            hi = np.array(self.var_hi, dtype=np.int64)
+            q.var_lo, q.var_hi = lo.ctypes.data, hi.ctypes.data
+            keep += [lo, hi]
+        self._keep = keep
+        return q
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+class Context:
+    """hc_ctx on a torch device and stream, allocating through torch's caching allocator."""
+
+    def __init__(self, device: int = 0, stream=None, use_torch_allocator: bool = True):
+        import torch
+        self._torch = torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        sptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        self._sptr = sptr
+        if use_torch_allocator:
+            def _alloc(nbytes, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), device, sptr)
+                except Exception:
+                    return None
+
+            def _free(ptr, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._cb = (_ALLOC(_alloc), _FREE(_free))
+        else:
+            self._cb = (_ALLOC(), _FREE())
+        h = ctypes.c_void_p()
+        st = lib().hc_ctx_create(device, ctypes.c_void_p(sptr), self._cb[0], self._cb[1], None, ctypes.byref(h))
+        if st != HC_OK:
+            raise HCError(st, "hc_ctx_create failed")
+        self.h = h
+
+    def check(self, st: int):
+        if st != HC_OK:
+            raise HCError(st, lib().hc_last_error(self.h).decode())
+
+    def set_profiling(self, on: bool):
+        lib().hc_ctx_set_profiling(self.h, 1 if on else 0)
+
+    def timing(self) -> Timing:
+        t = Timing()
+        lib().hc_ctx_get_timing(self.h, ctypes.byref(t))
+        return t
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hc_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Coco:
+    def __init__(self, ctx: Context, handle):
+        self.ctx = ctx
+        self.h = handle
+        info = CocoInfo()
+        lib().hc_coco_get_info(self.h, ctypes.byref(info))
+        self.info = info
+
+    def free(self):
+        if self.h:
+            lib().hc_coco_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build_coco(ctx: Context, tuples, col_order=None, key_bits: int = 0, seed: int = 0,
+               symmetric: bool = False) -> Coco:
+    """hc_build_coco on a CUDA tensor [n, arity] of int32/int64."""
+    torch = ctx._torch
+    t = tuples
+    assert t.is_cuda and t.dim() == 2, "tuples must be a 2-D CUDA tensor"
+    t = t.contiguous()
+    dt = {torch.int32: HC_I32, torch.int64: HC_I64}[t.dtype]
+    arity = t.shape[1]
+    co = _i32(list(range(arity)) if col_order is None else col_order)
+    h = ctypes.c_void_p()
+    st = lib().hc_build_coco(ctx.h, ctypes.c_void_p(t.data_ptr()), t.shape[0], arity, dt, co.ctypes.data,
+                             key_bits, seed & 0xFFFFFFFFFFFFFFFF, HC_BUILD_SYMMETRIC if symmetric else 0,
+                             ctypes.byref(h))
+    ctx.check(st)
+    return Coco(ctx, h)
+
+
+def coco_level(ctx: Context, coco: Coco, level: int):
+    n = coco.info.level_len[level]
+    vals = np.zeros(max(n, 1), dtype=np.uint32)
+    offs = np.zeros(n + 1, dtype=np.int32) if level + 1 < coco.info.arity else None
+    ctx.check(lib().hc_coco_copy_level(ctx.h, coco.h, level, vals.ctypes.data,
+                                       offs.ctypes.data if offs is not None else None))
+    return vals[:n], offs
+
+
+def partition_sizes(ctx: Context, coco: Coco, log2_shares):
+    ls = _i32(log2_shares)
+    total = 1 << int(ls.sum())
+    B = np.zeros(total, dtype=np.int64)
+    Bp = np.zeros(total, dtype=np.int64)
+    ctx.check(lib().hc_partition_sizes(ctx.h, coco.h, ls.ctypes.data, B.ctypes.data, Bp.ctypes.data))
+    return B, Bp
+
+
+def _handles(cocos):
+    return (ctypes.c_void_p * len(cocos))(*[c.h for c in cocos])
+
+
+def compute_shares(ctx: Context, q: Query, cocos, log2_total_P: int, flags: int = 0, order=None):
+    order_a = _i32(order if order is not None else list(range(q.n_vars)))
+    shares = np.zeros(q.n_vars, dtype=np.int32)
+    if order is not None:
+        flags |= HC_KEEP_ORDER
+    qc = q.c()
+    ctx.check(lib().hc_compute_shares(ctx.h, ctypes.byref(qc), _handles(cocos), log2_total_P, flags,
+                                      order_a.ctypes.data, shares.ctypes.data))
+    return order_a.tolist(), shares.tolist()
+
+
+def compute_shares_from_info(q: Query, infos, log2_total_P: int, flags: int = 0, order=None):
+    """Host-only share decision from CocoInfo structs (no GPU needed)."""
+    order_a = _i32(order if order is not None else list(range(q.n_vars)))
+    shares = np.zeros(q.n_vars, dtype=np.int32)
+    if order is not None:
+        flags |= HC_KEEP_ORDER
+    arr = (CocoInfo * len(infos))(*infos)
+    qc = q.c()
+    st = lib().hc_compute_shares_from_info(ctypes.byref(qc), arr, log2_total_P, flags, order_a.ctypes.data,
+                                           shares.ctypes.data)
+    if st != HC_OK:
+        raise HCError(st, "hc_compute_shares_from_info failed")
+    return order_a.tolist(), shares.tolist()
+
+
+def join_count(ctx: Context, q: Query, cocos, order, log2_shares=None, flags: int = 0, digest: bool = False):
+    order_a = _i32(order)
+    sh = _i32(log2_shares) if log2_shares is not None else None
+    cnt = ctypes.c_uint64(0)
+    dg = (ctypes.c_uint64 * 2)()
+    qc = q.c()
+    ctx.check(lib().hc_join_count(ctx.h, ctypes.byref(qc), _handles(cocos), order_a.ctypes.data,
+                                  sh.ctypes.data if sh is not None else None, flags, ctypes.byref(cnt),
+                                  dg if digest else None))
+    if digest:
+        return int(cnt.value), (int(dg[0]), int(dg[1]))
+    return int(cnt.value)
+
+
+def join_emit(ctx: Context, q: Query, cocos, order, log2_shares=None, flags: int = 0, capacity: int = None,
+              out=None):
+    """Returns (rows tensor [n_out, n_vars] view, n_out).  Raises HCError(HC_ERR_OVERFLOW)
+    (with .n_out set) when the result exceeds the capacity."""
+    torch = ctx._torch
+    dt = torch.int64 if cocos[0].info.dtype == HC_I64 else torch.int32
+    if out is None:
+        cap = capacity if capacity is not None else 0
+        out = torch.empty((max(cap, 1), q.n_vars), dtype=dt, device="cuda:%d" % ctx.device)
+    else:
+        cap = out.shape[0] if capacity is None else capacity
+    order_a = _i32(order)
+    sh = _i32(log2_shares) if log2_shares is not None else None
+    n_out = ctypes.c_int64(0)
+    qc = q.c()
+    st = lib().hc_join_emit(ctx.h, ctypes.byref(qc), _handles(cocos), order_a.ctypes.data,
+                            sh.ctypes.data if sh is not None else None, flags, ctypes.c_void_p(out.data_ptr()),
+                            cap, ctypes.byref(n_out))
+    if st == HC_ERR_OVERFLOW:
+        e = HCError(st, lib().hc_last_error(ctx.h).decode())
+        e.n_out = int(n_out.value)
+        raise e
+    ctx.check(st)
+    return out[: n_out.value], int(n_out.value)
+
+
+def plan_describe(q: Query, order, flags: int = 0) -> dict:
+    buf = ctypes.create_string_buffer(1 << 16)
+    order_a = _i32(order)
+    qc = q.c()
+    st = lib().hc_plan_describe(ctypes.byref(qc), order_a.ctypes.data, flags, buf, len(buf))
+    if st != HC_OK:
+        raise HCError(st, "hc_plan_describe failed")
+    return json.loads(buf.value.decode())
