@@ -1,0 +1,202 @@
+"""Benchmark of the Generic Join hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2] [--no-cpu-baseline]
+
+A step is one pass of the whole hot path over the workload, with the input
+tuples already resident in HBM: CoCo build (key mix, radix sort, levels),
+share/order decision, and the HyperCube-partitioned Generic Join count.
+Default workload: triangle query Q(a,b,c) = R(a,b), S(b,c), T(a,c) with
+R = S = T the symmetric edge set of an R-MAT graph (scale 20, a,b,c,d =
+0.57, 0.19, 0.19, 0.05, 2^24 undirected edges -> 2^25 int32 tuples), shares
+over all three variables from the cost model with P = 2^12 cells.
+
+Prints one JSON line: output tuples/s (the count divided by the step time),
+the roofline of the dominant kernel (the deepest Generic Join level, timed
+with HIP events on the library's stream), and the CPU oracle timed on a
+bounded sample of the same workload on this host's cores.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _source_hash():
+    h = hashlib.sha256()
+    for f in ["join.hip", "prim_dev.h", "hc_internal.h"]:
+        h.update(open(os.path.join(ROOT, "paper_2502_06715_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _workload(cfg):
+    from paper_2502_06715_amd import inputs
+    spec = inputs.CONFIGS[cfg]
+    if spec["kind"] == "rmat":
+        desc = ("triangle query, R=S=T symmetric edge set of R-MAT scale %d (a,b,c,d = 0.57,0.19,0.19,0.05), "
+                "2^%d undirected edges (2^%d int32 tuples), HyperCube shares over all 3 variables, count"
+                % (spec["scale"], spec["m"].bit_length() - 1, spec["m"].bit_length()))
+        return desc, spec["scale"], "triangle"
+    if spec["kind"] == "er":
+        desc = ("triangle query, R=S=T symmetric edge set of an Erdos-Renyi graph, 2^%d vertices, 2^%d "
+                "undirected edges, count" % (spec["n"].bit_length() - 1, spec["m"].bit_length() - 1))
+        return desc, spec["n"].bit_length() - 1, "triangle"
+    desc = ("4-clique query over 6 atoms on one Chung-Lu graph (beta 2.1), 2^%d vertices, 2^%d undirected "
+            "edges, count" % (spec["n"].bit_length() - 1, spec["m"].bit_length() - 1))
+    return desc, spec["n"].bit_length() - 1, "clique4"
+
+
+def cpu_baseline(E, n_vars, atoms, full_count, budget_s=15.0):
+    """The oracle on this host: sort once, then Generic Join over randomly chosen
+    blocks of first-variable ids until budget_s of join time; the full-job time is
+    estimated as sort + join_time * full_count / sample_count."""
+    from oracle import oracle
+    try:
+        threads = min(16, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        threads = min(16, os.cpu_count() or 1)
+    nid = int(E.max()) + 1
+    nblk = 1024
+    width = (nid + nblk - 1) // nblk
+    perm = np.random.default_rng(0x4843).permutation(nblk)
+    ranges = [(int(b) * width, int(b + 1) * width) for b in perm]
+    sort_s, done = oracle.gj_sample(n_vars, atoms, [E] * len(atoms), ranges, budget_s, threads=threads)
+    cnt = sum(d[2] for d in done)
+    js = sum(d[3] for d in done)
+    frac = cnt / full_count if full_count else 0.0
+    est = sort_s + (js / frac if frac > 0 else float("inf"))
+    return {
+        "value": full_count / est if est > 0 else 0.0,
+        "unit": "tuples/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": ("oracle sort+dedup of all %d atoms (%.1f s) then Generic Join over %d of %d random "
+                   "first-variable id blocks (%.1f s, %.2f%% of the output); full-job time extrapolated "
+                   "as sort + join/fraction = %.1f s" % (len(atoms), sort_s, len(done), nblk, js,
+                                                         100 * frac, est)),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--log2-cells", type=int, default=12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2502_06715_amd import hc, inputs
+
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "workloads.json")))
+    desc, b, qname = _workload(args.config)
+    n_vars, atoms = inputs.QUERIES[qname]
+    t0 = time.time()
+    E = inputs.config_graph(args.config)
+    print("# generated workload %d: %d tuples in %.1f s" % (args.config, E.shape[0], time.time() - t0),
+          file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    E_dev = torch.from_numpy(E).to(dev)
+    ctx = hc.Context(0)
+    ctx.set_profiling(True)
+    q = hc.Query(n_vars, atoms)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        coco = hc.build_coco(ctx, E_dev, [0, 1], key_bits=b)
+        ev[1].record(stream)
+        order, shares = hc.compute_shares(ctx, q, [coco] * len(atoms), args.log2_cells)
+        ev[2].record(stream)
+        cnt = hc.join_count(ctx, q, [coco] * len(atoms), order, shares)
+        ev[3].record(stream)
+        ev[3].synchronize()
+        t = ctx.timing()
+        coco.free()
+        return dict(count=cnt, order=order, shares=shares, build_ms=ev[0].elapsed_time(ev[1]),
+                    shares_ms=ev[1].elapsed_time(ev[2]), join_ms=ev[2].elapsed_time(ev[3]),
+                    leaf_ms=t.leaf_ms, leaf_launches=t.leaf_launches, leaf_items=t.leaf_items)
+
+    for _ in range(args.warmup):
+        r = step()
+        print("# warmup step: %s" % json.dumps(r), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    res = []
+    for _ in range(args.steps):
+        res.append(step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    for r in res:
+        print("# step: %s" % json.dumps(r), file=sys.stderr, flush=True)
+    ms_per_step = 1000.0 * elapsed / args.steps
+    count = res[-1]["count"]
+    expect = gold[str(args.config)]["count"]
+    if any(r["count"] != expect for r in res):
+        print("count mismatch: %s vs oracle %d" % ([r["count"] for r in res], expect), file=sys.stderr)
+        sys.exit(1)
+
+    # roofline of the dominant kernel: the deepest level of Generic Join
+    leaf_ms = sum(r["leaf_ms"] for r in res)
+    launches = sum(r["leaf_launches"] for r in res)
+    wk = gold[str(args.config)].get("work_gallop_per_level")
+    roof = None
+    if wk and launches:
+        alg_bytes_step = 4.0 * wk[-1] + 8.0          # elements touched x 4 B + the count
+        per_launch = alg_bytes_step * args.steps / launches
+        avg_ms = leaf_ms / launches
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        traffic = None
+        tf = os.path.join(ROOT, "profiles", "leaf_traffic_config%d.json" % args.config)
+        if os.path.exists(tf):
+            t = json.load(open(tf))
+            if t.get("source_hash") == _source_hash():
+                traffic = t.get("bytes_per_launch")
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_probe<M_COUNT> (deepest level)", "avg_launch_ms": round(avg_ms, 3),
+                "launches_per_step": launches / args.steps,
+                "algorithmic_bytes_per_launch": per_launch}
+    out = {
+        "metric": "output tuples/s on triangle query" if qname == "triangle" else "output tuples/s",
+        "value": count / (ms_per_step / 1000.0),
+        "unit": "tuples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": desc, "tuples": int(E.shape[0]), "count": count, "order": res[-1]["order"],
+                   "log2_shares": res[-1]["shares"], "log2_cells": args.log2_cells},
+        "phases_ms": {k: round(float(np.mean([r[k] for r in res])), 3)
+                      for k in ["build_ms", "shares_ms", "join_ms", "leaf_ms"]},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(E, n_vars, atoms, expect, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

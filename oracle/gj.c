@@ -67,7 +67,8 @@ typedef struct {
     int64_t lo[OQ_MAX_ATOMS], hi[OQ_MAX_ATOMS];
     int depth[OQ_MAX_ATOMS];
     int64_t val[OQ_MAX_VARS];
-    uint64_t count, dsum, dxor, work;
+    uint64_t count, dsum, dxor;
+    uint64_t work[OQ_MAX_VARS];
     int64_t* out_pos;              /* shared cursor */
 } oq_frame;
 
@@ -190,7 +191,7 @@ static void gj_level(const oq_state* s, oq_frame* f, int i) {
             uint64_t g = (uint64_t)m * ceil_log2_ratio(z, m);
             w += (uint64_t)z < g ? (uint64_t)z : g;
         }
-        f->work += w;
+        f->work[i] += w;
     }
     int ab = s->ops[i][best];
     const oq_rel* rb = &s->rel[ab];
@@ -225,39 +226,40 @@ static void gj_level(const oq_state* s, oq_frame* f, int i) {
  *   var_lo/var_hi: nullable, per-variable range predicate lo <= x < hi
  *   out/out_cap: nullable output buffer, head-order rows, arbitrary row order
  *   digest: nullable uint64[2] (sum, xor)
- *   work: nullable uint64[1] galloping work counter
+ *   work: nullable uint64[n_vars] galloping work counter per level
  * Returns the count, or -1 on an invalid query.
  */
-int64_t oracle_gj(int n_vars, int n_atoms, const int* arity, const int* atom_vars,
-                  const int64_t* const* rel, const int64_t* rows, const int* order,
-                  const int64_t* var_lo, const int64_t* var_hi,
-                  int64_t* out, int64_t out_cap, uint64_t* digest, uint64_t* work,
-                  int nthreads) {
+static void free_state(oq_state* s) {
+    for (int j = 0; j < OQ_MAX_ATOMS; ++j) { free(s->rel[j].t); s->rel[j].t = NULL; }
+}
+
+/* Sort and deduplicate every atom in variable-order column order; returns 0 or -1. */
+static int prepare(oq_state* s, int n_vars, int n_atoms, const int* arity, const int* atom_vars,
+                   const int64_t* const* rel, const int64_t* rows, const int* order) {
     if (n_vars < 1 || n_vars > OQ_MAX_VARS || n_atoms < 1 || n_atoms > OQ_MAX_ATOMS) return -1;
-    oq_state s;
-    memset(&s, 0, sizeof(s));
-    s.n_vars = n_vars; s.n_atoms = n_atoms; s.order = order;
+    memset(s, 0, sizeof(*s));
+    s->n_vars = n_vars; s->n_atoms = n_atoms; s->order = order;
     int seen[OQ_MAX_VARS] = {0};
     for (int i = 0; i < n_vars; ++i) {
         if (order[i] < 0 || order[i] >= n_vars || seen[order[i]]) return -1;
-        seen[order[i]] = 1; s.pos[order[i]] = i;
+        seen[order[i]] = 1; s->pos[order[i]] = i;
     }
     int covered[OQ_MAX_VARS] = {0};
     const int* av = atom_vars;
     for (int j = 0; j < n_atoms; ++j) {
         int k = arity[j];
-        if (k < 1 || k > OQ_MAX_ARITY) return -1;
-        oq_rel* r = &s.rel[j];
+        if (k < 1 || k > OQ_MAX_ARITY) { free_state(s); return -1; }
+        oq_rel* r = &s->rel[j];
         r->k = k;
         /* columns sorted by the level of their variable */
         int perm[OQ_MAX_ARITY];
         for (int c = 0; c < k; ++c) {
-            if (av[c] < 0 || av[c] >= n_vars) return -1;
-            for (int c2 = 0; c2 < c; ++c2) if (av[c2] == av[c]) return -1;
+            if (av[c] < 0 || av[c] >= n_vars) { free_state(s); return -1; }
+            for (int c2 = 0; c2 < c; ++c2) if (av[c2] == av[c]) { free_state(s); return -1; }
             perm[c] = c; covered[av[c]] = 1;
         }
         for (int x = 1; x < k; ++x)
-            for (int y = x; y > 0 && s.pos[av[perm[y]]] < s.pos[av[perm[y - 1]]]; --y) {
+            for (int y = x; y > 0 && s->pos[av[perm[y]]] < s->pos[av[perm[y - 1]]]; --y) {
                 int tmp = perm[y]; perm[y] = perm[y - 1]; perm[y - 1] = tmp;
             }
         for (int c = 0; c < k; ++c) r->var_of_col[c] = av[perm[c]];
@@ -279,94 +281,185 @@ int64_t oracle_gj(int n_vars, int n_atoms, const int* arity, const int* atom_var
             if (row == 0 || r->t[row * k] != r->t[(row - 1) * k]) r->distinct0++;
         av += k;
     }
-    for (int v = 0; v < n_vars; ++v) if (!covered[v]) goto fail;
+    for (int v = 0; v < n_vars; ++v) if (!covered[v]) { free_state(s); return -1; }
     for (int i = 0; i < n_vars; ++i) {
-        s.n_ops[i] = 0;
+        s->n_ops[i] = 0;
         for (int j = 0; j < n_atoms; ++j)
-            for (int c = 0; c < s.rel[j].k; ++c)
-                if (s.rel[j].var_of_col[c] == order[i]) s.ops[i][s.n_ops[i]++] = j;
+            for (int c = 0; c < s->rel[j].k; ++c)
+                if (s->rel[j].var_of_col[c] == order[i]) s->ops[i][s->n_ops[i]++] = j;
     }
+    return 0;
+}
+
+typedef struct {
+    int best;                /* operand of level 0 whose runs are split across threads */
+    int64_t nruns;
+    int64_t* starts;         /* run start rows, nruns + 1 entries */
+} oq_level0;
+
+static void level0_runs(const oq_state* s, oq_level0* L) {
+    int na = s->n_ops[0];
+    L->best = 0;
+    for (int q = 1; q < na; ++q)
+        if (s->rel[s->ops[0][q]].rows < s->rel[s->ops[0][L->best]].rows) L->best = q;
+    const oq_rel* rb = &s->rel[s->ops[0][L->best]];
+    L->nruns = rb->distinct0;
+    L->starts = (int64_t*)malloc(sizeof(int64_t) * (size_t)(L->nruns + 1));
+    int64_t q0 = 0;
+    for (int64_t row = 0; row < rb->rows; ++row)
+        if (row == 0 || rb->t[row * rb->k] != rb->t[(row - 1) * rb->k]) L->starts[q0++] = row;
+    L->starts[L->nruns] = rb->rows;
+}
+
+/* Generic Join over the level-0 runs [run_lo, run_hi), OpenMP over runs; adds into acc. */
+static void run_runs(const oq_state* s, const oq_level0* L, int64_t run_lo, int64_t run_hi,
+                     uint64_t* tc, uint64_t* ts, uint64_t* tx, uint64_t* tw, int64_t* out_pos) {
+    oq_frame base;
+    memset(&base, 0, sizeof(base));
+    for (int j = 0; j < s->n_atoms; ++j) { base.lo[j] = 0; base.hi[j] = s->rel[j].rows; base.depth[j] = 0; }
+    const int na = s->n_ops[0];
+    const int best = L->best;
+    const oq_rel* rb = &s->rel[s->ops[0][best]];
+#pragma omp parallel
+    {
+        oq_frame f = base;
+        f.out_pos = out_pos;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t run = run_lo; run < run_hi; ++run) {
+            int64_t r = L->starts[run], r1 = L->starts[run + 1];
+            int64_t v = rb->t[r * rb->k];
+            int var = s->order[0];
+            if (s->lo && (v < s->lo[var] || v >= s->hi[var])) continue;
+            int64_t nlo[OQ_MAX_ATOMS], nhi[OQ_MAX_ATOMS];
+            int ok = 1;
+            for (int q = 0; q < na && ok; ++q) {
+                int a = s->ops[0][q];
+                if (q == best) { nlo[q] = r; nhi[q] = r1; continue; }
+                const oq_rel* ra = &s->rel[a];
+                int64_t e0 = lower_row(ra, 0, 0, ra->rows, v);
+                int64_t e1 = upper_row(ra, 0, e0, ra->rows, v);
+                if (e0 == e1) ok = 0;
+                nlo[q] = e0; nhi[q] = e1;
+            }
+            if (ok) bind_and_recurse(s, &f, 0, v, nlo, nhi);
+        }
+#pragma omp critical
+        {
+            *tc += f.count; *ts += f.dsum; *tx ^= f.dxor;
+            for (int q = 0; q < OQ_MAX_VARS; ++q) tw[q] += f.work[q];
+        }
+    }
+}
+
+/*
+ * Run Generic Join.
+ *   n_vars, n_atoms, arity[n_atoms], atom_vars[sum arity]: the query (var ids are head order)
+ *   rel[j]: row-major int64 tuples of atom j (rows[j] rows), duplicates allowed
+ *   order[n_vars]: variable order (a permutation of 0..n_vars-1)
+ *   var_lo/var_hi: nullable, per-variable range predicate lo <= x < hi
+ *   out/out_cap: nullable output buffer, head-order rows, arbitrary row order
+ *   digest: nullable uint64[2] (sum, xor)
+ *   work: nullable uint64[n_vars] galloping work counter per level
+ * Returns the count, or -1 on an invalid query.
+ */
+int64_t oracle_gj(int n_vars, int n_atoms, const int* arity, const int* atom_vars,
+                  const int64_t* const* rel, const int64_t* rows, const int* order,
+                  const int64_t* var_lo, const int64_t* var_hi,
+                  int64_t* out, int64_t out_cap, uint64_t* digest, uint64_t* work,
+                  int nthreads) {
+    oq_state s;
+    if (prepare(&s, n_vars, n_atoms, arity, atom_vars, rel, rows, order) != 0) return -1;
     s.lo = var_lo; s.hi = var_hi;
     s.out = out; s.out_cap = out_cap;
     s.want_digest = digest != NULL;
     s.want_work = work != NULL;
-
-    {
-        /* Level 0 is split across threads by the runs of the smallest operand. */
-        oq_frame base;
-        memset(&base, 0, sizeof(base));
-        int64_t out_pos = 0;
-        for (int j = 0; j < n_atoms; ++j) { base.lo[j] = 0; base.hi[j] = s.rel[j].rows; base.depth[j] = 0; }
+    oq_level0 L;
+    level0_runs(&s, &L);
+    uint64_t tc = 0, ts = 0, tx = 0, tw[OQ_MAX_VARS] = {0};
+    if (s.want_work) {
+        /* level-0 intersection work, counted once */
+        oq_frame wf;
+        memset(&wf, 0, sizeof(wf));
+        for (int j = 0; j < n_atoms; ++j) { wf.lo[j] = 0; wf.hi[j] = s.rel[j].rows; }
         int na = s.n_ops[0];
-        int best = 0;
-        for (int q = 1; q < na; ++q)
-            if (s.rel[s.ops[0][q]].rows < s.rel[s.ops[0][best]].rows) best = q;
-        int ab = s.ops[0][best];
-        const oq_rel* rb = &s.rel[ab];
-        int64_t nruns = rb->distinct0;
-        int64_t* starts = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nruns + 1));
-        int64_t q0 = 0;
-        for (int64_t row = 0; row < rb->rows; ++row)
-            if (row == 0 || rb->t[row * rb->k] != rb->t[(row - 1) * rb->k]) starts[q0++] = row;
-        starts[nruns] = rb->rows;
-        uint64_t tc = 0, ts = 0, tx = 0, tw = 0;
-        if (s.want_work) {
-            /* level-0 intersection work, counted once */
-            oq_frame wf = base;
-            int64_t m = -1;
-            for (int q = 0; q < na; ++q) {
-                int64_t z = operand_size(&s, s.ops[0][q], &wf);
-                if (m < 0 || z < m) m = z;
-            }
-            uint64_t w0 = (uint64_t)m;
-            int skipped = 0;
-            for (int q = 0; q < na; ++q) {
-                int64_t z = operand_size(&s, s.ops[0][q], &wf);
-                if (z == m && !skipped) { skipped = 1; continue; }
-                if (m == 0) continue;
-                uint64_t g = (uint64_t)m * ceil_log2_ratio(z, m);
-                w0 += (uint64_t)z < g ? (uint64_t)z : g;
-            }
-            tw += w0;
+        int64_t m = -1;
+        for (int q = 0; q < na; ++q) {
+            int64_t z = operand_size(&s, s.ops[0][q], &wf);
+            if (m < 0 || z < m) m = z;
         }
-#ifdef _OPENMP
-        if (nthreads > 0) omp_set_num_threads(nthreads);
-#endif
-#pragma omp parallel
-        {
-            oq_frame f = base;
-            f.out_pos = &out_pos;
-#pragma omp for schedule(dynamic, 16)
-            for (int64_t run = 0; run < nruns; ++run) {
-                int64_t r = starts[run], r1 = starts[run + 1];
-                int64_t v = rb->t[r * rb->k];
-                int var = order[0];
-                if (s.lo && (v < s.lo[var] || v >= s.hi[var])) continue;
-                int64_t nlo[OQ_MAX_ATOMS], nhi[OQ_MAX_ATOMS];
-                int ok = 1;
-                for (int q = 0; q < na && ok; ++q) {
-                    int a = s.ops[0][q];
-                    if (q == best) { nlo[q] = r; nhi[q] = r1; continue; }
-                    const oq_rel* ra = &s.rel[a];
-                    int64_t e0 = lower_row(ra, 0, 0, ra->rows, v);
-                    int64_t e1 = upper_row(ra, 0, e0, ra->rows, v);
-                    if (e0 == e1) ok = 0;
-                    nlo[q] = e0; nhi[q] = e1;
-                }
-                if (ok) bind_and_recurse(&s, &f, 0, v, nlo, nhi);
-            }
-#pragma omp critical
-            { tc += f.count; ts += f.dsum; tx ^= f.dxor; tw += f.work; }
+        uint64_t w0 = (uint64_t)m;
+        int skipped = 0;
+        for (int q = 0; q < na; ++q) {
+            int64_t z = operand_size(&s, s.ops[0][q], &wf);
+            if (z == m && !skipped) { skipped = 1; continue; }
+            if (m == 0) continue;
+            uint64_t g = (uint64_t)m * ceil_log2_ratio(z, m);
+            w0 += (uint64_t)z < g ? (uint64_t)z : g;
         }
-        free(starts);
-        for (int j = 0; j < n_atoms; ++j) free(s.rel[j].t);
-        if (digest) { digest[0] = ts; digest[1] = tx; }
-        if (work) work[0] = tw;
-        return (int64_t)tc;
+        tw[0] += w0;
     }
-fail:
-    for (int j = 0; j < n_atoms; ++j) free(s.rel[j].t);
-    return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    int64_t out_pos = 0;
+    run_runs(&s, &L, 0, L.nruns, &tc, &ts, &tx, tw, &out_pos);
+    free(L.starts);
+    free_state(&s);
+    if (digest) { digest[0] = ts; digest[1] = tx; }
+    if (work) for (int q = 0; q < n_vars; ++q) work[q] = tw[q];
+    return (int64_t)tc;
+}
+
+#ifdef _OPENMP
+static double now_s(void) { return omp_get_wtime(); }
+#else
+#include <time.h>
+static double now_s(void) {
+    struct timespec t;
+    clock_gettime(CLOCK_MONOTONIC, &t);
+    return t.tv_sec + 1e-9 * t.tv_nsec;
+}
+#endif
+
+/*
+ * Timed sample for the CPU baseline: sort once, then run Generic Join on the
+ * level-0 value ranges [lo[k], hi[k]) in the given order until the join time
+ * reaches budget_s.  Writes per-range counts and seconds; returns the number of
+ * ranges run (or -1).  *sort_s receives the preparation (sort + dedup) time.
+ */
+int64_t oracle_gj_sample(int n_vars, int n_atoms, const int* arity, const int* atom_vars,
+                         const int64_t* const* rel, const int64_t* rows, const int* order,
+                         int64_t n_ranges, const int64_t* lo, const int64_t* hi, double budget_s,
+                         uint64_t* counts, double* secs, double* sort_s, int nthreads) {
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    double t0 = now_s();
+    oq_state s;
+    if (prepare(&s, n_vars, n_atoms, arity, atom_vars, rel, rows, order) != 0) return -1;
+    oq_level0 L;
+    level0_runs(&s, &L);
+    *sort_s = now_s() - t0;
+    const oq_rel* rb = &s.rel[s.ops[0][L.best]];
+    double spent = 0;
+    int64_t k = 0;
+    for (; k < n_ranges && spent < budget_s; ++k) {
+        double t1 = now_s();
+        /* runs whose value lies in [lo, hi) */
+        int64_t a = 0, z = L.nruns;
+        while (a < z) { int64_t m = (a + z) / 2; if (rb->t[L.starts[m] * rb->k] < lo[k]) a = m + 1; else z = m; }
+        int64_t b = a; z = L.nruns;
+        while (b < z) { int64_t m = (b + z) / 2; if (rb->t[L.starts[m] * rb->k] < hi[k]) b = m + 1; else z = m; }
+        uint64_t tc = 0, ts = 0, tx = 0, tw[OQ_MAX_VARS] = {0};
+        int64_t out_pos = 0;
+        run_runs(&s, &L, a, b, &tc, &ts, &tx, tw, &out_pos);
+        counts[k] = tc;
+        secs[k] = now_s() - t1;
+        spent += secs[k];
+    }
+    free(L.starts);
+    free_state(&s);
+    return k;
 }
 
 /* Digest of an explicit list of head-order tuples (so tests can digest brute-force

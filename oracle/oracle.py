@@ -41,6 +41,9 @@ def lib():
         L.oracle_gj.restype = ctypes.c_int64
         L.oracle_gj.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P, P,
                                 ctypes.c_int64, P, P, ctypes.c_int]
+        L.oracle_gj_sample.restype = ctypes.c_int64
+        L.oracle_gj_sample.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, ctypes.c_int64, P, P,
+                                       ctypes.c_double, P, P, P, ctypes.c_int]
         L.oracle_digest_rows.restype = None
         L.oracle_digest_rows.argtypes = [P, ctypes.c_int64, ctypes.c_int, P]
         L.textbook_triangles.restype = ctypes.c_int64
@@ -98,7 +101,7 @@ def gj(n_vars: int, atoms, relations, order=None, lo=None, hi=None, emit=False,
         cap = max(int(c0), 1)
         out = np.zeros((cap, n_vars), dtype=np.int64)
     dg = np.zeros(2, dtype=np.uint64) if digest else None
-    wk = np.zeros(1, dtype=np.uint64) if work else None
+    wk = np.zeros(n_vars, dtype=np.uint64) if work else None
     c = L.oracle_gj(n_vars, len(atoms), _ptr(arity), _ptr(avars), ptrs, _ptr(rows), _ptr(ordr),
                     _ptr(lo_a) if lo_a is not None else None,
                     _ptr(hi_a) if hi_a is not None else None,
@@ -114,7 +117,33 @@ def gj(n_vars: int, atoms, relations, order=None, lo=None, hi=None, emit=False,
             res_rows = res_rows[np.lexsort(res_rows.T[::-1])]
     return Result(int(c), res_rows,
                   (int(dg[0]), int(dg[1])) if dg is not None else None,
-                  int(wk[0]) if wk is not None else None)
+                  [int(x) for x in wk] if wk is not None else None)
+
+
+def gj_sample(n_vars: int, atoms, relations, ranges, budget_s: float, order=None, threads: int = 0):
+    """Sort once, then count the ranges (lo, hi) of the first variable of the order one
+    after the other until budget_s seconds of join time are spent.
+    Returns (sort_seconds, [(lo, hi, count, seconds), ...])."""
+    L = lib()
+    order = list(range(n_vars)) if order is None else list(order)
+    arity = np.array([len(a) for a in atoms], dtype=np.int32)
+    avars = np.array([v for a in atoms for v in a], dtype=np.int32)
+    rels = [np.ascontiguousarray(np.asarray(r, dtype=np.int64).reshape(-1, len(a)))
+            for r, a in zip(relations, atoms)]
+    rows = np.array([r.shape[0] for r in rels], dtype=np.int64)
+    ptrs = (ctypes.c_void_p * len(rels))(*[r.ctypes.data for r in rels])
+    ordr = np.array(order, dtype=np.int32)
+    lo = np.array([r[0] for r in ranges], dtype=np.int64)
+    hi = np.array([r[1] for r in ranges], dtype=np.int64)
+    counts = np.zeros(len(ranges), dtype=np.uint64)
+    secs = np.zeros(len(ranges), dtype=np.float64)
+    sort_s = np.zeros(1, dtype=np.float64)
+    k = L.oracle_gj_sample(n_vars, len(atoms), _ptr(arity), _ptr(avars), ptrs, _ptr(rows), _ptr(ordr),
+                           len(ranges), _ptr(lo), _ptr(hi), budget_s, _ptr(counts), _ptr(secs), _ptr(sort_s),
+                           threads)
+    if k < 0:
+        raise ValueError("invalid query")
+    return float(sort_s[0]), [(int(lo[i]), int(hi[i]), int(counts[i]), float(secs[i])) for i in range(k)]
 
 
 def digest_rows(rows: np.ndarray) -> tuple:

@@ -288,6 +288,196 @@ __global__ __launch_bounds__(kBlock) void k_probe(KData D, KStep S, const int32_
     }
 }
 
+// ---------------------------------------------------------------- cursor-based intersection
+// Each wave owns a block of kUnroll * 64 consecutive elements.  While a 64-element
+// chunk stays inside one entry, the chunk's values are consecutive elements of the
+// iterated operand (coalesced load); for every other operand the wave keeps a
+// cursor and finds the window [lo, hi) holding the chunk's value range by
+// exponential search from the cursor (the galloping search of Section 5), then
+// either stages the window in LDS with coalesced loads and searches it there
+// (dense case), or binary-searches the window in place (sparse case).  Chunks
+// spanning several entries fall back to one independent search per lane.
+constexpr int kWin = 512;       // LDS window per wave (elements)
+constexpr int kUnroll = 8;      // chunks of 64 elements per wave block
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// First p in [c, end) with B[p] >= v; exponential search from c (wave-uniform arguments).
+__device__ inline int64_t gallop_lb(const uint32_t* __restrict__ B, int64_t c, int64_t end, uint32_t v) {
+    if (c >= end || B[c] >= v) return c;
+    int64_t lo = c, step = 1;   // B[lo] < v
+    while (lo + step < end && B[lo + step] < v) {
+        lo += step;
+        step <<= 1;
+    }
+    const int64_t hi = lo + step < end ? lo + step : end;
+    return lower_bound_u32(B, lo + 1, hi, v);
+}
+
+template <int MODE, int NOPS>
+__global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32_t* __restrict__ F, Seg G,
+                                                   const uint64_t* __restrict__ prefix, int64_t e_begin,
+                                                   int64_t e_end, uint64_t item_begin, uint64_t n_items,
+                                                   uint64_t* __restrict__ words, unsigned long long* acc) {
+    __shared__ uint32_t win_all[kWaves][kWin];
+    const int lane = threadIdx.x & 63;
+    uint32_t* win = win_all[threadIdx.x >> 6];
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const uint64_t CH = 64ull * kUnroll;
+    const int64_t n_blocks = (int64_t)((n_items + CH - 1) / CH);
+    const uint32_t* arr[NOPS];
+#pragma unroll
+    for (int o = 0; o < NOPS; ++o) arr[o] = op_array(D, S.ops[o]);
+    uint64_t cnt = 0, dsum = 0, dxor = 0;
+    for (int64_t blk = wave; blk < n_blocks; blk += nwaves) {
+        const uint64_t rb = (uint64_t)blk * CH;
+        const uint64_t re = rb + CH < n_items ? rb + CH : n_items;
+        int64_t e = find_entry(prefix, e_begin, e_end, item_begin + rb);
+        int64_t cur[NOPS];
+        bool fresh = true;
+        for (uint64_t rc = rb; rc < re; rc += 64) {
+            const uint64_t g = item_begin + rc;
+            const int nv = (int)(re - rc < 64 ? re - rc : 64);
+            const bool valid = lane < nv;
+            const uint64_t g_last = g + (uint64_t)nv - 1;
+            if (prefix[e + 1] <= g) {
+                e = find_entry(prefix, e + 1, e_end, g);
+                fresh = true;
+            }
+            bool found = false;
+            uint32_t a = 0;
+            int64_t my_e = e;
+            if (g_last < prefix[e + 1]) {
+                const int it = G.iter[e];
+                int64_t beg[NOPS], end[NOPS];
+#pragma unroll
+                for (int o = 0; o < NOPS; ++o) {
+                    beg[o] = G.seg[(2 * o) * G.stride + e];
+                    end[o] = G.seg[(2 * o + 1) * G.stride + e];
+                }
+                if (fresh) {
+#pragma unroll
+                    for (int o = 0; o < NOPS; ++o) cur[o] = beg[o];
+                    fresh = false;
+                }
+                const int64_t off = (int64_t)(g - prefix[e]) + lane;
+#pragma unroll
+                for (int o = 0; o < NOPS; ++o)
+                    if (o == it && valid) a = arr[o][beg[o] + off];
+                found = valid;
+                const uint32_t a_first = __shfl(a, 0, 64);
+                const uint32_t a_last = __shfl(a, nv - 1, 64);
+#pragma unroll
+                for (int o = 0; o < NOPS; ++o) {
+                    if (o == it) continue;
+                    const uint32_t* B = arr[o];
+                    const int64_t lo = gallop_lb(B, cur[o], end[o], a_first);
+                    const int64_t hi = a_last == 0xFFFFFFFFu ? end[o] : gallop_lb(B, lo, end[o], a_last + 1u);
+                    cur[o] = hi;
+                    bool fo;
+                    if (hi - lo <= kWin) {
+                        const int len = (int)(hi - lo);
+                        for (int k = lane; k < len; k += 64) win[k] = B[lo + k];
+                        wave_sync();
+                        int l = 0, h = len;
+                        while (l < h) {
+                            const int mid = (l + h) >> 1;
+                            if (win[mid] < a) l = mid + 1; else h = mid;
+                        }
+                        fo = l < len && win[l] == a;
+                        wave_sync();
+                    } else {
+                        const int64_t p = lower_bound_u32(B, lo, hi, a);
+                        fo = p < hi && B[p] == a;
+                    }
+                    found = found && fo;
+                }
+                if (found && S.has_pred) {
+                    const int64_t raw = (int64_t)unmix_key(a, D.mix);
+                    found = raw >= S.pred_lo && raw < S.pred_hi;
+                }
+            } else {
+                const int64_t e_hi = find_entry(prefix, e, e_end, g_last);
+                if (valid) {
+                    const uint64_t gl = g + lane;
+                    my_e = find_entry(prefix, e, e_hi + 1, gl);
+                    Probe P;
+                    probe_item(D, S, G, prefix, my_e, gl, P);
+                    found = P.found;
+                    a = P.a;
+                }
+                e = e_hi;
+                fresh = true;
+            }
+            const uint64_t bal = __ballot(found);
+            if (MODE == M_BITMAP) {
+                if (lane == 0) words[rc >> 6] = bal;
+            } else {
+                cnt += (uint64_t)__popcll(bal);
+                if (MODE == M_DIGEST && found) {
+                    const int32_t* ent = F + my_e * S.W_in;
+                    uint64_t h = 0x6A09E667F3BCC909ull;
+                    for (int v = 0; v < S.n_vars; ++v) {
+                        const int hw = S.head_word[v];
+                        const uint32_t key = hw < 0 ? a : (uint32_t)ent[hw];
+                        const uint64_t raw = (uint64_t)unmix_key(key, D.mix);
+                        h = fmix64(h ^ (raw + (uint64_t)(v + 1) * 0x9E3779B97F4A7C15ull));
+                    }
+                    dsum += h;
+                    dxor ^= h;
+                }
+            }
+        }
+    }
+    if (MODE != M_BITMAP) {
+        if (MODE == M_DIGEST) {
+            dsum = wave_sum(dsum);
+            dxor = wave_xor(dxor);
+        }
+        if (lane == 0) {
+            if (cnt) atomicAdd(&acc[0], (unsigned long long)cnt);
+            if (MODE == M_DIGEST) {
+                atomicAdd(&acc[1], (unsigned long long)dsum);
+                atomicXor(&acc[2], (unsigned long long)dxor);
+            }
+        }
+    }
+}
+
+template <int MODE>
+static void launch_probe(const KData& D, const KStep& S, const int32_t* F, const Seg& G, const uint64_t* prefix,
+                         int64_t e_begin, int64_t e_end, uint64_t item_begin, uint64_t n_items, uint64_t* words,
+                         unsigned long long* acc, hipStream_t s) {
+    const uint64_t CH = 64ull * kUnroll;
+    int64_t nblk = (int64_t)((n_items + CH - 1) / CH);
+    int64_t grid = (nblk + kWaves - 1) / kWaves;
+    if (grid < 1) grid = 1;
+    if (grid > 16384) grid = 16384;
+#define HC_PROBE2(N) \
+    k_probe2<MODE, N><<<(unsigned)grid, kBlock, 0, s>>>(D, S, F, G, prefix, e_begin, e_end, item_begin, n_items, words, acc)
+    switch (S.n_ops) {
+        case 1: HC_PROBE2(1); break;
+        case 2: HC_PROBE2(2); break;
+        case 3: HC_PROBE2(3); break;
+        case 4: HC_PROBE2(4); break;
+        default: {
+            const int64_t nw = (int64_t)((n_items + 63) / 64);
+            int64_t g2 = (nw + kWaves - 1) / kWaves;
+            if (g2 < 1) g2 = 1;
+            if (g2 > 16384) g2 = 16384;
+            k_probe<MODE><<<(unsigned)g2, kBlock, 0, s>>>(D, S, F, G, prefix, e_begin, e_end, item_begin, n_items,
+                                                         words, acc);
+        }
+    }
+#undef HC_PROBE2
+    HC_HIP(hipGetLastError());
+}
+
 struct MatOut {
     int32_t* F;            // EXPAND
     uint32_t* tval;        // TMP
@@ -604,11 +794,7 @@ struct Runner {
         const int64_t nw = (int64_t)((ni + 63) / 64);
         words = DevBuf<uint64_t>(A, (size_t)nw + 1);
         wpre = DevBuf<uint64_t>(A, (size_t)nw + 1);
-        if (nw > 0) {
-            k_probe<M_BITMAP><<<grid_waves(nw), kBlock, 0, s>>>(D, S, F, B.G, prefix_abs, ea, eb, ib, ni, words.p,
-                                                                  nullptr);
-            HC_HIP(hipGetLastError());
-        }
+        if (nw > 0) launch_probe<M_BITMAP>(D, S, F, B.G, prefix_abs, ea, eb, ib, ni, words.p, nullptr, s);
         scan_popc(A, words.p, wpre.p, nw, s);
         return read_u64(wpre.p + nw);
     }
@@ -686,15 +872,11 @@ void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
         if (i == nv - 1) {
             if (!emit) {
                 if (total > 0) {
-                    const int64_t nw = (int64_t)((total + 63) / 64);
                     if (ctx->profiling) HC_HIP(hipEventRecord(ev0, s));
                     if (digest)
-                        k_probe<M_DIGEST><<<grid_waves(nw, 16384), kBlock, 0, s>>>(D, S, F, B.G, prefix_abs, ea, eb, 0,
-                                                                                    total, nullptr, acc.p);
+                        launch_probe<M_DIGEST>(D, S, F, B.G, prefix_abs, ea, eb, 0, total, nullptr, acc.p, s);
                     else
-                        k_probe<M_COUNT><<<grid_waves(nw, 16384), kBlock, 0, s>>>(D, S, F, B.G, prefix_abs, ea, eb, 0,
-                                                                                   total, nullptr, acc.p);
-                    HC_HIP(hipGetLastError());
+                        launch_probe<M_COUNT>(D, S, F, B.G, prefix_abs, ea, eb, 0, total, nullptr, acc.p, s);
                     if (ctx->profiling) {
                         HC_HIP(hipEventRecord(ev1, s));
                         HC_HIP(hipEventSynchronize(ev1));

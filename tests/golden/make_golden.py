@@ -62,7 +62,7 @@ def main():
             assert r.count == 6 * tb, (r.count, tb)
             rec["textbook_triangles"] = tb
             if r.work is not None:
-                rec["work_gallop_order_abc"] = r.work
+                rec["work_gallop_per_level"] = r.work
         rec["count"] = r.count
         rec["digest"] = [str(r.digest[0]), str(r.digest[1])]
         rec["oracle_seconds"] = round(time.time() - t0, 1)
