@@ -289,16 +289,18 @@ __global__ __launch_bounds__(kBlock) void k_probe(KData D, KStep S, const int32_
 }
 
 // ---------------------------------------------------------------- cursor-based intersection
-// Each wave owns a block of kUnroll * 64 consecutive elements.  While a 64-element
-// chunk stays inside one entry, the chunk's values are consecutive elements of the
-// iterated operand (coalesced load); for every other operand the wave keeps a
-// cursor and finds the window [lo, hi) holding the chunk's value range by
-// exponential search from the cursor (the galloping search of Section 5), then
-// either stages the window in LDS with coalesced loads and searches it there
-// (dense case), or binary-searches the window in place (sparse case).  Chunks
-// spanning several entries fall back to one independent search per lane.
-constexpr int kWin = 512;       // LDS window per wave (elements)
-constexpr int kUnroll = 8;      // chunks of 64 elements per wave block
+// The deepest (hottest) level.  Each wave owns one contiguous range of the
+// flattened elements, so it visits its entries in order and keeps, per entry,
+// one cursor per probed operand.  While the next elements stay inside one entry
+// they are consecutive elements of the iterated operand: the wave takes up to
+// 4 x 64 of them at once (4 per lane, coalesced loads), finds the window
+// [lo, hi) of every other operand that can hold their value range by
+// exponential search from the cursor (the galloping search of Section 5),
+// stages a dense window in LDS with coalesced loads and searches it there, or
+// binary-searches a sparse window in place.  Stretches where one 64-element
+// chunk spans several small entries fall back to one search per lane.
+constexpr int kWin = 1024;      // LDS window per wave (elements)
+constexpr int kSub = 4;         // 64-element chunks per cursor step
 
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -318,119 +320,202 @@ __device__ inline int64_t gallop_lb(const uint32_t* __restrict__ B, int64_t c, i
     return lower_bound_u32(B, lo + 1, hi, v);
 }
 
+// Largest e' in [e, e_end) with prefix[e'] <= g, given prefix[e] <= g: exponential
+// search forward from e (the next entries are usually close).
+__device__ inline int64_t advance_entry(const uint64_t* __restrict__ prefix, int64_t e, int64_t e_end, uint64_t g) {
+    int64_t lo = e, step = 1;   // prefix[lo] <= g
+    while (lo + step < e_end && prefix[lo + step] <= g) {
+        lo += step;
+        step <<= 1;
+    }
+    const int64_t hi = lo + step < e_end ? lo + step : e_end;
+    return find_entry(prefix, lo, hi, g);
+}
+
+__device__ inline int lds_lower_bound(const uint32_t* w, int len, uint32_t a) {
+    int l = 0, h = len;
+    while (l < h) {
+        const int mid = (l + h) >> 1;
+        if (w[mid] < a) l = mid + 1; else h = mid;
+    }
+    return l;
+}
+
+template <int MODE>
+__device__ inline void digest_add(const KData& D, const KStep& S, const int32_t* ent, uint32_t a, uint64_t& dsum,
+                                  uint64_t& dxor) {
+    uint64_t h = 0x6A09E667F3BCC909ull;
+    for (int v = 0; v < S.n_vars; ++v) {
+        const int hw = S.head_word[v];
+        const uint32_t key = hw < 0 ? a : (uint32_t)ent[hw];
+        const uint64_t raw = (uint64_t)unmix_key(key, D.mix);
+        h = fmix64(h ^ (raw + (uint64_t)(v + 1) * 0x9E3779B97F4A7C15ull));
+    }
+    dsum += h;
+    dxor ^= h;
+}
+
 template <int MODE, int NOPS>
 __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32_t* __restrict__ F, Seg G,
                                                    const uint64_t* __restrict__ prefix, int64_t e_begin,
                                                    int64_t e_end, uint64_t item_begin, uint64_t n_items,
-                                                   uint64_t* __restrict__ words, unsigned long long* acc) {
+                                                   uint64_t per_wave, uint64_t* __restrict__ words,
+                                                   unsigned long long* acc) {
     __shared__ uint32_t win_all[kWaves][kWin];
     const int lane = threadIdx.x & 63;
     uint32_t* win = win_all[threadIdx.x >> 6];
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const uint64_t CH = 64ull * kUnroll;
-    const int64_t n_blocks = (int64_t)((n_items + CH - 1) / CH);
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t* arr[NOPS];
 #pragma unroll
     for (int o = 0; o < NOPS; ++o) arr[o] = op_array(D, S.ops[o]);
     uint64_t cnt = 0, dsum = 0, dxor = 0;
-    for (int64_t blk = wave; blk < n_blocks; blk += nwaves) {
-        const uint64_t rb = (uint64_t)blk * CH;
-        const uint64_t re = rb + CH < n_items ? rb + CH : n_items;
-        int64_t e = find_entry(prefix, e_begin, e_end, item_begin + rb);
-        int64_t cur[NOPS];
-        bool fresh = true;
-        for (uint64_t rc = rb; rc < re; rc += 64) {
+    const uint64_t r_begin = wave * per_wave;
+    const uint64_t r_end = r_begin + per_wave < n_items ? r_begin + per_wave : n_items;
+    if (r_begin < r_end) {
+        // current entry and its wave-uniform description
+        int64_t e = find_entry(prefix, e_begin, e_end, item_begin + r_begin);
+        uint64_t pe0 = prefix[e], pe1 = prefix[e + 1];
+        int it = G.iter[e];
+        int64_t beg[NOPS], end[NOPS], cur[NOPS];
+#pragma unroll
+        for (int o = 0; o < NOPS; ++o) {
+            beg[o] = G.seg[(2 * o) * G.stride + e];
+            end[o] = G.seg[(2 * o + 1) * G.stride + e];
+            cur[o] = beg[o];
+        }
+        uint64_t rc = r_begin;
+        while (rc < r_end) {
             const uint64_t g = item_begin + rc;
-            const int nv = (int)(re - rc < 64 ? re - rc : 64);
-            const bool valid = lane < nv;
-            const uint64_t g_last = g + (uint64_t)nv - 1;
-            if (prefix[e + 1] <= g) {
-                e = find_entry(prefix, e + 1, e_end, g);
-                fresh = true;
-            }
-            bool found = false;
-            uint32_t a = 0;
-            int64_t my_e = e;
-            if (g_last < prefix[e + 1]) {
-                const int it = G.iter[e];
-                int64_t beg[NOPS], end[NOPS];
+            if (pe1 <= g) {   // move to the entry holding g
+                e = advance_entry(prefix, e + 1, e_end, g);
+                pe0 = prefix[e];
+                pe1 = prefix[e + 1];
+                it = G.iter[e];
 #pragma unroll
                 for (int o = 0; o < NOPS; ++o) {
                     beg[o] = G.seg[(2 * o) * G.stride + e];
                     end[o] = G.seg[(2 * o + 1) * G.stride + e];
+                    cur[o] = beg[o];
                 }
-                if (fresh) {
+            }
+            const uint64_t left_wave = r_end - rc;
+            const uint64_t left_entry = pe1 - g;
+            const uint64_t chunk = left_wave < 64 ? left_wave : 64;
+            if (left_entry >= chunk) {
+                // ---- uniform step: up to kSub*64 elements of entry e; it ends on a
+                // 64-element boundary (match words stay aligned) or at the range end
+                uint64_t n_sc = left_entry >= left_wave ? left_wave : (left_entry & ~63ull);
+                if (n_sc > 64ull * kSub) n_sc = 64ull * kSub;
+                const int nsc = (int)n_sc;
+                const int64_t off0 = (int64_t)(g - pe0);
+                uint32_t a[kSub];
+                bool v[kSub], f[kSub];
 #pragma unroll
-                    for (int o = 0; o < NOPS; ++o) cur[o] = beg[o];
-                    fresh = false;
+                for (int k = 0; k < kSub; ++k) {
+                    const int j = k * 64 + lane;
+                    v[k] = j < nsc;
+                    f[k] = v[k];
+                    a[k] = 0;
+#pragma unroll
+                    for (int o = 0; o < NOPS; ++o)
+                        if (o == it && v[k]) a[k] = arr[o][beg[o] + off0 + j];
                 }
-                const int64_t off = (int64_t)(g - prefix[e]) + lane;
-#pragma unroll
-                for (int o = 0; o < NOPS; ++o)
-                    if (o == it && valid) a = arr[o][beg[o] + off];
-                found = valid;
-                const uint32_t a_first = __shfl(a, 0, 64);
-                const uint32_t a_last = __shfl(a, nv - 1, 64);
+                const uint32_t a_first = __shfl(a[0], 0, 64);
+                const int last = nsc - 1;
 #pragma unroll
                 for (int o = 0; o < NOPS; ++o) {
                     if (o == it) continue;
                     const uint32_t* B = arr[o];
                     const int64_t lo = gallop_lb(B, cur[o], end[o], a_first);
-                    const int64_t hi = a_last == 0xFFFFFFFFu ? end[o] : gallop_lb(B, lo, end[o], a_last + 1u);
-                    cur[o] = hi;
-                    bool fo;
-                    if (hi - lo <= kWin) {
-                        const int len = (int)(hi - lo);
-                        for (int k = lane; k < len; k += 64) win[k] = B[lo + k];
-                        wave_sync();
-                        int l = 0, h = len;
-                        while (l < h) {
-                            const int mid = (l + h) >> 1;
-                            if (win[mid] < a) l = mid + 1; else h = mid;
+                    const int64_t avail = end[o] - lo;
+                    // window sized by this step's share of the entry's remaining elements
+                    uint64_t est = (uint64_t)nsc * (uint64_t)avail / (pe1 - g);
+                    est += (est >> 2) + 64;
+                    int64_t lw = avail < (int64_t)kWin ? avail : (int64_t)kWin;
+                    if ((int64_t)est < lw) lw = (int64_t)est;
+                    const int len = (int)lw;
+                    for (int k = lane; k < len; k += 64) win[k] = B[lo + k];
+                    wave_sync();
+                    const uint32_t wmax = len > 0 ? win[len - 1] : 0u;
+                    int rel[kSub];
+#pragma unroll
+                    for (int k = 0; k < kSub; ++k) {
+                        rel[k] = 0;
+                        if (v[k]) {
+                            bool fo;
+                            if (len > 0 && a[k] <= wmax) {
+                                const int p = lds_lower_bound(win, len, a[k]);
+                                rel[k] = p;
+                                fo = win[p] == a[k];
+                            } else {
+                                const int64_t p = lower_bound_u32(B, lo + len, end[o], a[k]);
+                                rel[k] = (int)(p - lo);
+                                fo = p < end[o] && B[p] == a[k];
+                            }
+                            f[k] = f[k] && fo;
                         }
-                        fo = l < len && win[l] == a;
-                        wave_sync();
-                    } else {
-                        const int64_t p = lower_bound_u32(B, lo, hi, a);
-                        fo = p < hi && B[p] == a;
                     }
-                    found = found && fo;
+                    wave_sync();
+                    // cursor: lower bound of the step's last element
+                    int rl = 0;
+#pragma unroll
+                    for (int k = 0; k < kSub; ++k) {
+                        const int t = __shfl(rel[k], last & 63, 64);
+                        if (k == (last >> 6)) rl = t;
+                    }
+                    cur[o] = lo + rl;
                 }
-                if (found && S.has_pred) {
-                    const int64_t raw = (int64_t)unmix_key(a, D.mix);
-                    found = raw >= S.pred_lo && raw < S.pred_hi;
+#pragma unroll
+                for (int k = 0; k < kSub; ++k) {
+                    if (f[k] && S.has_pred) {
+                        const int64_t raw = (int64_t)unmix_key(a[k], D.mix);
+                        f[k] = raw >= S.pred_lo && raw < S.pred_hi;
+                    }
+                    const uint64_t bal = __ballot(f[k]);
+                    if (MODE == M_BITMAP) {
+                        if (lane == 0 && k * 64 < nsc) words[(rc >> 6) + k] = bal;
+                    } else {
+                        cnt += (uint64_t)__popcll(bal);
+                        if (MODE == M_DIGEST && f[k]) digest_add<MODE>(D, S, F + e * S.W_in, a[k], dsum, dxor);
+                    }
                 }
+                rc += n_sc;
             } else {
-                const int64_t e_hi = find_entry(prefix, e, e_end, g_last);
+                // ---- mixed chunk: 64 elements spanning several entries
+                const int nv = (int)chunk;
+                const bool valid = lane < nv;
+                const uint64_t g_last = g + chunk - 1;
+                const int64_t e_hi = advance_entry(prefix, e, e_end, g_last);
+                bool found = false;
+                uint32_t av = 0;
+                int64_t my_e = e;
                 if (valid) {
                     const uint64_t gl = g + lane;
                     my_e = find_entry(prefix, e, e_hi + 1, gl);
                     Probe P;
                     probe_item(D, S, G, prefix, my_e, gl, P);
                     found = P.found;
-                    a = P.a;
+                    av = P.a;
                 }
+                const uint64_t bal = __ballot(found);
+                if (MODE == M_BITMAP) {
+                    if (lane == 0) words[rc >> 6] = bal;
+                } else {
+                    cnt += (uint64_t)__popcll(bal);
+                    if (MODE == M_DIGEST && found) digest_add<MODE>(D, S, F + my_e * S.W_in, av, dsum, dxor);
+                }
+                // continue inside the last entry touched (its cursors restart)
                 e = e_hi;
-                fresh = true;
-            }
-            const uint64_t bal = __ballot(found);
-            if (MODE == M_BITMAP) {
-                if (lane == 0) words[rc >> 6] = bal;
-            } else {
-                cnt += (uint64_t)__popcll(bal);
-                if (MODE == M_DIGEST && found) {
-                    const int32_t* ent = F + my_e * S.W_in;
-                    uint64_t h = 0x6A09E667F3BCC909ull;
-                    for (int v = 0; v < S.n_vars; ++v) {
-                        const int hw = S.head_word[v];
-                        const uint32_t key = hw < 0 ? a : (uint32_t)ent[hw];
-                        const uint64_t raw = (uint64_t)unmix_key(key, D.mix);
-                        h = fmix64(h ^ (raw + (uint64_t)(v + 1) * 0x9E3779B97F4A7C15ull));
-                    }
-                    dsum += h;
-                    dxor ^= h;
+                pe0 = prefix[e];
+                pe1 = prefix[e + 1];
+                it = G.iter[e];
+#pragma unroll
+                for (int o = 0; o < NOPS; ++o) {
+                    beg[o] = G.seg[(2 * o) * G.stride + e];
+                    end[o] = G.seg[(2 * o + 1) * G.stride + e];
+                    cur[o] = beg[o];
                 }
+                rc += chunk;
             }
         }
     }
@@ -453,20 +538,22 @@ template <int MODE>
 static void launch_probe(const KData& D, const KStep& S, const int32_t* F, const Seg& G, const uint64_t* prefix,
                          int64_t e_begin, int64_t e_end, uint64_t item_begin, uint64_t n_items, uint64_t* words,
                          unsigned long long* acc, hipStream_t s) {
-    const uint64_t CH = 64ull * kUnroll;
-    int64_t nblk = (int64_t)((n_items + CH - 1) / CH);
-    int64_t grid = (nblk + kWaves - 1) / kWaves;
-    if (grid < 1) grid = 1;
-    if (grid > 16384) grid = 16384;
-#define HC_PROBE2(N) \
-    k_probe2<MODE, N><<<(unsigned)grid, kBlock, 0, s>>>(D, S, F, G, prefix, e_begin, e_end, item_begin, n_items, words, acc)
+    // one contiguous, 64-aligned range of elements per wave; at most 16384 workgroups
+    const uint64_t n_chunks = (n_items + 63) / 64;
+    uint64_t waves = n_chunks < 65536 ? n_chunks : 65536;
+    if (waves < 1) waves = 1;
+    const uint64_t per_wave = ((n_chunks + waves - 1) / waves) * 64;
+    const uint64_t grid = (waves + kWaves - 1) / kWaves;
+#define HC_PROBE2(N)                                                                                             \
+    k_probe2<MODE, N><<<(unsigned)grid, kBlock, 0, s>>>(D, S, F, G, prefix, e_begin, e_end, item_begin, n_items, \
+                                                        per_wave, words, acc)
     switch (S.n_ops) {
         case 1: HC_PROBE2(1); break;
         case 2: HC_PROBE2(2); break;
         case 3: HC_PROBE2(3); break;
         case 4: HC_PROBE2(4); break;
         default: {
-            const int64_t nw = (int64_t)((n_items + 63) / 64);
+            const int64_t nw = (int64_t)n_chunks;
             int64_t g2 = (nw + kWaves - 1) / kWaves;
             if (g2 < 1) g2 = 1;
             if (g2 > 16384) g2 = 16384;
