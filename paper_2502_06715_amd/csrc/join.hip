@@ -301,6 +301,9 @@ __global__ __launch_bounds__(kBlock) void k_probe(KData D, KStep S, const int32_
 // chunk spans several small entries fall back to one search per lane.
 constexpr int kWin = 1024;      // LDS window per wave (elements)
 constexpr int kSub = 4;         // 64-element chunks per cursor step
+constexpr uint64_t kChunk = 2048;       // elements per work-queue chunk
+constexpr int kXcd = 8;                 // XCDs of an MI355X
+constexpr uint64_t kPersistBlocks = 2048;
 
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -359,21 +362,33 @@ template <int MODE, int NOPS>
 __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32_t* __restrict__ F, Seg G,
                                                    const uint64_t* __restrict__ prefix, int64_t e_begin,
                                                    int64_t e_end, uint64_t item_begin, uint64_t n_items,
-                                                   uint64_t per_wave, uint64_t* __restrict__ words,
-                                                   unsigned long long* acc) {
+                                                   const int64_t* __restrict__ chunk_entry,
+                                                   unsigned long long* queue, uint64_t n_chunks,
+                                                   uint64_t* __restrict__ words, unsigned long long* acc) {
     __shared__ uint32_t win_all[kWaves][kWin];
     const int lane = threadIdx.x & 63;
     uint32_t* win = win_all[threadIdx.x >> 6];
-    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t* arr[NOPS];
 #pragma unroll
     for (int o = 0; o < NOPS; ++o) arr[o] = op_array(D, S.ops[o]);
     uint64_t cnt = 0, dsum = 0, dxor = 0;
-    const uint64_t r_begin = wave * per_wave;
-    const uint64_t r_end = r_begin + per_wave < n_items ? r_begin + per_wave : n_items;
-    if (r_begin < r_end) {
+    // Work queue per XCD: workgroups are dispatched to the 8 XCDs round-robin, so
+    // blockIdx % 8 names the XCD; each XCD sweeps its own contiguous eighth of the
+    // chunks in order, which keeps the few HyperCube cells it works on at a time
+    // (and their slices of the CoCo arrays) resident in its L2.  Every wave leaves
+    // once its XCD's queue is exhausted.
+    const int xcd = (int)(blockIdx.x % kXcd);
+    const uint64_t c_lo = n_chunks * (uint64_t)xcd / kXcd, c_hi = n_chunks * (uint64_t)(xcd + 1) / kXcd;
+    for (;;) {
+        unsigned long long t = 0;
+        if (lane == 0) t = atomicAdd(&queue[xcd], 1ull);
+        const uint64_t c = c_lo + (((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(t >> 32)) << 32) |
+                                   (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)t));
+        if (c >= c_hi) break;
+        const uint64_t r_begin = c * kChunk;
+        const uint64_t r_end = r_begin + kChunk < n_items ? r_begin + kChunk : n_items;
         // current entry and its wave-uniform description
-        int64_t e = find_entry(prefix, e_begin, e_end, item_begin + r_begin);
+        int64_t e = chunk_entry[c];
         uint64_t pe0 = prefix[e], pe1 = prefix[e + 1];
         int it = G.iter[e];
         int64_t beg[NOPS], end[NOPS], cur[NOPS];
@@ -534,32 +549,50 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
     }
 }
 
+__global__ void k_chunk_entries(const uint64_t* __restrict__ prefix, int64_t e_begin, int64_t e_end,
+                                uint64_t item_begin, uint64_t n_chunks, int64_t* __restrict__ out) {
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_chunks;
+         t += (uint64_t)gridDim.x * blockDim.x)
+        out[t] = find_entry(prefix, e_begin, e_end, item_begin + t * kChunk);
+}
+
 template <int MODE>
-static void launch_probe(const KData& D, const KStep& S, const int32_t* F, const Seg& G, const uint64_t* prefix,
-                         int64_t e_begin, int64_t e_end, uint64_t item_begin, uint64_t n_items, uint64_t* words,
-                         unsigned long long* acc, hipStream_t s) {
-    // one contiguous, 64-aligned range of elements per wave; at most 16384 workgroups
-    const uint64_t n_chunks = (n_items + 63) / 64;
-    uint64_t waves = n_chunks < 65536 ? n_chunks : 65536;
-    if (waves < 1) waves = 1;
-    const uint64_t per_wave = ((n_chunks + waves - 1) / waves) * 64;
-    const uint64_t grid = (waves + kWaves - 1) / kWaves;
-#define HC_PROBE2(N)                                                                                             \
-    k_probe2<MODE, N><<<(unsigned)grid, kBlock, 0, s>>>(D, S, F, G, prefix, e_begin, e_end, item_begin, n_items, \
-                                                        per_wave, words, acc)
+static void launch_probe(const Alloc& A, const KData& D, const KStep& S, const int32_t* F, const Seg& G,
+                         const uint64_t* prefix, int64_t e_begin, int64_t e_end, uint64_t item_begin,
+                         uint64_t n_items, uint64_t* words, unsigned long long* acc, hipStream_t s) {
+    if (S.n_ops > 4) {
+        const int64_t nw = (int64_t)((n_items + 63) / 64);
+        int64_t g2 = (nw + kWaves - 1) / kWaves;
+        if (g2 < 1) g2 = 1;
+        if (g2 > 16384) g2 = 16384;
+        k_probe<MODE><<<(unsigned)g2, kBlock, 0, s>>>(D, S, F, G, prefix, e_begin, e_end, item_begin, n_items,
+                                                     words, acc);
+        HC_HIP(hipGetLastError());
+        return;
+    }
+    const uint64_t n_chunks = (n_items + kChunk - 1) / kChunk;
+    DevBuf<int64_t> ce(A, (size_t)n_chunks + 1);
+    DevBuf<unsigned long long> q(A, kXcd);
+    HC_HIP(hipMemsetAsync(q.p, 0, sizeof(unsigned long long) * kXcd, s));
+    {
+        int64_t g = (int64_t)((n_chunks + kBlock - 1) / kBlock);
+        if (g < 1) g = 1;
+        if (g > 16384) g = 16384;
+        k_chunk_entries<<<(unsigned)g, kBlock, 0, s>>>(prefix, e_begin, e_end, item_begin, n_chunks, ce.p);
+        HC_HIP(hipGetLastError());
+    }
+    // persistent grid: a multiple of 8 workgroups (every XCD queue has consumers)
+    uint64_t blocks = (n_chunks + kWaves - 1) / kWaves;
+    if (blocks > kPersistBlocks) blocks = kPersistBlocks;
+    blocks = ((blocks + kXcd - 1) / kXcd) * kXcd;
+#define HC_PROBE2(N)                                                                                          \
+    k_probe2<MODE, N><<<(unsigned)blocks, kBlock, 0, s>>>(D, S, F, G, prefix, e_begin, e_end, item_begin,     \
+                                                          n_items, ce.p, q.p, n_chunks, words, acc)
     switch (S.n_ops) {
         case 1: HC_PROBE2(1); break;
         case 2: HC_PROBE2(2); break;
         case 3: HC_PROBE2(3); break;
-        case 4: HC_PROBE2(4); break;
-        default: {
-            const int64_t nw = (int64_t)n_chunks;
-            int64_t g2 = (nw + kWaves - 1) / kWaves;
-            if (g2 < 1) g2 = 1;
-            if (g2 > 16384) g2 = 16384;
-            k_probe<MODE><<<(unsigned)g2, kBlock, 0, s>>>(D, S, F, G, prefix, e_begin, e_end, item_begin, n_items,
-                                                         words, acc);
-        }
+        default: HC_PROBE2(4); break;
     }
 #undef HC_PROBE2
     HC_HIP(hipGetLastError());
@@ -881,7 +914,7 @@ struct Runner {
         const int64_t nw = (int64_t)((ni + 63) / 64);
         words = DevBuf<uint64_t>(A, (size_t)nw + 1);
         wpre = DevBuf<uint64_t>(A, (size_t)nw + 1);
-        if (nw > 0) launch_probe<M_BITMAP>(D, S, F, B.G, prefix_abs, ea, eb, ib, ni, words.p, nullptr, s);
+        if (nw > 0) launch_probe<M_BITMAP>(A, D, S, F, B.G, prefix_abs, ea, eb, ib, ni, words.p, nullptr, s);
         scan_popc(A, words.p, wpre.p, nw, s);
         return read_u64(wpre.p + nw);
     }
@@ -961,9 +994,9 @@ void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
                 if (total > 0) {
                     if (ctx->profiling) HC_HIP(hipEventRecord(ev0, s));
                     if (digest)
-                        launch_probe<M_DIGEST>(D, S, F, B.G, prefix_abs, ea, eb, 0, total, nullptr, acc.p, s);
+                        launch_probe<M_DIGEST>(A, D, S, F, B.G, prefix_abs, ea, eb, 0, total, nullptr, acc.p, s);
                     else
-                        launch_probe<M_COUNT>(D, S, F, B.G, prefix_abs, ea, eb, 0, total, nullptr, acc.p, s);
+                        launch_probe<M_COUNT>(A, D, S, F, B.G, prefix_abs, ea, eb, 0, total, nullptr, acc.p, s);
                     if (ctx->profiling) {
                         HC_HIP(hipEventRecord(ev1, s));
                         HC_HIP(hipEventSynchronize(ev1));
@@ -1068,10 +1101,13 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
     HC_REQUIRE(K <= 24, HC_ERR_INVALID, "more than 2^24 cells");
     R.K = K;
     {
+        // cell id: the first variable of the order in the low bits, the deepest in the
+        // high bits, so consecutive cells share the deepest level's key range (and
+        // the slices of the child lists the deepest intersections read)
         int acc_shift = 0;
-        for (int v = P.n_vars - 1; v >= 0; --v) {
-            R.cell_shift[v] = acc_shift;
-            acc_shift += R.shares[v];
+        for (int i = 0; i < P.n_vars; ++i) {
+            R.cell_shift[P.order[i]] = acc_shift;
+            acc_shift += R.shares[P.order[i]];
         }
     }
     R.D = KData{};
