@@ -87,8 +87,7 @@ struct KStep {
     int8_t head_word[kMaxVars];   // entry word of each head variable, -1 = the value bound here
 };
 
-enum Mode { M_COUNT = 0, M_DIGEST = 1, M_BITMAP = 2 };
-enum MatMode { MAT_EXPAND = 0, MAT_TMP = 1, MAT_EMIT = 2 };
+enum Mode { M_COUNT = 0, M_DIGEST = 1, M_BITMAP = 2, M_EXPAND = 3, M_TMPW = 4, M_EMIT = 5 };
 
 struct Seg {
     int32_t* seg;      // [2*n_ops][stride]: begin, end per operand
@@ -288,6 +287,46 @@ __global__ __launch_bounds__(kBlock) void k_probe(KData D, KStep S, const int32_
     }
 }
 
+struct MatOut {
+    int32_t* F;            // next frontier
+    uint32_t* tval;        // lifted intersection values
+    int32_t* tsrc[kMaxOps];
+    void* rows;            // emitted rows
+    int64_t row_base, row_cap;
+};
+
+// Write one match at its slot: a frontier entry (bound values, node indices of
+// the atoms whose first variable was just bound, live temporary references), a
+// lifted-intersection element with its source positions, or an output row.
+__device__ inline void write_item(int mode, const KData& D, const KStep& S, const int32_t* ent, uint32_t a,
+                                  const int64_t* pos, int64_t rank, const MatOut& out) {
+    if (mode == M_EXPAND) {
+        int32_t* o = out.F + rank * S.W_out;
+        for (int c = 0; c < S.n_copy; ++c) o[S.copy_to[c]] = ent[S.copy_from[c]];
+        o[S.val_word] = (int32_t)a;
+        for (int t = 0; t < S.n_new; ++t) {
+            const int op = S.new_op[t];
+            const int64_t p = pos[op];
+            o[S.new_word[t]] = S.ops[op].kind == OP_TMP ? D.tmp_src[S.ops[op].group][S.new_src[t]][p] : (int32_t)p;
+        }
+        for (int z = 0; z < S.n_zero; ++z) o[S.zero_word[z]] = 0;
+    } else if (mode == M_TMPW) {
+        out.tval[rank] = a;
+        for (int t = 0; t < S.n_src; ++t) out.tsrc[t][rank] = (int32_t)pos[S.src_op[t]];
+    } else {
+        const int64_t row = out.row_base + rank;
+        if (row < out.row_cap) {
+            for (int v = 0; v < S.n_vars; ++v) {
+                const int hw = S.head_word[v];
+                const uint32_t key = hw < 0 ? a : (uint32_t)ent[hw];
+                const uint32_t raw = unmix_key(key, D.mix);
+                if (D.dtype64) ((int64_t*)out.rows)[row * S.n_vars + v] = (int64_t)raw;
+                else ((int32_t*)out.rows)[row * S.n_vars + v] = (int32_t)raw;
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- cursor-based intersection
 // The deepest (hottest) level.  Each wave owns one contiguous range of the
 // flattened elements, so it visits its entries in order and keeps, per entry,
@@ -364,7 +403,9 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                                                    int64_t e_end, uint64_t item_begin, uint64_t n_items,
                                                    const int64_t* __restrict__ chunk_entry,
                                                    unsigned long long* queue, uint64_t n_chunks,
-                                                   uint64_t* __restrict__ words, unsigned long long* acc) {
+                                                   uint64_t* __restrict__ words, unsigned long long* acc,
+                                                   const uint64_t* __restrict__ wprefix, MatOut out) {
+    constexpr bool kMat = MODE >= M_EXPAND;
     __shared__ uint32_t win_all[kWaves][kWin];
     const int lane = threadIdx.x & 63;
     uint32_t* win = win_all[threadIdx.x >> 6];
@@ -425,12 +466,15 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                 const int64_t off0 = (int64_t)(g - pe0);
                 uint32_t a[kSub];
                 bool v[kSub], f[kSub];
+                int32_t pos[NOPS][kSub];   // absolute positions (materialising modes)
 #pragma unroll
                 for (int k = 0; k < kSub; ++k) {
                     const int j = k * 64 + lane;
                     v[k] = j < nsc;
                     f[k] = v[k];
                     a[k] = 0;
+#pragma unroll
+                    for (int o = 0; o < NOPS; ++o) pos[o][k] = (int32_t)(beg[o] + off0 + j);
 #pragma unroll
                     for (int o = 0; o < NOPS; ++o)
                         if (o == it && v[k]) a[k] = arr[o][beg[o] + off0 + j];
@@ -479,6 +523,10 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                         if (k == (last >> 6)) rl = t;
                     }
                     cur[o] = lo + rl;
+                    if (kMat) {
+#pragma unroll
+                        for (int k = 0; k < kSub; ++k) pos[o][k] = (int32_t)(lo + rel[k]);
+                    }
                 }
 #pragma unroll
                 for (int k = 0; k < kSub; ++k) {
@@ -487,7 +535,16 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                         f[k] = raw >= S.pred_lo && raw < S.pred_hi;
                     }
                     const uint64_t bal = __ballot(f[k]);
-                    if (MODE == M_BITMAP) {
+                    if (kMat) {
+                        if (f[k]) {
+                            int64_t pp[NOPS];
+#pragma unroll
+                            for (int o = 0; o < NOPS; ++o) pp[o] = pos[o][k];
+                            const int64_t rank =
+                                (int64_t)(wprefix[(rc >> 6) + k] + (uint64_t)__popcll(bal & lanemask_lt()));
+                            write_item(MODE, D, S, F + e * S.W_in, a[k], pp, rank, out);
+                        }
+                    } else if (MODE == M_BITMAP) {
                         if (lane == 0 && k * 64 < nsc) words[(rc >> 6) + k] = bal;
                     } else {
                         cnt += (uint64_t)__popcll(bal);
@@ -504,16 +561,21 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                 bool found = false;
                 uint32_t av = 0;
                 int64_t my_e = e;
+                Probe P;
                 if (valid) {
                     const uint64_t gl = g + lane;
                     my_e = find_entry(prefix, e, e_hi + 1, gl);
-                    Probe P;
                     probe_item(D, S, G, prefix, my_e, gl, P);
                     found = P.found;
                     av = P.a;
                 }
                 const uint64_t bal = __ballot(found);
-                if (MODE == M_BITMAP) {
+                if (kMat) {
+                    if (found) {
+                        const int64_t rank = (int64_t)(wprefix[rc >> 6] + (uint64_t)__popcll(bal & lanemask_lt()));
+                        write_item(MODE, D, S, F + my_e * S.W_in, av, P.pos, rank, out);
+                    }
+                } else if (MODE == M_BITMAP) {
                     if (lane == 0) words[rc >> 6] = bal;
                 } else {
                     cnt += (uint64_t)__popcll(bal);
@@ -534,7 +596,7 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
             }
         }
     }
-    if (MODE != M_BITMAP) {
+    if (MODE == M_COUNT || MODE == M_DIGEST) {
         if (MODE == M_DIGEST) {
             dsum = wave_sum(dsum);
             dxor = wave_xor(dxor);
@@ -549,64 +611,7 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
     }
 }
 
-__global__ void k_chunk_entries(const uint64_t* __restrict__ prefix, int64_t e_begin, int64_t e_end,
-                                uint64_t item_begin, uint64_t n_chunks, int64_t* __restrict__ out) {
-    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_chunks;
-         t += (uint64_t)gridDim.x * blockDim.x)
-        out[t] = find_entry(prefix, e_begin, e_end, item_begin + t * kChunk);
-}
-
 template <int MODE>
-static void launch_probe(const Alloc& A, const KData& D, const KStep& S, const int32_t* F, const Seg& G,
-                         const uint64_t* prefix, int64_t e_begin, int64_t e_end, uint64_t item_begin,
-                         uint64_t n_items, uint64_t* words, unsigned long long* acc, hipStream_t s) {
-    if (S.n_ops > 4) {
-        const int64_t nw = (int64_t)((n_items + 63) / 64);
-        int64_t g2 = (nw + kWaves - 1) / kWaves;
-        if (g2 < 1) g2 = 1;
-        if (g2 > 16384) g2 = 16384;
-        k_probe<MODE><<<(unsigned)g2, kBlock, 0, s>>>(D, S, F, G, prefix, e_begin, e_end, item_begin, n_items,
-                                                     words, acc);
-        HC_HIP(hipGetLastError());
-        return;
-    }
-    const uint64_t n_chunks = (n_items + kChunk - 1) / kChunk;
-    DevBuf<int64_t> ce(A, (size_t)n_chunks + 1);
-    DevBuf<unsigned long long> q(A, kXcd);
-    HC_HIP(hipMemsetAsync(q.p, 0, sizeof(unsigned long long) * kXcd, s));
-    {
-        int64_t g = (int64_t)((n_chunks + kBlock - 1) / kBlock);
-        if (g < 1) g = 1;
-        if (g > 16384) g = 16384;
-        k_chunk_entries<<<(unsigned)g, kBlock, 0, s>>>(prefix, e_begin, e_end, item_begin, n_chunks, ce.p);
-        HC_HIP(hipGetLastError());
-    }
-    // persistent grid: a multiple of 8 workgroups (every XCD queue has consumers)
-    uint64_t blocks = (n_chunks + kWaves - 1) / kWaves;
-    if (blocks > kPersistBlocks) blocks = kPersistBlocks;
-    blocks = ((blocks + kXcd - 1) / kXcd) * kXcd;
-#define HC_PROBE2(N)                                                                                          \
-    k_probe2<MODE, N><<<(unsigned)blocks, kBlock, 0, s>>>(D, S, F, G, prefix, e_begin, e_end, item_begin,     \
-                                                          n_items, ce.p, q.p, n_chunks, words, acc)
-    switch (S.n_ops) {
-        case 1: HC_PROBE2(1); break;
-        case 2: HC_PROBE2(2); break;
-        case 3: HC_PROBE2(3); break;
-        default: HC_PROBE2(4); break;
-    }
-#undef HC_PROBE2
-    HC_HIP(hipGetLastError());
-}
-
-struct MatOut {
-    int32_t* F;            // EXPAND
-    uint32_t* tval;        // TMP
-    int32_t* tsrc[kMaxOps];
-    void* rows;            // EMIT
-    int64_t row_base, row_cap;
-};
-
-template <int MAT>
 __global__ __launch_bounds__(kBlock) void k_materialize(KData D, KStep S, const int32_t* __restrict__ F, Seg G,
                                                         const uint64_t* __restrict__ prefix, int64_t e_begin,
                                                         int64_t e_end, uint64_t item_begin, uint64_t n_items,
@@ -629,33 +634,68 @@ __global__ __launch_bounds__(kBlock) void k_materialize(KData D, KStep S, const 
         Probe P;
         probe_item(D, S, G, prefix, find_entry(prefix, e_lo, e_hi + 1, g), g, P);
         const int64_t rank = (int64_t)(wprefix[w] + (uint64_t)__popcll(bal & lanemask_lt()));
-        const int32_t* ent = F + P.e * S.W_in;
-        if (MAT == MAT_EXPAND) {
-            int32_t* o = out.F + rank * S.W_out;
-            for (int c = 0; c < S.n_copy; ++c) o[S.copy_to[c]] = ent[S.copy_from[c]];
-            o[S.val_word] = (int32_t)P.a;
-            for (int t = 0; t < S.n_new; ++t) {
-                const int op = S.new_op[t];
-                const int64_t p = P.pos[op];
-                o[S.new_word[t]] = S.ops[op].kind == OP_TMP ? D.tmp_src[S.ops[op].group][S.new_src[t]][p] : (int32_t)p;
-            }
-            for (int z = 0; z < S.n_zero; ++z) o[S.zero_word[z]] = 0;
-        } else if (MAT == MAT_TMP) {
-            out.tval[rank] = P.a;
-            for (int t = 0; t < S.n_src; ++t) out.tsrc[t][rank] = (int32_t)P.pos[S.src_op[t]];
-        } else {
-            const int64_t row = out.row_base + rank;
-            if (row < out.row_cap) {
-                for (int v = 0; v < S.n_vars; ++v) {
-                    const int hw = S.head_word[v];
-                    const uint32_t key = hw < 0 ? P.a : (uint32_t)ent[hw];
-                    const uint32_t raw = unmix_key(key, D.mix);
-                    if (D.dtype64) ((int64_t*)out.rows)[row * S.n_vars + v] = (int64_t)raw;
-                    else ((int32_t*)out.rows)[row * S.n_vars + v] = (int32_t)raw;
-                }
-            }
-        }
+        write_item(MODE, D, S, F + P.e * S.W_in, P.a, P.pos, rank, out);
     }
+}
+
+__global__ void k_chunk_entries(const uint64_t* __restrict__ prefix, int64_t e_begin, int64_t e_end,
+                                uint64_t item_begin, uint64_t n_chunks, int64_t* __restrict__ out) {
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_chunks;
+         t += (uint64_t)gridDim.x * blockDim.x)
+        out[t] = find_entry(prefix, e_begin, e_end, item_begin + t * kChunk);
+}
+
+template <int MODE>
+static void launch_probe(const Alloc& A, const KData& D, const KStep& S, const int32_t* F, const Seg& G,
+                         const uint64_t* prefix, int64_t e_begin, int64_t e_end, uint64_t item_begin,
+                         uint64_t n_items, uint64_t* words, unsigned long long* acc, hipStream_t s,
+                         const uint64_t* wprefix = nullptr, MatOut out = MatOut{}) {
+    if (S.n_ops > 4) {
+        if (MODE >= M_EXPAND) {
+            const int64_t nw = (int64_t)((n_items + 63) / 64);
+            int64_t g2 = (nw + kWaves - 1) / kWaves;
+            if (g2 < 1) g2 = 1;
+            if (g2 > 16384) g2 = 16384;
+            k_materialize<MODE><<<(unsigned)g2, kBlock, 0, s>>>(D, S, F, G, prefix, e_begin, e_end, item_begin,
+                                                                n_items, words, wprefix, out);
+            HC_HIP(hipGetLastError());
+            return;
+        }
+        const int64_t nw = (int64_t)((n_items + 63) / 64);
+        int64_t g2 = (nw + kWaves - 1) / kWaves;
+        if (g2 < 1) g2 = 1;
+        if (g2 > 16384) g2 = 16384;
+        k_probe<MODE < M_EXPAND ? MODE : M_BITMAP><<<(unsigned)g2, kBlock, 0, s>>>(
+            D, S, F, G, prefix, e_begin, e_end, item_begin, n_items, words, acc);
+        HC_HIP(hipGetLastError());
+        return;
+    }
+    const uint64_t n_chunks = (n_items + kChunk - 1) / kChunk;
+    DevBuf<int64_t> ce(A, (size_t)n_chunks + 1);
+    DevBuf<unsigned long long> q(A, kXcd);
+    HC_HIP(hipMemsetAsync(q.p, 0, sizeof(unsigned long long) * kXcd, s));
+    {
+        int64_t g = (int64_t)((n_chunks + kBlock - 1) / kBlock);
+        if (g < 1) g = 1;
+        if (g > 16384) g = 16384;
+        k_chunk_entries<<<(unsigned)g, kBlock, 0, s>>>(prefix, e_begin, e_end, item_begin, n_chunks, ce.p);
+        HC_HIP(hipGetLastError());
+    }
+    // persistent grid: a multiple of 8 workgroups (every XCD queue has consumers)
+    uint64_t blocks = (n_chunks + kWaves - 1) / kWaves;
+    if (blocks > kPersistBlocks) blocks = kPersistBlocks;
+    blocks = ((blocks + kXcd - 1) / kXcd) * kXcd;
+#define HC_PROBE2(N)                                                                                          \
+    k_probe2<MODE, N><<<(unsigned)blocks, kBlock, 0, s>>>(D, S, F, G, prefix, e_begin, e_end, item_begin,     \
+                                                          n_items, ce.p, q.p, n_chunks, words, acc, wprefix, out)
+    switch (S.n_ops) {
+        case 1: HC_PROBE2(1); break;
+        case 2: HC_PROBE2(2); break;
+        case 3: HC_PROBE2(3); break;
+        default: HC_PROBE2(4); break;
+    }
+#undef HC_PROBE2
+    HC_HIP(hipGetLastError());
 }
 
 // (offset, length) of every entry's temporary result, from the match words.
@@ -974,9 +1014,8 @@ void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
                 MatOut mo{};
                 mo.tval = tmp_val[g].p;
                 for (int u = 0; u < S.n_src; ++u) mo.tsrc[u] = tmp_src[g][u].p;
-                k_materialize<MAT_TMP><<<grid_waves(nw), kBlock, 0, s>>>(D, S, F, gb[t].G, gb[t].prefix.p, ea, eb,
-                                                                          pr[0], ni, words.p, wpre.p, mo);
-                HC_HIP(hipGetLastError());
+                launch_probe<M_TMPW>(A, D, S, F, gb[t].G, gb[t].prefix.p, ea, eb, pr[0], ni, words.p, nullptr, s,
+                                     wpre.p, mo);
             }
             k_tmp_refs<<<grid_for(eb - ea), kBlock, 0, s>>>(Fmut, lay[i].W, lay[i].tmp_word[g], gb[t].prefix.p, ea,
                                                             eb, pr[0], words.p, wpre.p, 0);
@@ -1019,10 +1058,8 @@ void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
                         mo.rows = out_rows;
                         mo.row_base = out_count;
                         mo.row_cap = out_cap;
-                        const int64_t nw = (int64_t)((ni + 63) / 64);
-                        k_materialize<MAT_EMIT><<<grid_waves(nw), kBlock, 0, s>>>(D, S, F, B.G, prefix_abs, ea, eb,
-                                                                                   ib, ni, words.p, wpre.p, mo);
-                        HC_HIP(hipGetLastError());
+                        launch_probe<M_EMIT>(A, D, S, F, B.G, prefix_abs, ea, eb, ib, ni, words.p, nullptr, s,
+                                             wpre.p, mo);
                     }
                     out_count += (int64_t)got;
                     ib += ni;
@@ -1048,10 +1085,8 @@ void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
                     DevBuf<int32_t> Fn(A, (size_t)got * (size_t)lay[i + 1].W);
                     MatOut mo{};
                     mo.F = Fn.p;
-                    const int64_t nw = (int64_t)((ni + 63) / 64);
-                    k_materialize<MAT_EXPAND><<<grid_waves(nw), kBlock, 0, s>>>(D, S, F, B.G, prefix_abs, ca, cb,
-                                                                                 pr[0], ni, words.p, wpre.p, mo);
-                    HC_HIP(hipGetLastError());
+                    launch_probe<M_EXPAND>(A, D, S, F, B.G, prefix_abs, ca, cb, pr[0], ni, words.p, nullptr, s,
+                                           wpre.p, mo);
                     words.reset();
                     wpre.reset();
                     run_level(i + 1, Fn.p, Fn.p, (int64_t)got);
@@ -1125,8 +1160,8 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
     R.digest = digest != nullptr;
     R.out_rows = out;
     R.out_cap = capacity;
-    R.cap_entries = (int64_t)1 << 26;
-    R.tmp_cap = (int64_t)1 << 26;
+    R.cap_entries = (int64_t)1 << 27;
+    R.tmp_cap = (int64_t)1 << 27;
     R.acc = DevBuf<unsigned long long>(R.A, 4);
     R.split = DevBuf<int64_t>(R.A, 2);
     HC_HIP(hipMemsetAsync(R.acc.p, 0, sizeof(unsigned long long) * 4, R.s));
