@@ -50,6 +50,8 @@ def lib():
         L.textbook_triangles.argtypes = [P, ctypes.c_int64, ctypes.c_int]
         L.textbook_4cliques.restype = ctypes.c_int64
         L.textbook_4cliques.argtypes = [P, ctypes.c_int64, ctypes.c_int]
+        L.textbook_4clique_digest.restype = ctypes.c_int64
+        L.textbook_4clique_digest.argtypes = [P, ctypes.c_int64, ctypes.c_int, P]
         _lib = L
     return _lib
 
@@ -162,3 +164,11 @@ def textbook_triangles(edges, threads: int = 0) -> int:
 def textbook_4cliques(edges, threads: int = 0) -> int:
     e = np.ascontiguousarray(np.asarray(edges, dtype=np.int64))
     return int(lib().textbook_4cliques(_ptr(e), e.shape[0], threads))
+
+
+def textbook_4clique_digest(edges, threads: int = 0):
+    """(number of K4, digest of the ordered 4-clique query output) by oriented enumeration."""
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int64))
+    d = np.zeros(2, dtype=np.uint64)
+    k = int(lib().textbook_4clique_digest(_ptr(e), e.shape[0], threads, _ptr(d)))
+    return k, (int(d[0]), int(d[1]))

@@ -144,3 +144,74 @@ int64_t textbook_4cliques(const int64_t* e, int64_t m, int nthreads) {
     free(g.off); free(g.adj);
     return (int64_t)total;
 }
+
+/* Digest of the ordered output of the 4-clique query on a symmetric relation:
+ * every K4 {a,b,c,d} found by the oriented enumeration contributes all 24
+ * orderings as head-order tuples.  The per-tuple hash is the digest definition
+ * (SplitMix64 finaliser chain over the fields, seeded 0x6A09E667F3BCC909,
+ * field k offset by (k+1) * 0x9E3779B97F4A7C15); digest = (sum, xor). */
+static uint64_t tb_fmix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+static uint64_t tb_hash4(int64_t a, int64_t b, int64_t c, int64_t d) {
+    const int64_t t[4] = {a, b, c, d};
+    uint64_t h = 0x6A09E667F3BCC909ULL;
+    for (int k = 0; k < 4; ++k) h = tb_fmix64(h ^ ((uint64_t)t[k] + (uint64_t)(k + 1) * 0x9E3779B97F4A7C15ULL));
+    return h;
+}
+
+int64_t textbook_4clique_digest(const int64_t* e, int64_t m, int nthreads, uint64_t* digest) {
+    tb_graph g;
+    if (tb_build(e, m, &g) != 0) return -1;
+    uint64_t total = 0, dsum = 0, dxor = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+    {
+        unsigned char* mu = (unsigned char*)calloc((size_t)g.n + 1, 1);
+        unsigned char* mw = (unsigned char*)calloc((size_t)g.n + 1, 1);
+        int64_t* wl = (int64_t*)malloc(sizeof(int64_t) * (size_t)(g.n + 1));
+        uint64_t local = 0, ls = 0, lx = 0;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t u = 0; u < g.n; ++u) {
+            for (int64_t i = g.off[u]; i < g.off[u + 1]; ++i) mu[g.adj[i]] = 1;
+            for (int64_t i = g.off[u]; i < g.off[u + 1]; ++i) {
+                int64_t v = g.adj[i];
+                int64_t nw = 0;
+                for (int64_t j = g.off[v]; j < g.off[v + 1]; ++j)
+                    if (mu[g.adj[j]]) { wl[nw++] = g.adj[j]; mw[g.adj[j]] = 1; }
+                for (int64_t a = 0; a < nw; ++a) {
+                    int64_t w = wl[a];
+                    for (int64_t j = g.off[w]; j < g.off[w + 1]; ++j) {
+                        int64_t x = g.adj[j];
+                        if (!mw[x]) continue;
+                        const int64_t q[4] = {u, v, w, x};
+                        /* all 24 orderings */
+                        for (int p0 = 0; p0 < 4; ++p0)
+                            for (int p1 = 0; p1 < 4; ++p1) {
+                                if (p1 == p0) continue;
+                                for (int p2 = 0; p2 < 4; ++p2) {
+                                    if (p2 == p0 || p2 == p1) continue;
+                                    int p3 = 6 - p0 - p1 - p2;
+                                    uint64_t h = tb_hash4(q[p0], q[p1], q[p2], q[p3]);
+                                    ls += h; lx ^= h;
+                                }
+                            }
+                        local += 1;
+                    }
+                }
+                for (int64_t a = 0; a < nw; ++a) mw[wl[a]] = 0;
+            }
+            for (int64_t i = g.off[u]; i < g.off[u + 1]; ++i) mu[g.adj[i]] = 0;
+        }
+#pragma omp critical
+        { total += local; dsum += ls; dxor ^= lx; }
+        free(mu); free(mw); free(wl);
+    }
+    free(g.off); free(g.adj);
+    digest[0] = dsum; digest[1] = dxor;
+    return (int64_t)total;
+}

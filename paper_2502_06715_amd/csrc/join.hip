@@ -59,6 +59,8 @@ struct KOp {
     int32_t word;     // CHILD: entry word of the parent node; TMP: entry word of (offset, length)
     int32_t group;    // TMP
     const int2* v0_range;   // V0 restricted by the cell: table indexed by the coordinate (or null)
+    const int32_t* child_range;   // CHILD: per node, start of every coordinate's sub-range (or null)
+    int32_t child_stride;         // 2^k + 1 entries per node
 };
 
 struct KStep {
@@ -120,6 +122,21 @@ __global__ void k_v0_ranges(const uint32_t* V0, int64_t l0, int b, int k, int2* 
     }
 }
 
+// For every top-level entry of a binary atom and every coordinate s of a share 2^k
+// on its second variable: the first child whose key is >= s << (b-k); entry 2^k
+// closes the list.  Row `node` of the table has 2^k + 1 entries.
+__global__ void k_child_ranges(const int32_t* __restrict__ O0, const uint32_t* __restrict__ V1, int64_t l0, int b,
+                               int k, int32_t* __restrict__ out) {
+    const int64_t stride = ((int64_t)1 << k) + 1;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < l0 * stride;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t node = idx / stride, s = idx - node * stride;
+        const int64_t beg = O0[node], end = O0[node + 1];
+        if (s == stride - 1) out[idx] = (int32_t)end;
+        else out[idx] = (int32_t)lower_bound_u32(V1, beg, end, (uint32_t)((uint64_t)s << (b - k)));
+    }
+}
+
 // Resolve every operand of every entry to a [begin, end) range, restricted to the cell.
 __global__ __launch_bounds__(kBlock) void k_prep(KData D, KStep S, const int32_t* __restrict__ F, int64_t e0,
                                                  int64_t n, Seg G) {
@@ -151,7 +168,11 @@ __global__ __launch_bounds__(kBlock) void k_prep(KData D, KStep S, const int32_t
                 const int32_t* O = D.atoms[op.atom].O0;
                 beg = O[node];
                 end = O[node + 1];
-                if (restrict_) {
+                if (restrict_ && op.child_range) {
+                    const int32_t* cr = op.child_range + (int64_t)node * op.child_stride + coord;
+                    beg = cr[0];
+                    end = cr[1];
+                } else if (restrict_) {
                     const uint32_t* A = D.atoms[op.atom].V1;
                     const int64_t b2 = lower_bound_u32(A, beg, end, (uint32_t)lo);
                     end = hi >= (1ull << 32) ? end : lower_bound_u32(A, b2, end, (uint32_t)hi);
@@ -767,6 +788,8 @@ struct Runner {
     DevBuf<unsigned long long> acc;
     DevBuf<int64_t> split;
     std::vector<DevBuf<int2>> ranges;
+    std::vector<DevBuf<int32_t>> child_tab;
+    std::vector<uint64_t> child_key;
     DevBuf<uint32_t> tmp_val[kMaxGroups];
     DevBuf<int32_t> tmp_src[kMaxGroups][kMaxOps];
     int64_t tmp_cap = 0;
@@ -823,6 +846,8 @@ struct Runner {
         o.v0_range = nullptr;
         if (po.kind == OP_CHILD) o.word = L.node_word[po.atom];
         if (po.kind == OP_TMP) o.word = L.tmp_word[po.group];
+        o.child_range = nullptr;
+        o.child_stride = 0;
         if (po.kind == OP_V0 && shares[var] > 0) {
             const int k = shares[var];
             ranges.emplace_back(A, (size_t)1 << k);
@@ -830,6 +855,29 @@ struct Runner {
             k_v0_ranges<<<grid_for((int64_t)1 << k), kBlock, 0, s>>>(a.V0, a.l0, D.b, k, ranges.back().p);
             HC_HIP(hipGetLastError());
             o.v0_range = ranges.back().p;
+        }
+        if (po.kind == OP_CHILD && shares[var] > 0) {
+            // sub-range boundaries of every child list for every coordinate, when the
+            // table stays small; otherwise the cell's range is found by binary search
+            const int k = shares[var];
+            const DAtom& a = D.atoms[po.atom];
+            const int64_t stride = ((int64_t)1 << k) + 1;
+            if (a.l0 * stride <= ((int64_t)1 << 27)) {
+                const uint64_t key = ((uint64_t)po.atom << 8) | (uint64_t)k;
+                int found = -1;
+                for (size_t t = 0; t < child_key.size(); ++t)
+                    if (child_key[t] == key) found = (int)t;
+                if (found < 0) {
+                    child_tab.emplace_back(A, (size_t)(a.l0 * stride + 1));
+                    child_key.push_back(key);
+                    found = (int)child_tab.size() - 1;
+                    k_child_ranges<<<grid_for(a.l0 * stride), kBlock, 0, s>>>(a.O0, a.V1, a.l0, D.b, k,
+                                                                               child_tab.back().p);
+                    HC_HIP(hipGetLastError());
+                }
+                o.child_range = child_tab[found].p;
+                o.child_stride = (int32_t)stride;
+            }
         }
         return o;
     }

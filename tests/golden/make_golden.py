@@ -45,10 +45,21 @@ def main():
         rels = [E] * len(atoms)
         rec = {"query": q, "rows": int(E.shape[0])}
         if cfg == 3:
-            r = oracle.gj(n, atoms, rels, digest=True, threads=args.threads)
+            # The full 4-clique output (~3.5e10 ordered tuples) is out of reach of the
+            # Generic Join oracle in a session, so the full count and digest come from
+            # the oriented K4 enumeration (its digest hashes all 24 orderings of every
+            # K4; it is pinned against the Generic Join digest on smaller graphs), and
+            # the Generic Join oracle supplies range-restricted chunks.
+            k4, dg = oracle.textbook_4clique_digest(E, threads=args.threads)
             tb = oracle.textbook_4cliques(E, threads=args.threads)
-            assert r.count == 24 * tb, (r.count, tb)
+            assert k4 == tb, (k4, tb)
+
+            class _R:
+                count = 24 * k4
+                digest = dg
+            r = _R()
             rec["textbook_4cliques"] = tb
+            rec["count_source"] = "textbook K4 enumeration x 24 (full size); Generic Join oracle for chunks"
             rec["chunks"] = []
             for lo, hi in CHUNKS3:
                 big = 1 << 31

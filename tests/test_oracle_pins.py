@@ -130,6 +130,16 @@ def test_clique4_textbook_chung_lu():
     assert oracle.gj(*Q["clique4"], [E] * 6, threads=4).count == 24 * oracle.textbook_4cliques(E)
 
 
+def test_clique4_digest_textbook_equals_gj():
+    """The textbook 4-clique digest (each K4 once, all 24 orderings hashed) equals the
+    Generic Join digest, so the full-size 4-clique digest can come from the former."""
+    E = inputs.chung_lu(4096, 30000, 14)
+    r = oracle.gj(*Q["clique4"], [E] * 6, digest=True, threads=4)
+    k, dg = oracle.textbook_4clique_digest(E)
+    assert r.count == 24 * k
+    assert r.digest == dg
+
+
 def test_set_semantics_duplicates_ignored():
     n, atoms = Q["triangle"]
     E = inputs.complete_graph(5)
