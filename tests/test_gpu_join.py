@@ -193,3 +193,48 @@ def test_config2_triangle_count(ctx):
     log("config2 order=%s shares=%s" % (order, shares))
     assert hc.join_count(ctx, q, [c] * 3, order, shares) == GOLD["2"]["count"]
     assert hc.join_count(ctx, q, [c] * 3, [0, 1, 2], [0, 0, 0]) == GOLD["2"]["count"]
+
+
+def _config3(ctx):
+    E = config_graph(3)
+    n, atoms = inputs.QUERIES["clique4"]
+    c = _coco(ctx, E, b=18, symmetric=True)
+    return E, n, atoms, c
+
+
+def test_config3_clique4_count_and_digest(ctx):
+    """Full-size 4-clique workload: count and output digest against the oracle's values
+    (oriented K4 enumeration; Generic Join digest pinned to it on smaller graphs)."""
+    E, n, atoms, c = _config3(ctx)
+    q = hc.Query(n, atoms)
+    order, shares = hc.compute_shares(ctx, q, [c] * 6, 12)
+    log("config3 order=%s shares=%s" % (order, shares))
+    cnt, dg = hc.join_count(ctx, q, [c] * 6, order, shares, digest=True)
+    g = GOLD["3"]
+    assert cnt == g["count"]
+    assert dg == (int(g["digest"][0]), int(g["digest"][1]))
+    assert hc.join_count(ctx, q, [c] * 6, order, shares, flags=hc.HC_NO_REWRITE) == g["count"]
+
+
+def test_config3_chunked_emit(ctx):
+    """Range-restricted chunks of the materialised output (predicate on variable 0)."""
+    E, n, atoms, c = _config3(ctx)
+    for ch in GOLD["3"]["chunks"]:
+        lo = [ch["lo"], 0, 0, 0]
+        hi = [ch["hi"], 1 << 31, 1 << 31, 1 << 31]
+        q = hc.Query(n, atoms, lo, hi)
+        rows, n_out = hc.join_emit(ctx, q, [c] * 6, [0, 1, 2, 3], [3, 4, 3, 2], capacity=ch["count"] + 16)
+        assert n_out == ch["count"]
+        r = rows.cpu().numpy().astype(np.int64)
+        assert oracle.digest_rows(r) == (int(ch["digest"][0]), int(ch["digest"][1]))
+        assert np.all((r[:, 0] >= ch["lo"]) & (r[:, 0] < ch["hi"]))
+
+
+def test_config3_emit_capacity_2_28(ctx):
+    """Materialising the full output into 2^28 rows overflows with the exact total."""
+    E, n, atoms, c = _config3(ctx)
+    q = hc.Query(n, atoms)
+    with pytest.raises(hc.HCError) as ei:
+        hc.join_emit(ctx, q, [c] * 6, [0, 1, 2, 3], [6, 6, 0, 0], capacity=1 << 28)
+    assert ei.value.status == hc.HC_ERR_OVERFLOW
+    assert ei.value.n_out == GOLD["3"]["count"]
