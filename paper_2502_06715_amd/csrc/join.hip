@@ -418,6 +418,36 @@ __device__ inline void digest_add(const KData& D, const KStep& S, const int32_t*
     dxor ^= h;
 }
 
+__device__ inline int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline uint64_t uni64(uint64_t v) {
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(v >> 32)) << 32) |
+           (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)v);
+}
+
+// First p in [c, end) with B[p] >= v; exponential search from c (wave-uniform).
+__device__ inline int32_t gallop32(const uint32_t* __restrict__ B, int32_t c, int32_t end, uint32_t v) {
+    if (c >= end || B[c] >= v) return c;
+    int32_t lo = c, step = 1;   // B[lo] < v
+    while (lo + step < end && B[lo + step] < v) {
+        lo += step;
+        step <<= 1;
+    }
+    int32_t l = lo + 1, h = lo + step < end ? lo + step : end;
+    while (l < h) {
+        const int32_t mid = (l + h) >> 1;
+        if (B[mid] < v) l = mid + 1; else h = mid;
+    }
+    return l;
+}
+
+__device__ inline int32_t lower_bound32(const uint32_t* __restrict__ B, int32_t l, int32_t h, uint32_t v) {
+    while (l < h) {
+        const int32_t mid = (l + h) >> 1;
+        if (B[mid] < v) l = mid + 1; else h = mid;
+    }
+    return l;
+}
+
 template <int MODE, int NOPS>
 __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32_t* __restrict__ F, Seg G,
                                                    const uint64_t* __restrict__ prefix, int64_t e_begin,
@@ -433,6 +463,7 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
     const uint32_t* arr[NOPS];
 #pragma unroll
     for (int o = 0; o < NOPS; ++o) arr[o] = op_array(D, S.ops[o]);
+    const int64_t stride = G.stride;
     uint64_t cnt = 0, dsum = 0, dxor = 0;
     // Work queue per XCD: workgroups are dispatched to the 8 XCDs round-robin, so
     // blockIdx % 8 names the XCD; each XCD sweeps its own contiguous eighth of the
@@ -444,36 +475,33 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
     for (;;) {
         unsigned long long t = 0;
         if (lane == 0) t = atomicAdd(&queue[xcd], 1ull);
-        const uint64_t c = c_lo + (((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(t >> 32)) << 32) |
-                                   (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)t));
+        const uint64_t c = c_lo + uni64(t);
         if (c >= c_hi) break;
         const uint64_t r_begin = c * kChunk;
         const uint64_t r_end = r_begin + kChunk < n_items ? r_begin + kChunk : n_items;
         // current entry and its wave-uniform description
-        int64_t e = chunk_entry[c];
-        uint64_t pe0 = prefix[e], pe1 = prefix[e + 1];
-        int it = G.iter[e];
-        int64_t beg[NOPS], end[NOPS], cur[NOPS];
+        int64_t e = (int64_t)uni64((uint64_t)chunk_entry[c]);
+        uint64_t pe0, pe1;
+        int it;
+        int32_t beg[NOPS], end[NOPS], cur[NOPS];
+        auto load_entry = [&](int64_t ee) {
+            pe0 = uni64(prefix[ee]);
+            pe1 = uni64(prefix[ee + 1]);
+            it = uni(G.iter[ee]);
 #pragma unroll
-        for (int o = 0; o < NOPS; ++o) {
-            beg[o] = G.seg[(2 * o) * G.stride + e];
-            end[o] = G.seg[(2 * o + 1) * G.stride + e];
-            cur[o] = beg[o];
-        }
+            for (int o = 0; o < NOPS; ++o) {
+                beg[o] = uni(G.seg[(2 * o) * stride + ee]);
+                end[o] = uni(G.seg[(2 * o + 1) * stride + ee]);
+                cur[o] = beg[o];
+            }
+        };
+        load_entry(e);
         uint64_t rc = r_begin;
         while (rc < r_end) {
             const uint64_t g = item_begin + rc;
             if (pe1 <= g) {   // move to the entry holding g
-                e = advance_entry(prefix, e + 1, e_end, g);
-                pe0 = prefix[e];
-                pe1 = prefix[e + 1];
-                it = G.iter[e];
-#pragma unroll
-                for (int o = 0; o < NOPS; ++o) {
-                    beg[o] = G.seg[(2 * o) * G.stride + e];
-                    end[o] = G.seg[(2 * o + 1) * G.stride + e];
-                    cur[o] = beg[o];
-                }
+                e = (int64_t)uni64((uint64_t)advance_entry(prefix, e + 1, e_end, g));
+                load_entry(e);
             }
             const uint64_t left_wave = r_end - rc;
             const uint64_t left_entry = pe1 - g;
@@ -484,7 +512,7 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                 uint64_t n_sc = left_entry >= left_wave ? left_wave : (left_entry & ~63ull);
                 if (n_sc > 64ull * kSub) n_sc = 64ull * kSub;
                 const int nsc = (int)n_sc;
-                const int64_t off0 = (int64_t)(g - pe0);
+                const int32_t off0 = (int32_t)(g - pe0);
                 uint32_t a[kSub];
                 bool v[kSub], f[kSub];
                 int32_t pos[NOPS][kSub];   // absolute positions (materialising modes)
@@ -495,10 +523,10 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                     f[k] = v[k];
                     a[k] = 0;
 #pragma unroll
-                    for (int o = 0; o < NOPS; ++o) pos[o][k] = (int32_t)(beg[o] + off0 + j);
-#pragma unroll
-                    for (int o = 0; o < NOPS; ++o)
+                    for (int o = 0; o < NOPS; ++o) {
+                        pos[o][k] = beg[o] + off0 + j;
                         if (o == it && v[k]) a[k] = arr[o][beg[o] + off0 + j];
+                    }
                 }
                 const uint32_t a_first = __shfl(a[0], 0, 64);
                 const int last = nsc - 1;
@@ -506,48 +534,55 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                 for (int o = 0; o < NOPS; ++o) {
                     if (o == it) continue;
                     const uint32_t* B = arr[o];
-                    const int64_t lo = gallop_lb(B, cur[o], end[o], a_first);
-                    const int64_t avail = end[o] - lo;
+                    const int32_t lo = uni(gallop32(B, cur[o], end[o], a_first));
+                    const int32_t avail = end[o] - lo;
                     // window sized by this step's share of the entry's remaining elements
                     uint64_t est = (uint64_t)nsc * (uint64_t)avail / (pe1 - g);
                     est += (est >> 2) + 64;
-                    int64_t lw = avail < (int64_t)kWin ? avail : (int64_t)kWin;
-                    if ((int64_t)est < lw) lw = (int64_t)est;
-                    const int len = (int)lw;
-                    for (int k = lane; k < len; k += 64) win[k] = B[lo + k];
+                    int32_t len = avail < kWin ? avail : kWin;
+                    if ((int64_t)est < len) len = (int32_t)est;
+                    len = uni(len);
+                    // power-of-two window, padded with the largest key (never below a value)
+                    int32_t p2 = 1;
+                    while (p2 < len) p2 <<= 1;
+                    for (int k = lane; k < p2; k += 64) win[k] = k < len ? B[lo + k] : 0xFFFFFFFFu;
                     wave_sync();
                     const uint32_t wmax = len > 0 ? win[len - 1] : 0u;
-                    int rel[kSub];
+                    int32_t p[kSub];
+#pragma unroll
+                    for (int k = 0; k < kSub; ++k) p[k] = 0;
+                    // branch-free lower bound of every value in the window (all kSub searches
+                    // advance together)
+                    for (int32_t step = p2 >> 1; step > 0; step >>= 1) {
+#pragma unroll
+                        for (int k = 0; k < kSub; ++k)
+                            if (win[p[k] + step - 1] < a[k]) p[k] += step;
+                    }
 #pragma unroll
                     for (int k = 0; k < kSub; ++k) {
-                        rel[k] = 0;
+                        if (len > 0 && win[p[k]] < a[k]) p[k] += 1;
                         if (v[k]) {
                             bool fo;
                             if (len > 0 && a[k] <= wmax) {
-                                const int p = lds_lower_bound(win, len, a[k]);
-                                rel[k] = p;
-                                fo = win[p] == a[k];
-                            } else {
-                                const int64_t p = lower_bound_u32(B, lo + len, end[o], a[k]);
-                                rel[k] = (int)(p - lo);
-                                fo = p < end[o] && B[p] == a[k];
+                                fo = win[p[k]] == a[k];
+                            } else {   // beyond the window: search the rest in place
+                                const int32_t q = lower_bound32(B, lo + len, end[o], a[k]);
+                                p[k] = q - lo;
+                                fo = q < end[o] && B[q] == a[k];
                             }
                             f[k] = f[k] && fo;
                         }
+                        if (kMat) pos[o][k] = lo + p[k];
                     }
                     wave_sync();
                     // cursor: lower bound of the step's last element
-                    int rl = 0;
+                    int32_t rl = 0;
 #pragma unroll
                     for (int k = 0; k < kSub; ++k) {
-                        const int t = __shfl(rel[k], last & 63, 64);
-                        if (k == (last >> 6)) rl = t;
+                        const int32_t tt = __shfl(p[k], last & 63, 64);
+                        if (k == (last >> 6)) rl = tt;
                     }
-                    cur[o] = lo + rl;
-                    if (kMat) {
-#pragma unroll
-                        for (int k = 0; k < kSub; ++k) pos[o][k] = (int32_t)(lo + rel[k]);
-                    }
+                    cur[o] = uni(lo + rl);
                 }
 #pragma unroll
                 for (int k = 0; k < kSub; ++k) {
@@ -574,27 +609,50 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                 }
                 rc += n_sc;
             } else {
-                // ---- mixed chunk: 64 elements spanning several entries
+                // ---- mixed chunk: 64 elements spanning several entries, one search per lane
                 const int nv = (int)chunk;
                 const bool valid = lane < nv;
                 const uint64_t g_last = g + chunk - 1;
-                const int64_t e_hi = advance_entry(prefix, e, e_end, g_last);
+                const int64_t e_hi = (int64_t)uni64((uint64_t)advance_entry(prefix, e, e_end, g_last));
                 bool found = false;
                 uint32_t av = 0;
                 int64_t my_e = e;
-                Probe P;
+                int64_t pp[NOPS];
                 if (valid) {
                     const uint64_t gl = g + lane;
                     my_e = find_entry(prefix, e, e_hi + 1, gl);
-                    probe_item(D, S, G, prefix, my_e, gl, P);
-                    found = P.found;
-                    av = P.a;
+                    const int il = G.iter[my_e];
+                    int32_t bl[NOPS], el[NOPS];
+#pragma unroll
+                    for (int o = 0; o < NOPS; ++o) {
+                        bl[o] = G.seg[(2 * o) * stride + my_e];
+                        el[o] = G.seg[(2 * o + 1) * stride + my_e];
+                    }
+                    const int32_t offl = (int32_t)(gl - prefix[my_e]);
+#pragma unroll
+                    for (int o = 0; o < NOPS; ++o)
+                        if (o == il) {
+                            pp[o] = bl[o] + offl;
+                            av = arr[o][bl[o] + offl];
+                        }
+                    found = true;
+#pragma unroll
+                    for (int o = 0; o < NOPS; ++o) {
+                        if (o == il || !found) continue;
+                        const int32_t q = lower_bound32(arr[o], bl[o], el[o], av);
+                        pp[o] = q;
+                        found = q < el[o] && arr[o][q] == av;
+                    }
+                    if (found && S.has_pred) {
+                        const int64_t raw = (int64_t)unmix_key(av, D.mix);
+                        found = raw >= S.pred_lo && raw < S.pred_hi;
+                    }
                 }
                 const uint64_t bal = __ballot(found);
                 if (kMat) {
                     if (found) {
                         const int64_t rank = (int64_t)(wprefix[rc >> 6] + (uint64_t)__popcll(bal & lanemask_lt()));
-                        write_item(MODE, D, S, F + my_e * S.W_in, av, P.pos, rank, out);
+                        write_item(MODE, D, S, F + my_e * S.W_in, av, pp, rank, out);
                     }
                 } else if (MODE == M_BITMAP) {
                     if (lane == 0) words[rc >> 6] = bal;
@@ -604,15 +662,7 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                 }
                 // continue inside the last entry touched (its cursors restart)
                 e = e_hi;
-                pe0 = prefix[e];
-                pe1 = prefix[e + 1];
-                it = G.iter[e];
-#pragma unroll
-                for (int o = 0; o < NOPS; ++o) {
-                    beg[o] = G.seg[(2 * o) * G.stride + e];
-                    end[o] = G.seg[(2 * o + 1) * G.stride + e];
-                    cur[o] = beg[o];
-                }
+                load_entry(e);
                 rc += chunk;
             }
         }
