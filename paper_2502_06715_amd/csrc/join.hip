@@ -361,6 +361,7 @@ __device__ inline void write_item(int mode, const KData& D, const KStep& S, cons
 // chunk spans several small entries fall back to one search per lane.
 constexpr int kWin = 1024;      // LDS window per wave (elements)
 constexpr int kSub = 4;         // 64-element chunks per cursor step
+constexpr int kTiny = 24;       // counting modes: entries shorter than this take the per-lane path
 constexpr uint64_t kChunk = 2048;       // elements per work-queue chunk
 constexpr int kXcd = 8;                 // XCDs of an MI355X
 constexpr uint64_t kPersistBlocks = 2048;
@@ -457,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                                                    uint64_t* __restrict__ words, unsigned long long* acc,
                                                    const uint64_t* __restrict__ wprefix, MatOut out) {
     constexpr bool kMat = MODE >= M_EXPAND;
-    __shared__ uint32_t win_all[kWaves][kWin];
+    __shared__ __attribute__((aligned(16))) uint32_t win_all[kWaves][kWin];
     const int lane = threadIdx.x & 63;
     uint32_t* win = win_all[threadIdx.x >> 6];
     const uint32_t* arr[NOPS];
@@ -506,10 +507,21 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
             const uint64_t left_wave = r_end - rc;
             const uint64_t left_entry = pe1 - g;
             const uint64_t chunk = left_wave < 64 ? left_wave : 64;
-            if (left_entry >= chunk) {
-                // ---- uniform step: up to kSub*64 elements of entry e; it ends on a
-                // 64-element boundary (match words stay aligned) or at the range end
-                uint64_t n_sc = left_entry >= left_wave ? left_wave : (left_entry & ~63ull);
+            // Modes that write match words keep every step on 64-element boundaries;
+            // counting modes let a step end where its entry ends, so only runs of tiny
+            // entries take the per-lane path.
+            constexpr bool kAligned = !(MODE == M_COUNT || MODE == M_DIGEST);
+            bool uniform_step;
+            uint64_t n_sc;
+            if (kAligned) {
+                uniform_step = left_entry >= chunk;
+                n_sc = left_entry >= left_wave ? left_wave : (left_entry & ~63ull);
+            } else {
+                uniform_step = left_entry >= (uint64_t)kTiny || left_entry >= left_wave;
+                n_sc = left_entry < left_wave ? left_entry : left_wave;
+            }
+            if (uniform_step) {
+                // ---- uniform step: up to kSub*64 elements of entry e
                 if (n_sc > 64ull * kSub) n_sc = 64ull * kSub;
                 const int nsc = (int)n_sc;
                 const int32_t off0 = (int32_t)(g - pe0);
@@ -539,15 +551,38 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                     // window sized by this step's share of the entry's remaining elements
                     uint64_t est = (uint64_t)nsc * (uint64_t)avail / (pe1 - g);
                     est += (est >> 2) + 64;
-                    int32_t len = avail < kWin ? avail : kWin;
+                    int32_t len = avail < kWin - 4 ? avail : kWin - 4;
                     if ((int64_t)est < len) len = (int32_t)est;
                     len = uni(len);
-                    // power-of-two window, padded with the largest key (never below a value)
-                    int32_t p2 = 1;
-                    while (p2 < len) p2 <<= 1;
-                    for (int k = lane; k < p2; k += 64) win[k] = k < len ? B[lo + k] : 0xFFFFFFFFu;
+                    // The window starts at the 16-byte boundary below lo (16-byte loads);
+                    // its first sh slots hold zero so that it stays sorted, and positions
+                    // below sh are never reported.  It is padded to a power of two with
+                    // the largest key, which is never below a searched value.
+                    const int32_t lo_al = lo & ~3;
+                    const int32_t sh = lo - lo_al;
+                    const int32_t len_al = len + sh;
+                    int32_t p2 = 4;
+                    while (p2 < len_al) p2 <<= 1;
+                    for (int q = lane; q < (p2 >> 2); q += 64) {
+                        const int32_t k0 = 4 * q;
+                        uint4 val;
+                        if (k0 + 4 <= len_al) {
+                            val = *reinterpret_cast<const uint4*>(B + lo_al + k0);
+                        } else {
+                            val.x = k0 + 0 < len_al ? B[lo_al + k0 + 0] : 0xFFFFFFFFu;
+                            val.y = k0 + 1 < len_al ? B[lo_al + k0 + 1] : 0xFFFFFFFFu;
+                            val.z = k0 + 2 < len_al ? B[lo_al + k0 + 2] : 0xFFFFFFFFu;
+                            val.w = k0 + 3 < len_al ? B[lo_al + k0 + 3] : 0xFFFFFFFFu;
+                        }
+                        if (k0 == 0) {
+                            if (sh > 0) val.x = 0u;
+                            if (sh > 1) val.y = 0u;
+                            if (sh > 2) val.z = 0u;
+                        }
+                        *reinterpret_cast<uint4*>(win + k0) = val;
+                    }
                     wave_sync();
-                    const uint32_t wmax = len > 0 ? win[len - 1] : 0u;
+                    const uint32_t wmax = len > 0 ? win[len_al - 1] : 0u;
                     int32_t p[kSub];
 #pragma unroll
                     for (int k = 0; k < kSub; ++k) p[k] = 0;
@@ -560,19 +595,20 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                     }
 #pragma unroll
                     for (int k = 0; k < kSub; ++k) {
-                        if (len > 0 && win[p[k]] < a[k]) p[k] += 1;
+                        if (win[p[k]] < a[k]) p[k] += 1;
+                        if (p[k] < sh) p[k] = sh;
                         if (v[k]) {
                             bool fo;
                             if (len > 0 && a[k] <= wmax) {
                                 fo = win[p[k]] == a[k];
                             } else {   // beyond the window: search the rest in place
-                                const int32_t q = lower_bound32(B, lo + len, end[o], a[k]);
-                                p[k] = q - lo;
+                                const int32_t q = lower_bound32(B, lo_al + len_al, end[o], a[k]);
+                                p[k] = q - lo_al;
                                 fo = q < end[o] && B[q] == a[k];
                             }
                             f[k] = f[k] && fo;
                         }
-                        if (kMat) pos[o][k] = lo + p[k];
+                        if (kMat) pos[o][k] = lo_al + p[k];
                     }
                     wave_sync();
                     // cursor: lower bound of the step's last element
@@ -582,7 +618,7 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                         const int32_t tt = __shfl(p[k], last & 63, 64);
                         if (k == (last >> 6)) rl = tt;
                     }
-                    cur[o] = uni(lo + rl);
+                    cur[o] = uni(lo_al + rl);
                 }
 #pragma unroll
                 for (int k = 0; k < kSub; ++k) {
