@@ -120,6 +120,21 @@ hc_status hc_build_coco(hc_ctx* ctx, const void* tuples, int64_t n, int32_t arit
                         uint32_t flags, hc_coco** out);
 void hc_coco_free(hc_coco* coco);
 
+/*
+ * Segmented build, for many independent relations fused into one index (one
+ * query per segment of a batch): ids are seg * 2^mix_bits + x with x < 2^mix_bits
+ * and seg < 2^segment_bits; only the low mix_bits are mixed, so every segment
+ * occupies one contiguous key range.  key_bits = mix_bits + segment_bits <= 32.
+ * A join over segmented CoCos must give the first variable of the order a share
+ * of at least segment_bits (its coordinate names the segment) and no share to
+ * the other variables; every operand then stays inside the segment of its cell,
+ * so one cell never mixes two relations.  Other arguments as hc_build_coco.
+ */
+hc_status hc_build_coco_segmented(hc_ctx* ctx, const void* tuples, int64_t n, int32_t arity,
+                                  hc_dtype dtype, const int32_t* col_order, int32_t mix_bits,
+                                  int32_t segment_bits, uint64_t mix_seed, uint32_t flags,
+                                  hc_coco** out);
+
 /* Statistics of a built CoCo (host struct, filled by hc_coco_get_info). */
 typedef struct {
     int64_t n_input;            /* rows given */
@@ -134,6 +149,8 @@ typedef struct {
     int32_t symmetric;          /* verified symmetric binary relation */
     int32_t dtype;              /* hc_dtype of the input ids (also of emitted rows) */
     int64_t bytes;              /* device bytes held by the index */
+    int32_t mix_bits;           /* low key bits that are mixed (= key_bits unless segmented) */
+    int32_t reserved;
 } hc_coco_info;
 
 hc_status hc_coco_get_info(const hc_coco* coco, hc_coco_info* info);
@@ -206,6 +223,19 @@ hc_status hc_compute_shares_from_info(const hc_query* q, const hc_coco_info* inf
 hc_status hc_join_count(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
                         const int32_t* var_order, const int32_t* log2_shares, uint32_t flags,
                         uint64_t* count_out, uint64_t* digest_out);
+
+/*
+ * Count per HyperCube cell (the output of each of the paper's threads, Section
+ * 5): cell_counts (host, 2^(sum of log2_shares) entries) receives the number of
+ * result tuples of every cell; the cell id packs the coordinates of the
+ * variables in order, the first variable of the order in the lowest bits, each
+ * taking log2_shares[v] bits.  count_out receives the total.  With segmented
+ * CoCos and only the first variable split by exactly segment_bits, cell c is
+ * segment c, i.e. one query of a batch.  Errors as hc_join_count.
+ */
+hc_status hc_join_count_cells(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
+                              const int32_t* var_order, const int32_t* log2_shares, uint32_t flags,
+                              uint64_t* cell_counts, uint64_t* count_out);
 
 /*
  * Materialise Q(D) (Section 5: each cell writes its own outputs, then they are

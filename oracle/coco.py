@@ -41,6 +41,14 @@ def mix_params(b: int):
     return h, max(1, h - 1), h
 
 
+def mix_segmented(x, b: int, seed: int = 0):
+    """Segmented keys (batched relations): H_b on the low b bits, the bits above them
+    (the segment number) unchanged."""
+    x = np.asarray(x).astype(np.uint64)
+    hi = (x >> np.uint64(b)) << np.uint64(b)
+    return hi | mix(x & np.uint64((1 << b) - 1), b, seed)
+
+
 def mix(x, b: int, seed: int = 0):
     """H_b on an array of non-negative ids < 2^b (uint64 arithmetic)."""
     x = np.asarray(x).astype(np.uint64)
@@ -74,14 +82,16 @@ def key_bits_for(tuples) -> int:
     return max(1, mx.bit_length())
 
 
-def coco_levels(tuples, col_order, b, seed: int = 0):
+def coco_levels(tuples, col_order, b, seed: int = 0, segmented: bool = False):
     """CoCo of a relation: returns dict with V (list of arrays: uint32 mixed keys, or the
     raw int64 values when b is None), O (list of int64 arrays, one per level except
-    the last), n_unique, n_dup."""
+    the last), n_unique, n_dup.  segmented: only the low b bits are mixed."""
     t = np.asarray(tuples, dtype=np.int64)
     k = t.shape[1]
     if b is None:
         cols = [t[:, c].copy() for c in col_order]
+    elif segmented:
+        cols = [mix_segmented(t[:, c], b, seed) for c in col_order]
     else:
         cols = [mix(t[:, c], b, seed) for c in col_order]
     if t.shape[0] == 0:

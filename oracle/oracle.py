@@ -52,6 +52,8 @@ def lib():
         L.textbook_4cliques.argtypes = [P, ctypes.c_int64, ctypes.c_int]
         L.textbook_4clique_digest.restype = ctypes.c_int64
         L.textbook_4clique_digest.argtypes = [P, ctypes.c_int64, ctypes.c_int, P]
+        L.textbook_closed_4walks.restype = ctypes.c_int64
+        L.textbook_closed_4walks.argtypes = [P, ctypes.c_int64, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -172,3 +174,13 @@ def textbook_4clique_digest(edges, threads: int = 0):
     d = np.zeros(2, dtype=np.uint64)
     k = int(lib().textbook_4clique_digest(_ptr(e), e.shape[0], threads, _ptr(d)))
     return k, (int(d[0]), int(d[1]))
+
+
+def textbook_cycle4(edges, threads: int = 0) -> int:
+    """Ordered 4-cycle query count on a symmetric loop-free relation: the closed
+    4-walks, trace(A^4) = sum over (u, w) of c(u, w)^2, c = common neighbours
+    (wedge counting in textbook.c)."""
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int64))
+    if e.shape[0] == 0:
+        return 0
+    return int(lib().textbook_closed_4walks(_ptr(e), e.shape[0], threads))

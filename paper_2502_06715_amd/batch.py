@@ -1,0 +1,91 @@
+"""Batched execution of many small join queries.
+
+All queries of one shape (triangle or 4-cycle) are fused into a single Generic
+Join: their graphs become one relation whose ids carry the query number above
+the vertex bits (a segmented CoCo, see hc_build_coco_segmented), the first
+variable's share is the query number, so every query is one HyperCube cell (or
+2^extra cells), and the per-cell counts of hc_join_count_cells are the per-query
+counts.  The deepest level of all queries of a shape then runs as one persistent
+launch whose per-XCD queues sweep the queries in order.
+
+`run_sequential` is the one-query-per-launch baseline: build, decide shares and
+count each query on its own.
+"""
+
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import hc, inputs
+
+
+def union_relation(graphs, mix_bits: int):
+    """Concatenate graphs with query i's ids shifted to i * 2^mix_bits."""
+    seg_bits = max(1, int(len(graphs) - 1).bit_length())
+    assert mix_bits + seg_bits <= 31, "batch too large for int32 ids"
+    parts = []
+    for i, g in enumerate(graphs):
+        if g.shape[0]:
+            assert int(g.max()) < (1 << mix_bits)
+        parts.append(g.astype(np.int64) + (np.int64(i) << np.int64(mix_bits)))
+    rel = np.concatenate(parts).astype(np.int32) if parts else np.zeros((0, 2), np.int32)
+    return rel, seg_bits
+
+
+def id_bits(graphs) -> int:
+    mx = max((int(g.max()) for g in graphs if g.shape[0]), default=1)
+    return max(1, mx.bit_length())
+
+
+class Autotune:
+    """Measured choice of the extra split of every query's first variable (2^extra
+    cells per query), cached per batch signature."""
+
+    def __init__(self, candidates=(0, 1, 2, 3)):
+        self.candidates = tuple(candidates)
+        self.choice = {}
+
+    def pick(self, key, run):
+        if key in self.choice:
+            return self.choice[key]
+        best, best_t = None, None
+        for x in self.candidates:
+            t0 = time.perf_counter()
+            run(x)
+            dt = time.perf_counter() - t0
+            if best_t is None or dt < best_t:
+                best, best_t = x, dt
+        self.choice[key] = best
+        return best
+
+
+def count_batched(ctx: hc.Context, shape: str, rel_dev, n_queries: int, mix_bits: int, seg_bits: int,
+                  extra_bits: int = 0, coco=None):
+    """Per-query counts (uint64 array) of one fused join over a segmented relation."""
+    n, atoms = inputs.QUERIES[shape]
+    own = coco is None
+    if own:
+        coco = hc.build_coco(ctx, rel_dev, [0, 1], key_bits=mix_bits, segment_bits=seg_bits, symmetric=True)
+    order = list(range(n))
+    shares = [0] * n
+    shares[order[0]] = seg_bits + extra_bits
+    cells, _ = hc.join_count_cells(ctx, hc.Query(n, atoms), [coco] * len(atoms), order, shares)
+    if own:
+        coco.free()
+    per_query = cells.reshape(-1, 1 << extra_bits).sum(axis=1)
+    return per_query[:n_queries]
+
+
+def count_sequential(ctx: hc.Context, shape: str, graphs_dev, log2_cells: int = 6):
+    """One query per launch: build, choose shares by the cost model, count."""
+    n, atoms = inputs.QUERIES[shape]
+    q = hc.Query(n, atoms)
+    out = np.zeros(len(graphs_dev), dtype=np.uint64)
+    for i, t in enumerate(graphs_dev):
+        c = hc.build_coco(ctx, t, [0, 1], symmetric=True)
+        order, shares = hc.compute_shares(ctx, q, [c] * len(atoms), log2_cells)
+        out[i] = hc.join_count(ctx, q, [c] * len(atoms), order, shares)
+        c.free()
+    return out

@@ -100,9 +100,31 @@ void hc_ctx_destroy(hc_ctx* ctx) { delete ctx; }
 
 const char* hc_last_error(const hc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+static hc_status build_any(hc_ctx* ctx, const void* tuples, int64_t n, int32_t arity, hc_dtype dtype,
+                           const int32_t* col_order, int32_t key_bits, int32_t mix_bits, uint64_t mix_seed,
+                           uint32_t flags, hc_coco** out);
+
 hc_status hc_build_coco(hc_ctx* ctx, const void* tuples, int64_t n, int32_t arity, hc_dtype dtype,
                         const int32_t* col_order, int32_t key_bits, uint64_t mix_seed, uint32_t flags,
                         hc_coco** out) {
+    return build_any(ctx, tuples, n, arity, dtype, col_order, key_bits, 0, mix_seed, flags, out);
+}
+
+hc_status hc_build_coco_segmented(hc_ctx* ctx, const void* tuples, int64_t n, int32_t arity, hc_dtype dtype,
+                                  const int32_t* col_order, int32_t mix_bits, int32_t segment_bits,
+                                  uint64_t mix_seed, uint32_t flags, hc_coco** out) {
+    if (!ctx) return HC_ERR_INVALID;
+    if (mix_bits < 1 || segment_bits < 0 || mix_bits + segment_bits > 32) {
+        ctx->err = "hc_build_coco_segmented: need mix_bits >= 1, segment_bits >= 0, sum <= 32";
+        return HC_ERR_INVALID;
+    }
+    return build_any(ctx, tuples, n, arity, dtype, col_order, mix_bits + segment_bits, mix_bits, mix_seed, flags,
+                     out);
+}
+
+static hc_status build_any(hc_ctx* ctx, const void* tuples, int64_t n, int32_t arity, hc_dtype dtype,
+                           const int32_t* col_order, int32_t key_bits, int32_t mix_bits, uint64_t mix_seed,
+                           uint32_t flags, hc_coco** out) {
     if (!ctx) return HC_ERR_INVALID;
     return guarded(ctx, [&] {
         HC_REQUIRE(out != nullptr, HC_ERR_INVALID, "out is NULL");
@@ -122,7 +144,7 @@ hc_status hc_build_coco(hc_ctx* ctx, const void* tuples, int64_t n, int32_t arit
         }
         hc_coco* c = new hc_coco();
         try {
-            hc::build_coco(ctx, tuples, n, arity, dtype, col_order, key_bits, mix_seed, flags, c);
+            hc::build_coco(ctx, tuples, n, arity, dtype, col_order, key_bits, mix_bits, mix_seed, flags, c);
         } catch (...) {
             hc_coco_free(c);
             throw;
@@ -147,6 +169,7 @@ hc_status hc_coco_get_info(const hc_coco* c, hc_coco_info* info) {
     info->n_unique = c->n_unique;
     info->arity = c->arity;
     info->key_bits = c->key_bits;
+    info->mix_bits = c->mix_bits;
     info->mix_seed = c->mix_seed;
     for (int r = 0; r < 4; ++r) {
         info->col_order[r] = c->col_order[r];
@@ -246,6 +269,18 @@ hc_status hc_join_count(hc_ctx* ctx, const hc_query* q, const hc_coco* const* at
         HC_REQUIRE(atom_index && var_order && count_out, HC_ERR_INVALID, "NULL argument");
         hc::join_run(ctx, q, atom_index, var_order, log2_shares, flags, false, count_out, digest_out, nullptr, 0,
                      nullptr);
+    });
+}
+
+hc_status hc_join_count_cells(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
+                              const int32_t* var_order, const int32_t* log2_shares, uint32_t flags,
+                              uint64_t* cell_counts, uint64_t* count_out) {
+    if (!ctx) return HC_ERR_INVALID;
+    return guarded(ctx, [&] {
+        check_query_ptrs(q);
+        HC_REQUIRE(atom_index && var_order && cell_counts && count_out, HC_ERR_INVALID, "NULL argument");
+        hc::join_run(ctx, q, atom_index, var_order, log2_shares, flags, false, count_out, nullptr, nullptr, 0,
+                     nullptr, cell_counts);
     });
 }
 

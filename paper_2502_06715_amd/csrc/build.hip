@@ -22,9 +22,11 @@
 
 namespace hc {
 
-Mixer make_mixer(int b, uint64_t seed) {
+Mixer make_mixer(int b, uint64_t seed, int kb) {
     Mixer m{};
     m.b = b;
+    m.kb = kb;
+    m.kmask = kb >= 32 ? 0xFFFFFFFFu : ((1u << kb) - 1u);
     m.mask = b >= 32 ? 0xFFFFFFFFu : ((1u << b) - 1u);
     m.seed = (uint32_t)seed & m.mask;
     const uint32_t h = (uint32_t)(b + 1) / 2;
@@ -75,8 +77,8 @@ __global__ void k_pack(const T* __restrict__ t, int64_t n, int arity, ColOrder c
         uint64_t key = 0;
         for (int c = 0; c < arity; ++c) {
             const T v = t[i * arity + co.c[c]];
-            if (v < 0 || (unsigned long long)v > (unsigned long long)m.mask) err = 1;
-            key = (key << m.b) | mix_key((uint32_t)v, m);
+            if (v < 0 || (unsigned long long)v > (unsigned long long)m.kmask) err = 1;
+            key = (key << m.kb) | mix_key((uint32_t)v, m);
         }
         keys[i] = key;
     }
@@ -189,7 +191,8 @@ static unsigned grid_for(int64_t n, int cap = 8192) {
 }
 
 void build_coco(hc_ctx* ctx, const void* tuples, int64_t n, int arity, hc_dtype dtype,
-                const int32_t* col_order, int key_bits, uint64_t seed, uint32_t flags, hc_coco* out) {
+                const int32_t* col_order, int key_bits, int mix_bits, uint64_t seed, uint32_t flags,
+                hc_coco* out) {
     const Alloc& A = ctx->alloc;
     hipStream_t s = ctx->stream;
     ColOrder co{};
@@ -220,7 +223,10 @@ void build_coco(hc_ctx* ctx, const void* tuples, int64_t n, int arity, hc_dtype 
     if (b == 0) b = 1;
     HC_REQUIRE(b >= 1 && b <= 32, HC_ERR_INVALID, "hc_build_coco: key_bits must be 0..32");
     HC_REQUIRE(arity * b <= 64, HC_ERR_UNSUPPORTED, "hc_build_coco: arity * key_bits must be <= 64");
-    const Mixer mx = make_mixer(b, seed);
+    const int mb = mix_bits > 0 ? mix_bits : b;
+    HC_REQUIRE(mb >= 1 && mb <= b, HC_ERR_INVALID, "hc_build_coco: mixed bits must be 1..key_bits");
+    const Mixer mx = make_mixer(mb, seed, b);
+    out->mix_bits = mb;
 
     out->arity = arity;
     out->key_bits = b;

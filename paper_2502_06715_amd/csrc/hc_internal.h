@@ -31,22 +31,27 @@ struct Error {
 // ---------------------------------------------------------------- bijective b-bit mixer
 // H_b: Wellons' lowbias32 (xorshift, odd multiply, xorshift, odd multiply, xorshift)
 // restricted to b-bit words; shifts ceil(b/2), max(1, ceil(b/2)-1), ceil(b/2).
+// Keys are kb >= b bits wide: the low b bits are mixed, the kb-b bits above them
+// (a segment number, e.g. the query of a batch) pass through unchanged.
 struct Mixer {
-    uint32_t mask, seed;
+    uint32_t mask, seed;          // mask of the b mixed bits
     uint32_t s1, s2, s3;
     uint32_t c1, c2, c1inv, c2inv;
-    int32_t b;
+    int32_t b;                    // mixed bits
+    int32_t kb;                   // key bits
+    uint32_t kmask;               // mask of the kb key bits
 };
-Mixer make_mixer(int b, uint64_t seed);
+Mixer make_mixer(int b, uint64_t seed, int kb);
 
 __host__ __device__ inline uint32_t mix_key(uint32_t x, const Mixer& m) {
+    const uint32_t hi = x & ~m.mask;
     x = (x ^ m.seed) & m.mask;
     x ^= x >> m.s1;
     x = (x * m.c1) & m.mask;
     x ^= x >> m.s2;
     x = (x * m.c2) & m.mask;
     x ^= x >> m.s3;
-    return x;
+    return hi | x;
 }
 __host__ __device__ inline uint32_t unxorshift(uint32_t y, uint32_t s, int b) {
     uint32_t x = y;
@@ -54,12 +59,13 @@ __host__ __device__ inline uint32_t unxorshift(uint32_t y, uint32_t s, int b) {
     return x;
 }
 __host__ __device__ inline uint32_t unmix_key(uint32_t y, const Mixer& m) {
-    uint32_t x = unxorshift(y, m.s3, m.b);
+    const uint32_t hi = y & ~m.mask;
+    uint32_t x = unxorshift(y & m.mask, m.s3, m.b);
     x = (x * m.c2inv) & m.mask;
     x = unxorshift(x, m.s2, m.b);
     x = (x * m.c1inv) & m.mask;
     x = unxorshift(x, m.s1, m.b);
-    return (x ^ m.seed) & m.mask;
+    return hi | ((x ^ m.seed) & m.mask);
 }
 
 // ---------------------------------------------------------------- memory
@@ -114,6 +120,7 @@ struct hc_coco {
     hc::Alloc alloc;
     int32_t arity = 0;
     int32_t key_bits = 0;
+    int32_t mix_bits = 0;         // low bits mixed; the bits above are a segment number
     uint64_t mix_seed = 0;
     int32_t col_order[4] = {0, 1, 2, 3};
     hc_dtype dtype = HC_I32;
@@ -141,7 +148,8 @@ void radix_sort_u64(const Alloc& a, DevBuf<uint64_t>& keys, DevBuf<uint64_t>& tm
 
 // ---------------------------------------------------------------- build (build.hip)
 void build_coco(hc_ctx* ctx, const void* tuples, int64_t n, int arity, hc_dtype dtype,
-                const int32_t* col_order, int key_bits, uint64_t seed, uint32_t flags, hc_coco* out);
+                const int32_t* col_order, int key_bits, int mix_bits, uint64_t seed, uint32_t flags,
+                hc_coco* out);
 void partition_sizes(hc_ctx* ctx, const hc_coco* c, const int32_t* log2_shares, int64_t* B,
                      int64_t* Bpref);
 
@@ -205,6 +213,6 @@ void choose_shares(const hc_query* q, const std::vector<AtomStats>& st, int K, u
 // ---------------------------------------------------------------- join (join.hip)
 void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
               const int32_t* shares, uint32_t flags, bool emit, uint64_t* count, uint64_t* digest,
-              void* out, int64_t capacity, int64_t* n_out);
+              void* out, int64_t capacity, int64_t* n_out, uint64_t* cell_counts = nullptr);
 
 }  // namespace hc

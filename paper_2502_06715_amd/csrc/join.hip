@@ -59,6 +59,7 @@ struct KOp {
     int32_t word;     // CHILD: entry word of the parent node; TMP: entry word of (offset, length)
     int32_t group;    // TMP
     const int2* v0_range;   // V0 restricted by the cell: table indexed by the coordinate (or null)
+    int32_t rng_shift, rng_k;     // coordinate = (cell >> rng_shift) & (2^rng_k - 1)
     const int32_t* child_range;   // CHILD: per node, start of every coordinate's sub-range (or null)
     int32_t child_stride;         // 2^k + 1 entries per node
 };
@@ -89,7 +90,9 @@ struct KStep {
     int8_t head_word[kMaxVars];   // entry word of each head variable, -1 = the value bound here
 };
 
-enum Mode { M_COUNT = 0, M_DIGEST = 1, M_BITMAP = 2, M_EXPAND = 3, M_TMPW = 4, M_EMIT = 5 };
+enum Mode { M_COUNT = 0, M_DIGEST = 1, M_BITMAP = 2, M_EXPAND = 3, M_TMPW = 4, M_EMIT = 5, M_CELLS = 6 };
+// modes that write every match at its rank (from the match words and their prefix)
+constexpr bool mat_mode(int m) { return m == M_EXPAND || m == M_TMPW || m == M_EMIT; }
 
 struct Seg {
     int32_t* seg;      // [2*n_ops][stride]: begin, end per operand
@@ -102,6 +105,38 @@ __device__ inline const uint32_t* op_array(const KData& D, const KOp& o) {
     if (o.kind == OP_V0) return D.atoms[o.atom].V0;
     if (o.kind == OP_CHILD) return D.atoms[o.atom].V1;
     return D.tmp_val[o.group];
+}
+
+// Per-cell match counts of one wave (M_CELLS).  Frontier entries are in cell order,
+// so a wave sees long runs of one cell: it accumulates the run in a wave-uniform
+// counter and issues one atomic per run, not one per match or per step.
+struct CellAcc {
+    uint32_t cell = 0xFFFFFFFFu;
+    uint64_t n = 0;
+};
+__device__ inline void cell_flush(unsigned long long* cells, CellAcc& ca, int lane) {
+    if (ca.n && lane == 0) atomicAdd(&cells[ca.cell], (unsigned long long)ca.n);
+    ca.n = 0;
+}
+// Add n matches (wave-uniform) of one cell (wave-uniform).
+__device__ inline void cell_add(unsigned long long* cells, CellAcc& ca, uint32_t cell, uint64_t n, int lane) {
+    if (n == 0) return;
+    if (cell != ca.cell) {
+        cell_flush(cells, ca, lane);
+        ca.cell = cell;
+    }
+    ca.n += n;
+}
+// Add one match per lane with found set, each of the lane's own cell cl.
+__device__ inline void cell_add_lanes(unsigned long long* cells, CellAcc& ca, bool found, uint32_t cl, int lane) {
+    const uint64_t bal = __ballot(found);
+    if (bal == 0) return;
+    const int lead = __ffsll((long long)bal) - 1;
+    const uint32_t c0 = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)__shfl(cl, lead, 64));
+    const bool other = found && cl != c0;
+    const uint64_t ob = __ballot(other);
+    cell_add(cells, ca, c0, (uint64_t)__popcll(bal & ~ob), lane);
+    if (other) atomicAdd(&cells[cl], 1ull);
 }
 
 __global__ void k_init_cells(int32_t* F, int64_t n, int W) {
@@ -155,8 +190,8 @@ __global__ __launch_bounds__(kBlock) void k_prep(KData D, KStep S, const int32_t
             const KOp& op = S.ops[o];
             int64_t beg, end;
             if (op.kind == OP_V0) {
-                if (restrict_ && op.v0_range) {
-                    const int2 r = op.v0_range[coord];
+                if (op.v0_range) {
+                    const int2 r = op.v0_range[(cell >> op.rng_shift) & ((1u << op.rng_k) - 1u)];
                     beg = r.x;
                     end = r.y;
                 } else {
@@ -254,12 +289,14 @@ template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_probe(KData D, KStep S, const int32_t* __restrict__ F, Seg G,
                                                   const uint64_t* __restrict__ prefix, int64_t e_begin,
                                                   int64_t e_end, uint64_t item_begin, uint64_t n_items,
-                                                  uint64_t* __restrict__ words, unsigned long long* acc) {
+                                                  uint64_t* __restrict__ words, unsigned long long* acc,
+                                                  unsigned long long* cells) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int64_t n_words = (int64_t)((n_items + 63) / 64);
     uint64_t cnt = 0, dsum = 0, dxor = 0;
+    CellAcc ca;
     for (int64_t w = wave; w < n_words; w += nwaves) {
         const uint64_t rel = (uint64_t)w * 64 + lane;
         const bool valid = rel < n_items;
@@ -278,6 +315,7 @@ __global__ __launch_bounds__(kBlock) void k_probe(KData D, KStep S, const int32_
             if (lane == 0) words[w] = bal;
         } else {
             cnt += (uint64_t)__popcll(bal);
+            if (MODE == M_CELLS) cell_add_lanes(cells, ca, P.found, P.found ? (uint32_t)F[P.e * S.W_in] : 0u, lane);
             if (MODE == M_DIGEST && P.found) {
                 const int32_t* ent = F + P.e * S.W_in;
                 uint64_t h = 0x6A09E667F3BCC909ull;
@@ -292,6 +330,7 @@ __global__ __launch_bounds__(kBlock) void k_probe(KData D, KStep S, const int32_
             }
         }
     }
+    if (MODE == M_CELLS) cell_flush(cells, ca, lane);
     if (MODE != M_BITMAP) {
         // cnt is wave-uniform (sum of ballots); digest terms are per lane
         if (MODE == M_DIGEST) {
@@ -313,6 +352,7 @@ struct MatOut {
     uint32_t* tval;        // lifted intersection values
     int32_t* tsrc[kMaxOps];
     void* rows;            // emitted rows
+    unsigned long long* cells;   // per-cell counts
     int64_t row_base, row_cap;
 };
 
@@ -457,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                                                    unsigned long long* queue, uint64_t n_chunks,
                                                    uint64_t* __restrict__ words, unsigned long long* acc,
                                                    const uint64_t* __restrict__ wprefix, MatOut out) {
-    constexpr bool kMat = MODE >= M_EXPAND;
+    constexpr bool kMat = mat_mode(MODE);
     __shared__ __attribute__((aligned(16))) uint32_t win_all[kWaves][kWin];
     const int lane = threadIdx.x & 63;
     uint32_t* win = win_all[threadIdx.x >> 6];
@@ -466,6 +506,7 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
     for (int o = 0; o < NOPS; ++o) arr[o] = op_array(D, S.ops[o]);
     const int64_t stride = G.stride;
     uint64_t cnt = 0, dsum = 0, dxor = 0;
+    CellAcc ca;
     // Work queue per XCD: workgroups are dispatched to the 8 XCDs round-robin, so
     // blockIdx % 8 names the XCD; each XCD sweeps its own contiguous eighth of the
     // chunks in order, which keeps the few HyperCube cells it works on at a time
@@ -510,7 +551,7 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
             // Modes that write match words keep every step on 64-element boundaries;
             // counting modes let a step end where its entry ends, so only runs of tiny
             // entries take the per-lane path.
-            constexpr bool kAligned = !(MODE == M_COUNT || MODE == M_DIGEST);
+            constexpr bool kAligned = !(MODE == M_COUNT || MODE == M_DIGEST || MODE == M_CELLS);
             bool uniform_step;
             uint64_t n_sc;
             if (kAligned) {
@@ -641,6 +682,8 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                     } else {
                         cnt += (uint64_t)__popcll(bal);
                         if (MODE == M_DIGEST && f[k]) digest_add<MODE>(D, S, F + e * S.W_in, a[k], dsum, dxor);
+                        if (MODE == M_CELLS)
+                            cell_add(out.cells, ca, (uint32_t)uni(F[e * S.W_in]), (uint64_t)__popcll(bal), lane);
                     }
                 }
                 rc += n_sc;
@@ -695,6 +738,8 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                 } else {
                     cnt += (uint64_t)__popcll(bal);
                     if (MODE == M_DIGEST && found) digest_add<MODE>(D, S, F + my_e * S.W_in, av, dsum, dxor);
+                    if (MODE == M_CELLS)
+                        cell_add_lanes(out.cells, ca, found, found ? (uint32_t)F[my_e * S.W_in] : 0u, lane);
                 }
                 // continue inside the last entry touched (its cursors restart)
                 e = e_hi;
@@ -703,7 +748,8 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
             }
         }
     }
-    if (MODE == M_COUNT || MODE == M_DIGEST) {
+    if (MODE == M_CELLS) cell_flush(out.cells, ca, lane);
+    if (MODE == M_COUNT || MODE == M_DIGEST || MODE == M_CELLS) {
         if (MODE == M_DIGEST) {
             dsum = wave_sum(dsum);
             dxor = wave_xor(dxor);
@@ -757,8 +803,12 @@ static void launch_probe(const Alloc& A, const KData& D, const KStep& S, const i
                          const uint64_t* prefix, int64_t e_begin, int64_t e_end, uint64_t item_begin,
                          uint64_t n_items, uint64_t* words, unsigned long long* acc, hipStream_t s,
                          const uint64_t* wprefix = nullptr, MatOut out = MatOut{}) {
+    HC_REQUIRE(!mat_mode(MODE) || wprefix != nullptr, HC_ERR_DEVICE, "materialising probe without match ranks");
+    HC_REQUIRE(MODE != M_CELLS || out.cells != nullptr, HC_ERR_DEVICE, "per-cell probe without a cell buffer");
+    HC_REQUIRE(MODE != M_BITMAP || words != nullptr, HC_ERR_DEVICE, "bitmap probe without match words");
+    HC_REQUIRE(MODE == M_BITMAP || mat_mode(MODE) || acc != nullptr, HC_ERR_DEVICE, "counting probe without accumulator");
     if (S.n_ops > 4) {
-        if (MODE >= M_EXPAND) {
+        if (mat_mode(MODE)) {
             const int64_t nw = (int64_t)((n_items + 63) / 64);
             int64_t g2 = (nw + kWaves - 1) / kWaves;
             if (g2 < 1) g2 = 1;
@@ -772,8 +822,8 @@ static void launch_probe(const Alloc& A, const KData& D, const KStep& S, const i
         int64_t g2 = (nw + kWaves - 1) / kWaves;
         if (g2 < 1) g2 = 1;
         if (g2 > 16384) g2 = 16384;
-        k_probe<MODE < M_EXPAND ? MODE : M_BITMAP><<<(unsigned)g2, kBlock, 0, s>>>(
-            D, S, F, G, prefix, e_begin, e_end, item_begin, n_items, words, acc);
+        k_probe<mat_mode(MODE) ? M_BITMAP : MODE><<<(unsigned)g2, kBlock, 0, s>>>(
+            D, S, F, G, prefix, e_begin, e_end, item_begin, n_items, words, acc, out.cells);
         HC_HIP(hipGetLastError());
         return;
     }
@@ -870,6 +920,8 @@ struct Runner {
     int cell_shift[kMaxVars];
     int K;
     bool emit, digest;
+    int seg_bits = 0;                        // key bits above the mixed bits (batched queries)
+    unsigned long long* cell_out = nullptr;  // per-cell counts (device), or null
     int64_t cap_entries;
     DevBuf<unsigned long long> acc;
     DevBuf<int64_t> split;
@@ -934,13 +986,27 @@ struct Runner {
         if (po.kind == OP_TMP) o.word = L.tmp_word[po.group];
         o.child_range = nullptr;
         o.child_stride = 0;
+        o.rng_shift = 0;
+        o.rng_k = 0;
+        int vk = 0, vshift = 0;
         if (po.kind == OP_V0 && shares[var] > 0) {
-            const int k = shares[var];
-            ranges.emplace_back(A, (size_t)1 << k);
+            vk = shares[var];
+            vshift = cell_shift[var];
+        } else if (po.kind == OP_V0 && seg_bits > 0) {
+            // segmented keys: every variable stays inside the segment of the first
+            // variable's coordinate (its top seg_bits bits)
+            const int v0 = P.order[0];
+            vk = seg_bits;
+            vshift = cell_shift[v0] + shares[v0] - seg_bits;
+        }
+        if (vk > 0) {
+            ranges.emplace_back(A, (size_t)1 << vk);
             const DAtom& a = D.atoms[po.atom];
-            k_v0_ranges<<<grid_for((int64_t)1 << k), kBlock, 0, s>>>(a.V0, a.l0, D.b, k, ranges.back().p);
+            k_v0_ranges<<<grid_for((int64_t)1 << vk), kBlock, 0, s>>>(a.V0, a.l0, D.b, vk, ranges.back().p);
             HC_HIP(hipGetLastError());
             o.v0_range = ranges.back().p;
+            o.rng_k = vk;
+            o.rng_shift = vshift;
         }
         if (po.kind == OP_CHILD && shares[var] > 0) {
             // sub-range boundaries of every child list for every coordinate, when the
@@ -1168,7 +1234,12 @@ void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
                     if (ctx->profiling) HC_HIP(hipEventRecord(ev0, s));
                     if (digest)
                         launch_probe<M_DIGEST>(A, D, S, F, B.G, prefix_abs, ea, eb, 0, total, nullptr, acc.p, s);
-                    else
+                    else if (cell_out) {
+                        MatOut mo{};
+                        mo.cells = cell_out;
+                        launch_probe<M_CELLS>(A, D, S, F, B.G, prefix_abs, ea, eb, 0, total, nullptr, acc.p, s,
+                                              nullptr, mo);
+                    } else
                         launch_probe<M_COUNT>(A, D, S, F, B.G, prefix_abs, ea, eb, 0, total, nullptr, acc.p, s);
                     if (ctx->profiling) {
                         HC_HIP(hipEventRecord(ev1, s));
@@ -1234,12 +1305,12 @@ void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
 
 void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order, const int32_t* shares,
               uint32_t flags, bool emit, uint64_t* count, uint64_t* digest, void* out, int64_t capacity,
-              int64_t* n_out) {
+              int64_t* n_out, uint64_t* cell_counts) {
     Runner R(ctx);
     R.P = compile_plan(q, order, !(flags & HC_NO_REWRITE));
     const Plan& P = R.P;
     // CoCos: same key width and mixer, columns ordered by the variable order
-    int b = -1;
+    int b = -1, mb = -1;
     uint64_t seed = 0;
     int dtype64 = 0;
     for (int j = 0; j < P.n_atoms; ++j) {
@@ -1249,9 +1320,10 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
         if (b < 0) {
             b = c->key_bits;
             seed = c->mix_seed;
+            mb = c->mix_bits;
             dtype64 = c->dtype == HC_I64;
         }
-        HC_REQUIRE(c->key_bits == b && c->mix_seed == seed, HC_ERR_INVALID,
+        HC_REQUIRE(c->key_bits == b && c->mix_seed == seed && c->mix_bits == mb, HC_ERR_INVALID,
                    "all CoCos of a join must share key_bits and mix_seed");
         if (c->arity == 2) {
             int off = 0;
@@ -1268,6 +1340,16 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
         K += R.shares[v];
     }
     HC_REQUIRE(K <= 24, HC_ERR_INVALID, "more than 2^24 cells");
+    R.seg_bits = b - mb;
+    if (R.seg_bits > 0) {
+        // segmented keys (batched queries): the first variable's coordinate must name
+        // the segment, and no other variable may be split
+        HC_REQUIRE(R.shares[P.order[0]] >= R.seg_bits, HC_ERR_INVALID,
+                   "segmented CoCos: the first variable's share must cover the segment bits");
+        for (int v = 0; v < P.n_vars; ++v)
+            HC_REQUIRE(v == P.order[0] || R.shares[v] == 0, HC_ERR_INVALID,
+                       "segmented CoCos: only the first variable of the order may have a share");
+    }
     R.K = K;
     {
         // cell id: the first variable of the order in the low bits, the deepest in the
@@ -1287,7 +1369,7 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
         R.D.atoms[j].V1 = c->arity == 2 ? c->V[1] : nullptr;
         R.D.atoms[j].l0 = c->level_len[0];
     }
-    R.D.mix = make_mixer(b, seed);
+    R.D.mix = make_mixer(mb, seed, b);
     R.D.b = b;
     R.D.dtype64 = dtype64;
     R.emit = emit;
@@ -1318,12 +1400,21 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
     }
     // F_0: one entry per cell
     const int64_t ncell = (int64_t)1 << K;
+    DevBuf<unsigned long long> cells;
+    if (cell_counts) {
+        HC_REQUIRE(!emit, HC_ERR_INVALID, "per-cell counts are a counting mode");
+        cells = DevBuf<unsigned long long>(R.A, (size_t)ncell);
+        HC_HIP(hipMemsetAsync(cells.p, 0, sizeof(unsigned long long) * ncell, R.s));
+        R.cell_out = cells.p;
+    }
     DevBuf<int32_t> F0(R.A, (size_t)ncell * (size_t)R.lay[0].W);
     k_init_cells<<<grid_for(ncell), kBlock, 0, R.s>>>(F0.p, ncell, R.lay[0].W);
     HC_HIP(hipGetLastError());
     R.run_level(0, F0.p, F0.p, ncell);
     unsigned long long a[3] = {0, 0, 0};
     HC_HIP(hipMemcpyAsync(a, R.acc.p, sizeof(a), hipMemcpyDeviceToHost, R.s));
+    if (cell_counts)
+        HC_HIP(hipMemcpyAsync(cell_counts, cells.p, sizeof(unsigned long long) * ncell, hipMemcpyDeviceToHost, R.s));
     HC_HIP(hipStreamSynchronize(R.s));
     if (emit) {
         *count = (uint64_t)R.out_count;

@@ -47,7 +47,7 @@ class CocoInfo(ctypes.Structure):
                 ("key_bits", ctypes.c_int32), ("mix_seed", ctypes.c_uint64), ("col_order", ctypes.c_int32 * 4),
                 ("level_len", ctypes.c_int64 * 4), ("max_children", ctypes.c_int64 * 4),
                 ("distinct", ctypes.c_int64 * 4), ("symmetric", ctypes.c_int32), ("dtype", ctypes.c_int32),
-                ("bytes", ctypes.c_int64)]
+                ("bytes", ctypes.c_int64), ("mix_bits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Timing(ctypes.Structure):
@@ -65,6 +65,7 @@ SIGNATURES = {
     "hc_ctx_destroy": (None, [P]),
     "hc_last_error": (ctypes.c_char_p, [P]),
     "hc_build_coco": (ctypes.c_int, [P, P, I64, I32, ctypes.c_int, P, I32, U64, U32, P]),
+    "hc_build_coco_segmented": (ctypes.c_int, [P, P, I64, I32, ctypes.c_int, P, I32, I32, U64, U32, P]),
     "hc_coco_free": (None, [P]),
     "hc_coco_get_info": (ctypes.c_int, [P, P]),
     "hc_coco_copy_level": (ctypes.c_int, [P, P, I32, P, P]),
@@ -73,6 +74,7 @@ SIGNATURES = {
     "hc_compute_shares_from_info": (ctypes.c_int, [P, P, I32, U32, P, P]),
     "hc_join_count": (ctypes.c_int, [P, P, P, P, P, U32, P, P]),
     "hc_join_emit": (ctypes.c_int, [P, P, P, P, P, U32, P, I64, P]),
+    "hc_join_count_cells": (ctypes.c_int, [P, P, P, P, P, U32, P, P]),
     "hc_plan_describe": (ctypes.c_int, [P, P, U32, P, ctypes.c_size_t]),
     "hc_ctx_set_profiling": (ctypes.c_int, [P, ctypes.c_int]),
     "hc_ctx_get_timing": (ctypes.c_int, [P, P]),
@@ -199,8 +201,10 @@ class Coco:
 
 
 def build_coco(ctx: Context, tuples, col_order=None, key_bits: int = 0, seed: int = 0,
-               symmetric: bool = False) -> Coco:
-    """hc_build_coco on a CUDA tensor [n, arity] of int32/int64."""
+               symmetric: bool = False, segment_bits: int = 0) -> Coco:
+    """hc_build_coco on a CUDA tensor [n, arity] of int32/int64.  With segment_bits > 0
+    (hc_build_coco_segmented) key_bits is the number of mixed low bits and the ids
+    carry a segment number above them."""
     torch = ctx._torch
     t = tuples
     assert t.is_cuda and t.dim() == 2, "tuples must be a 2-D CUDA tensor"
@@ -209,9 +213,14 @@ def build_coco(ctx: Context, tuples, col_order=None, key_bits: int = 0, seed: in
     arity = t.shape[1]
     co = _i32(list(range(arity)) if col_order is None else col_order)
     h = ctypes.c_void_p()
-    st = lib().hc_build_coco(ctx.h, ctypes.c_void_p(t.data_ptr()), t.shape[0], arity, dt, co.ctypes.data,
-                             key_bits, seed & 0xFFFFFFFFFFFFFFFF, HC_BUILD_SYMMETRIC if symmetric else 0,
-                             ctypes.byref(h))
+    flags = HC_BUILD_SYMMETRIC if symmetric else 0
+    if segment_bits:
+        st = lib().hc_build_coco_segmented(ctx.h, ctypes.c_void_p(t.data_ptr()), t.shape[0], arity, dt,
+                                           co.ctypes.data, key_bits, segment_bits, seed & 0xFFFFFFFFFFFFFFFF,
+                                           flags, ctypes.byref(h))
+    else:
+        st = lib().hc_build_coco(ctx.h, ctypes.c_void_p(t.data_ptr()), t.shape[0], arity, dt, co.ctypes.data,
+                                 key_bits, seed & 0xFFFFFFFFFFFFFFFF, flags, ctypes.byref(h))
     ctx.check(st)
     return Coco(ctx, h)
 
@@ -276,6 +285,18 @@ def join_count(ctx: Context, q: Query, cocos, order, log2_shares=None, flags: in
     if digest:
         return int(cnt.value), (int(dg[0]), int(dg[1]))
     return int(cnt.value)
+
+
+def join_count_cells(ctx: Context, q: Query, cocos, order, log2_shares, flags: int = 0):
+    """Per-cell counts (numpy uint64, 2^sum(shares) entries) and the total."""
+    order_a = _i32(order)
+    sh = _i32(log2_shares)
+    cells = np.zeros(1 << int(sh.sum()), dtype=np.uint64)
+    cnt = ctypes.c_uint64(0)
+    qc = q.c()
+    ctx.check(lib().hc_join_count_cells(ctx.h, ctypes.byref(qc), _handles(cocos), order_a.ctypes.data,
+                                        sh.ctypes.data, flags, cells.ctypes.data, ctypes.byref(cnt)))
+    return cells, int(cnt.value)
 
 
 def join_emit(ctx: Context, q: Query, cocos, order, log2_shares=None, flags: int = 0, capacity: int = None,

@@ -68,6 +68,9 @@ def _draw_until(m: int, seed: int, id_bits: int, draw_batch) -> np.ndarray:
     key_bits = 2 * id_bits
     batch_bits = min(23, 64 - key_bits)
     assert batch_bits >= 10, "ids too wide for the packed dedup"
+    # candidates are drawn in batches of 2^k (k <= batch_bits); the batch size never
+    # changes which edges are kept, only how many draws are taken at a time
+    batch_bits = min(batch_bits, max(10, int(2 * m).bit_length()))
     batch = 1 << batch_bits
     accepted = np.zeros(0, dtype=np.uint64)          # sorted kept keys
     kept = []                                        # kept keys in generation order
@@ -219,3 +222,51 @@ QUERIES = {
     "clique4": (4, [(0, 1), (0, 2), (1, 3), (2, 3), (1, 2), (0, 3)]),            # Q6
     "twotriangle": (5, [(0, 1), (0, 2), (1, 2), (2, 3), (2, 4), (3, 4)]),        # Q8
 }
+
+GRAPH_SALT = 0x4752_4150_4853_4544   # separates a query's graph stream from its spec draws
+
+
+def _next_pow2(x: float) -> int:
+    v = 2
+    while v < x:
+        v <<= 1
+    return v
+
+
+def batch_spec(n_queries: int = 4096, seed_base: int = SEED_BATCH, log2_lo: float = 10.0, log2_hi: float = 18.0):
+    """The batched workload: query q draws 3 numbers from stream seed_base + q:
+    shape (triangle or 4-cycle, top bit of draw 0), graph (Erdos-Renyi or R-MAT, top
+    bit of draw 1) and m = round(2^U(log2_lo, log2_hi)) unique undirected edges (draw
+    2); n = next_pow2(m/8) vertices for Erdos-Renyi, next_pow2(m/16) for R-MAT."""
+    out = []
+    for q in range(n_queries):
+        r = splitmix64(seed_base + q, 0, 3)
+        shape = "triangle" if int(r[0]) >> 63 == 0 else "cycle4"
+        kind = "er" if int(r[1]) >> 63 == 0 else "rmat"
+        u = float(_unit_double(r[2:3])[0])
+        m = int(round(2.0 ** (log2_lo + (log2_hi - log2_lo) * u)))
+        n = _next_pow2(m / 8.0) if kind == "er" else _next_pow2(m / 16.0)
+        n = max(n, 64)
+        out.append({"q": q, "query": shape, "kind": kind, "m": m, "n": n, "seed": (seed_base + q) ^ GRAPH_SALT})
+    return out
+
+
+def batch_graph(spec) -> np.ndarray:
+    if spec["kind"] == "er":
+        return erdos_renyi(spec["n"], spec["m"], spec["seed"])
+    return rmat(spec["n"].bit_length() - 1, spec["m"], spec["seed"])
+
+
+def batch_graphs(specs, workers: int = 0):
+    """Graphs of a batch, generated in parallel processes (each is a pure function of its spec)."""
+    import os
+    from concurrent.futures import ProcessPoolExecutor
+    if workers <= 0:
+        try:
+            workers = min(16, len(os.sched_getaffinity(0)))
+        except AttributeError:
+            workers = min(16, os.cpu_count() or 1)
+    if workers == 1 or len(specs) < 8:
+        return [batch_graph(s) for s in specs]
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(batch_graph, specs, chunksize=8))

@@ -277,3 +277,41 @@ def test_rewritten_program_equals_plain_gj(name):
         c0, rows0 = rewrite.run_rewritten(n, atoms, [E] * len(atoms), order, rewrite=False)
         assert c1 == c0 == base.count
         assert rows1 == [tuple(x) for x in base.rows.tolist()]
+
+
+def test_textbook_cycle4_closed_forms_and_gj():
+    """trace(A^4) of K_k is (k-1)^4 + (k-1) (eigenvalues k-1 once, -1 k-1 times), of
+    K_{s,t} it is 2 s^2 t^2; on a random graph it equals the Generic Join count."""
+    for k in [3, 5, 9]:
+        assert oracle.textbook_cycle4(inputs.complete_graph(k)) == (k - 1) ** 4 + (k - 1)
+    for s, t in [(2, 3), (4, 7)]:
+        assert oracle.textbook_cycle4(inputs.complete_bipartite(s, t)) == 2 * s * s * t * t
+    E = inputs.rmat(10, 6000, 21)
+    assert oracle.textbook_cycle4(E) == oracle.gj(*Q["cycle4"], [E] * 4, threads=4).count
+    assert oracle.textbook_cycle4(np.zeros((0, 2), np.int64)) == 0
+
+
+@pytest.mark.parametrize("b,seg", [(4, 3), (9, 5), (16, 12)])
+def test_segmented_mixer_keeps_segment_and_mixes_low_bits(b, seg):
+    """Segmented keys: the segment number (bits above b) is kept, the low b bits are
+    H_b, so each segment is a bijection of its own block of 2^b ids."""
+    n = min(1 << (b + seg), 1 << 20)
+    x = np.arange(n, dtype=np.uint64)
+    y = coco.mix_segmented(x, b, seed=77)
+    assert np.array_equal(y >> np.uint64(b), x >> np.uint64(b))
+    assert np.array_equal(y & np.uint64((1 << b) - 1), coco.mix(x & np.uint64((1 << b) - 1), b, seed=77))
+    assert np.unique(y).size == n
+
+
+def test_batch_spec_deterministic_and_mixed():
+    a = inputs.batch_spec(256)
+    b = inputs.batch_spec(256)
+    assert a == b
+    shapes = {s["query"] for s in a}
+    kinds = {s["kind"] for s in a}
+    assert shapes == {"triangle", "cycle4"} and kinds == {"er", "rmat"}
+    ms = np.array([s["m"] for s in a])
+    assert ms.min() >= 1 << 10 and ms.max() <= 1 << 18
+    for s in a[:16]:
+        g = inputs.batch_graph(s)
+        assert g.shape[0] == 2 * s["m"] and int(g.max()) < s["n"]
