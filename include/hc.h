@@ -238,6 +238,24 @@ hc_status hc_join_count_cells(hc_ctx* ctx, const hc_query* q, const hc_coco* con
                               uint64_t* cell_counts, uint64_t* count_out);
 
 /*
+ * Memory estimate for admission control (the served workload keeps CoCos
+ * resident and admits a query while its estimate fits the free budget): an
+ * upper bound, in bytes, of the device memory one hc_join_count
+ * (per_cell = 0) or hc_join_count_cells (per_cell != 0) call with these
+ * arguments allocates through the context's allocator.  Host-only: it reads
+ * the CoCos' statistics (level lengths, longest child list) and launches
+ * nothing.  The bound follows the level-by-level frontiers of Generic Join
+ * (Section 5): entries of F_{i+1} are at most those of F_i times the longest
+ * list of level i's shortest operand (an id-range predicate on the variable
+ * caps it by the range width), and each frontier chunk, pool and table by the
+ * library's chunking cap of 2^27 entries.  bytes_out (host) receives it.
+ * Errors: HC_ERR_INVALID for a bad query, order or NULL argument.
+ */
+hc_status hc_join_workspace_bound(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
+                                  const int32_t* var_order, const int32_t* log2_shares, uint32_t flags,
+                                  int32_t per_cell, uint64_t* bytes_out);
+
+/*
  * Materialise Q(D) (Section 5: each cell writes its own outputs, then they are
  * concatenated).  out: device, row-major [capacity][n_vars] in head order,
  * raw ids, same dtype as the CoCos' input.  n_out (host) always receives the

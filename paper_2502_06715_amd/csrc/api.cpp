@@ -284,6 +284,18 @@ hc_status hc_join_count_cells(hc_ctx* ctx, const hc_query* q, const hc_coco* con
     });
 }
 
+hc_status hc_join_workspace_bound(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
+                                  const int32_t* var_order, const int32_t* log2_shares, uint32_t flags,
+                                  int32_t per_cell, uint64_t* bytes_out) {
+    if (!ctx) return HC_ERR_INVALID;
+    return guarded(ctx, [&] {
+        check_query_ptrs(q);
+        HC_REQUIRE(atom_index && var_order && bytes_out, HC_ERR_INVALID, "NULL argument");
+        for (int j = 0; j < q->n_atoms; ++j) HC_REQUIRE(atom_index[j] != nullptr, HC_ERR_INVALID, "atom CoCo handle is NULL");
+        *bytes_out = hc::join_workspace_bound(q, atom_index, var_order, log2_shares, flags, per_cell != 0);
+    });
+}
+
 hc_status hc_join_emit(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
                        const int32_t* var_order, const int32_t* log2_shares, uint32_t flags, void* out,
                        int64_t capacity, int64_t* n_out) {

@@ -393,12 +393,15 @@ __device__ inline void write_item(int mode, const KData& D, const KStep& S, cons
 // flattened elements, so it visits its entries in order and keeps, per entry,
 // one cursor per probed operand.  While the next elements stay inside one entry
 // they are consecutive elements of the iterated operand: the wave takes up to
-// 4 x 64 of them at once (4 per lane, coalesced loads), finds the window
-// [lo, hi) of every other operand that can hold their value range by
-// exponential search from the cursor (the galloping search of Section 5),
-// stages a dense window in LDS with coalesced loads and searches it there, or
-// binary-searches a sparse window in place.  Stretches where one 64-element
-// chunk spans several small entries fall back to one search per lane.
+// 4 x 64 of them at once (4 per lane, coalesced loads) and looks them up in
+// every other operand.  A short operand list is staged whole in an LDS region
+// and stays there while consecutive entries probe the same list (an operand
+// bound at a shallower level repeats over long runs of entries).  A long one is
+// searched from its cursor (the galloping search of Section 5, here 64-ary
+// across the wave's lanes), the window that can hold the step's value range is
+// staged in LDS with coalesced loads and searched there, and values beyond it
+// are binary-searched in place.  Stretches where one 64-element chunk spans
+// several small entries fall back to one search per lane.
 constexpr int kWin = 1024;      // LDS window per wave (elements)
 constexpr int kSub = 4;         // 64-element chunks per cursor step
 constexpr int kTiny = 24;       // counting modes: entries shorter than this take the per-lane path
@@ -422,6 +425,61 @@ __device__ inline int64_t gallop_lb(const uint32_t* __restrict__ B, int64_t c, i
     }
     const int64_t hi = lo + step < end ? lo + step : end;
     return lower_bound_u32(B, lo + 1, hi, v);
+}
+
+// First p in [c, end) with B[p] >= v (end if none), all 64 lanes cooperating: one
+// probe of the 64 elements at the cursor, then 64-ary narrowing, so a long jump
+// costs about log64 of its length in dependent loads (wave-uniform result).
+__device__ inline int32_t wave_search(const uint32_t* __restrict__ B, int32_t c, int32_t end, uint32_t v,
+                                      int lane) {
+    if (c >= end) return c;
+    {
+        const int32_t p = c + lane;
+        const bool lt = p < end && B[p] < v;
+        const int k = __popcll(__ballot(lt));
+        if (k < 64) return c + k;
+    }
+    int32_t lo = c + 64, hi = end;   // the answer lies in [lo, hi]
+    while (hi - lo > 64) {
+        const int32_t step = (hi - lo + 63) >> 6;
+        const int32_t p = lo + lane * step;
+        const bool lt = p < hi && B[p] < v;
+        const int k = __popcll(__ballot(lt));
+        if (k == 0) return lo;
+        const int32_t nlo = lo + (k - 1) * step + 1;
+        const int32_t nhi = lo + k * step < hi ? lo + k * step : hi;
+        lo = nlo;
+        hi = nhi;
+    }
+    const int32_t p = lo + lane;
+    const bool lt = p < hi && B[p] < v;
+    return lo + __popcll(__ballot(lt));
+}
+
+// Stage B[base, base + len_al) in an LDS region with 16-byte loads (base is a
+// multiple of 4): the first sh slots are zeroed (they hold the tail of the
+// previous list, so the region stays sorted) and slots len_al .. p2-1 hold the
+// largest key, which no searched value exceeds.
+__device__ inline void stage_window(uint32_t* rw, const uint32_t* __restrict__ B, int32_t base, int32_t sh,
+                                    int32_t len_al, int32_t p2, int lane) {
+    for (int q = lane; q < (p2 >> 2); q += 64) {
+        const int32_t k0 = 4 * q;
+        uint4 val;
+        if (k0 + 4 <= len_al) {
+            val = *reinterpret_cast<const uint4*>(B + base + k0);
+        } else {
+            val.x = k0 + 0 < len_al ? B[base + k0 + 0] : 0xFFFFFFFFu;
+            val.y = k0 + 1 < len_al ? B[base + k0 + 1] : 0xFFFFFFFFu;
+            val.z = k0 + 2 < len_al ? B[base + k0 + 2] : 0xFFFFFFFFu;
+            val.w = k0 + 3 < len_al ? B[base + k0 + 3] : 0xFFFFFFFFu;
+        }
+        if (k0 == 0) {
+            if (sh > 0) val.x = 0u;
+            if (sh > 1) val.y = 0u;
+            if (sh > 2) val.z = 0u;
+        }
+        *reinterpret_cast<uint4*>(rw + k0) = val;
+    }
 }
 
 // Largest e' in [e, e_end) with prefix[e'] <= g, given prefix[e] <= g: exponential
@@ -465,22 +523,6 @@ __device__ inline uint64_t uni64(uint64_t v) {
            (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)v);
 }
 
-// First p in [c, end) with B[p] >= v; exponential search from c (wave-uniform).
-__device__ inline int32_t gallop32(const uint32_t* __restrict__ B, int32_t c, int32_t end, uint32_t v) {
-    if (c >= end || B[c] >= v) return c;
-    int32_t lo = c, step = 1;   // B[lo] < v
-    while (lo + step < end && B[lo + step] < v) {
-        lo += step;
-        step <<= 1;
-    }
-    int32_t l = lo + 1, h = lo + step < end ? lo + step : end;
-    while (l < h) {
-        const int32_t mid = (l + h) >> 1;
-        if (B[mid] < v) l = mid + 1; else h = mid;
-    }
-    return l;
-}
-
 __device__ inline int32_t lower_bound32(const uint32_t* __restrict__ B, int32_t l, int32_t h, uint32_t v) {
     while (l < h) {
         const int32_t mid = (l + h) >> 1;
@@ -512,6 +554,14 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
     // chunks in order, which keeps the few HyperCube cells it works on at a time
     // (and their slices of the CoCo arrays) resident in its L2.  Every wave leaves
     // once its XCD's queue is exhausted.
+    // LDS-resident operand lists (per operand region): array, begin, end
+    const uint32_t* wc_ptr[NOPS];
+    int32_t wc_beg[NOPS], wc_end[NOPS];
+#pragma unroll
+    for (int o = 0; o < NOPS; ++o) {
+        wc_ptr[o] = nullptr;
+        wc_beg[o] = wc_end[o] = 0;
+    }
     const int xcd = (int)(blockIdx.x % kXcd);
     const uint64_t c_lo = n_chunks * (uint64_t)xcd / kXcd, c_hi = n_chunks * (uint64_t)(xcd + 1) / kXcd;
     for (;;) {
@@ -587,7 +637,52 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                 for (int o = 0; o < NOPS; ++o) {
                     if (o == it) continue;
                     const uint32_t* B = arr[o];
-                    const int32_t lo = uni(gallop32(B, cur[o], end[o], a_first));
+                    const int32_t full = end[o] - beg[o];
+                    // ---- short operand: its whole list sits in this operand's LDS region,
+                    // kept across steps and entries while the list stays the same (the
+                    // deepest level's entries come in key order, so an operand bound at a
+                    // shallower level repeats over long runs of entries)
+                    constexpr int kReg = NOPS <= 2 ? kWin : kWin / 4;
+                    uint32_t* rw = win + (NOPS <= 2 ? 0 : o * kReg);
+                    if (full <= kReg - 4) {
+                        const int32_t base = beg[o] & ~3;
+                        const int32_t sh = beg[o] - base;
+                        const int32_t len_al = full + sh;
+                        int32_t p2 = 4;
+                        while (p2 < len_al) p2 <<= 1;
+                        if (!(wc_ptr[o] == B && wc_beg[o] == beg[o] && wc_end[o] == end[o])) {
+                            wave_sync();   // earlier searches of this region are done
+                            stage_window(rw, B, base, sh, len_al, p2, lane);
+                            wave_sync();
+                            if (NOPS <= 2) {   // one region shared by both operands
+#pragma unroll
+                                for (int u = 0; u < NOPS; ++u) wc_ptr[u] = nullptr;
+                            }
+                            wc_ptr[o] = B;
+                            wc_beg[o] = beg[o];
+                            wc_end[o] = end[o];
+                        }
+                        int32_t p[kSub];
+#pragma unroll
+                        for (int k = 0; k < kSub; ++k) p[k] = 0;
+                        for (int32_t step = p2 >> 1; step > 0; step >>= 1) {
+#pragma unroll
+                            for (int k = 0; k < kSub; ++k)
+                                if (rw[p[k] + step - 1] < a[k]) p[k] += step;
+                        }
+#pragma unroll
+                        for (int k = 0; k < kSub; ++k) {
+                            if (rw[p[k]] < a[k]) p[k] += 1;
+                            if (p[k] < sh) p[k] = sh;
+                            if (v[k]) f[k] = f[k] && p[k] < len_al && rw[p[k]] == a[k];
+                            if (kMat) pos[o][k] = base + p[k];
+                        }
+                        continue;
+                    }
+                    // ---- long operand: a window of the list from the cursor on
+#pragma unroll
+                    for (int u = 0; u < NOPS; ++u) wc_ptr[u] = nullptr;   // the window overwrites every region
+                    const int32_t lo = uni(wave_search(B, cur[o], end[o], a_first, lane));
                     const int32_t avail = end[o] - lo;
                     // window sized by this step's share of the entry's remaining elements
                     uint64_t est = (uint64_t)nsc * (uint64_t)avail / (pe1 - g);
@@ -604,24 +699,7 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                     const int32_t len_al = len + sh;
                     int32_t p2 = 4;
                     while (p2 < len_al) p2 <<= 1;
-                    for (int q = lane; q < (p2 >> 2); q += 64) {
-                        const int32_t k0 = 4 * q;
-                        uint4 val;
-                        if (k0 + 4 <= len_al) {
-                            val = *reinterpret_cast<const uint4*>(B + lo_al + k0);
-                        } else {
-                            val.x = k0 + 0 < len_al ? B[lo_al + k0 + 0] : 0xFFFFFFFFu;
-                            val.y = k0 + 1 < len_al ? B[lo_al + k0 + 1] : 0xFFFFFFFFu;
-                            val.z = k0 + 2 < len_al ? B[lo_al + k0 + 2] : 0xFFFFFFFFu;
-                            val.w = k0 + 3 < len_al ? B[lo_al + k0 + 3] : 0xFFFFFFFFu;
-                        }
-                        if (k0 == 0) {
-                            if (sh > 0) val.x = 0u;
-                            if (sh > 1) val.y = 0u;
-                            if (sh > 2) val.z = 0u;
-                        }
-                        *reinterpret_cast<uint4*>(win + k0) = val;
-                    }
+                    stage_window(win, B, lo_al, sh, len_al, p2, lane);
                     wave_sync();
                     const uint32_t wmax = len > 0 ? win[len_al - 1] : 0u;
                     int32_t p[kSub];
@@ -907,6 +985,28 @@ struct Layout {
     int tmp_word[kMaxGroups];
 };
 
+// Words of a frontier F_i entry: the cell id, the i bound keys, the CoCo level-0
+// position of every atom whose first variable is bound and whose second is not
+// yet, and an (offset, length) pair per live lifted intersection.
+static Layout make_layout(const Plan& P, int i) {
+    Layout L;
+    int w = 1 + i;
+    for (int j = 0; j < kMaxAtoms; ++j) L.node_word[j] = -1;
+    for (int g = 0; g < kMaxGroups; ++g) L.tmp_word[g] = -1;
+    for (int j = 0; j < P.n_atoms; ++j) {
+        if (P.atom_second[j] < 0) continue;
+        const int pf = P.pos[P.atom_first[j]], ps = P.pos[P.atom_second[j]];
+        if (pf < i && i <= ps) L.node_word[j] = w++;
+    }
+    for (int g = 0; g < P.n_groups; ++g)
+        if (P.groups[g].lift <= i && i <= P.groups[g].consumer) {
+            L.tmp_word[g] = w;
+            w += 2;
+        }
+    L.W = w;
+    return L;
+}
+
 struct Runner {
     hc_ctx* ctx;
     const Alloc& A;
@@ -930,7 +1030,8 @@ struct Runner {
     std::vector<uint64_t> child_key;
     DevBuf<uint32_t> tmp_val[kMaxGroups];
     DevBuf<int32_t> tmp_src[kMaxGroups][kMaxOps];
-    int64_t tmp_cap = 0;
+    int64_t tmp_cap[kMaxGroups] = {};        // elements per lifted-intersection pool (grown on demand)
+    int64_t tmp_max = 0;                     // pool size the chunking aims for
     // emit
     void* out_rows = nullptr;
     int64_t out_cap = 0, out_count = 0;
@@ -954,24 +1055,9 @@ struct Runner {
     }
 
     void setup_layouts() {
-        const int n = P.n_vars;
-        for (int i = 0; i <= n; ++i) {
-            Layout& L = lay[i];
-            int w = 1 + i;
-            for (int j = 0; j < kMaxAtoms; ++j) L.node_word[j] = -1;
-            for (int g = 0; g < kMaxGroups; ++g) L.tmp_word[g] = -1;
-            for (int j = 0; j < P.n_atoms; ++j) {
-                if (P.atom_second[j] < 0) continue;
-                const int pf = P.pos[P.atom_first[j]], ps = P.pos[P.atom_second[j]];
-                if (pf < i && i <= ps) L.node_word[j] = w++;
-            }
-            for (int g = 0; g < P.n_groups; ++g)
-                if (P.groups[g].lift <= i && i <= P.groups[g].consumer) {
-                    L.tmp_word[g] = w;
-                    w += 2;
-                }
-            HC_REQUIRE(w <= kMaxW, HC_ERR_UNSUPPORTED, "frontier entry too wide");
-            L.W = w;
+        for (int i = 0; i <= P.n_vars; ++i) {
+            lay[i] = make_layout(P, i);
+            HC_REQUIRE(lay[i].W <= kMaxW, HC_ERR_UNSUPPORTED, "frontier entry too wide");
         }
     }
 
@@ -1159,6 +1245,14 @@ struct Runner {
         return read_u64(wpre.p + nw);
     }
 
+    // (Re)allocate the pool of group g; its previous contents are discarded.
+    void grow_tmp(int g, int64_t elems) {
+        tmp_val[g] = DevBuf<uint32_t>(A, (size_t)elems);
+        for (int u = 0; u < group_step[g].n_src; ++u) tmp_src[g][u] = DevBuf<int32_t>(A, (size_t)elems);
+        tmp_cap[g] = elems;
+        refresh_tmp_ptrs();
+    }
+
     void refresh_tmp_ptrs() {
         for (int g = 0; g < kMaxGroups; ++g) {
             D.tmp_val[g] = tmp_val[g].p;
@@ -1177,12 +1271,20 @@ void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
     for (int g = 0; g < P.n_groups; ++g)
         if (P.groups[g].lift == i) groups.push_back(g);
     std::vector<StepBufs> gb(groups.size());
-    for (size_t t = 0; t < groups.size(); ++t) prep(group_step[groups[t]], F, 0, n, gb[t]);
+    for (size_t t = 0; t < groups.size(); ++t) {
+        const int g = groups[t];
+        prep(group_step[g], F, 0, n, gb[t]);
+        // The pool of a group lifted at this level is dead between calls of this
+        // level and between its chunks, so it is sized here: all of this call's
+        // elements, up to tmp_max (the chunking below splits the rest).
+        const uint64_t need = std::max<uint64_t>(1, std::min<uint64_t>(read_u64(gb[t].prefix.p + n), (uint64_t)tmp_max));
+        if (need > (uint64_t)tmp_cap[g]) grow_tmp(g, (int64_t)need);
+    }
     int64_t ea = 0;
     while (ea < n) {
         int64_t eb = n;
         for (size_t t = 0; t < groups.size(); ++t) {
-            k_split<<<1, 1, 0, s>>>(gb[t].prefix.p, ea, eb, (uint64_t)tmp_cap, split.p);
+            k_split<<<1, 1, 0, s>>>(gb[t].prefix.p, ea, eb, (uint64_t)tmp_cap[groups[t]], split.p);
             HC_HIP(hipGetLastError());
             int64_t e2 = 0;
             HC_HIP(hipMemcpyAsync(&e2, split.p, sizeof(e2), hipMemcpyDeviceToHost, s));
@@ -1197,16 +1299,8 @@ void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
             HC_HIP(hipMemcpyAsync(&pr[1], gb[t].prefix.p + eb, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
             HC_HIP(hipStreamSynchronize(s));
             const uint64_t ni = pr[1] - pr[0];
-            HC_REQUIRE(ni <= (uint64_t)tmp_cap || eb == ea + 1, HC_ERR_DEVICE, "tmp chunking failed");
-            if (ni > (uint64_t)tmp_cap) {
-                // one entry larger than the pool: grow the pool
-                tmp_cap = (int64_t)ni;
-                for (int gg = 0; gg < P.n_groups; ++gg) {
-                    tmp_val[gg] = DevBuf<uint32_t>(A, (size_t)tmp_cap);
-                    for (int u = 0; u < kMaxOps; ++u) tmp_src[gg][u] = DevBuf<int32_t>(A, (size_t)tmp_cap);
-                }
-                refresh_tmp_ptrs();
-            }
+            HC_REQUIRE(ni <= (uint64_t)tmp_cap[g] || eb == ea + 1, HC_ERR_DEVICE, "tmp chunking failed");
+            if (ni > (uint64_t)tmp_cap[g]) grow_tmp(g, (int64_t)ni);   // one entry larger than the pool
             DevBuf<uint64_t> words, wpre;
             match_words(S, F, gb[t], gb[t].prefix.p, ea, eb, pr[0], ni, words, wpre);
             const int64_t nw = (int64_t)((ni + 63) / 64);
@@ -1377,16 +1471,12 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
     R.out_rows = out;
     R.out_cap = capacity;
     R.cap_entries = (int64_t)1 << 27;
-    R.tmp_cap = (int64_t)1 << 27;
+    R.tmp_max = (int64_t)1 << 27;
     R.acc = DevBuf<unsigned long long>(R.A, 4);
     R.split = DevBuf<int64_t>(R.A, 2);
     HC_HIP(hipMemsetAsync(R.acc.p, 0, sizeof(unsigned long long) * 4, R.s));
     R.setup_layouts();
     R.setup_steps(q);
-    for (int g = 0; g < P.n_groups; ++g) {
-        R.tmp_val[g] = DevBuf<uint32_t>(R.A, (size_t)R.tmp_cap);
-        for (int u = 0; u < R.group_step[g].n_src; ++u) R.tmp_src[g][u] = DevBuf<int32_t>(R.A, (size_t)R.tmp_cap);
-    }
     R.refresh_tmp_ptrs();
     if (ctx->profiling) {
         HC_HIP(hipEventCreate(&R.ev0));
@@ -1441,6 +1531,54 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
         ctx->timing = hc_timing{};
         ctx->timing.leaf_items = R.leaf_items;
     }
+}
+
+// Upper bound of the device memory one join call allocates (frontiers, per-level
+// step buffers, match words, lifted-intersection pools, work-queue tables), from
+// host-side CoCo statistics only.  Entries of F_{i+1} are bounded by those of F_i
+// times the longest list of level i's shortest operand (a predicate bounds it by
+// its id range), and every frontier chunk by the chunking cap.
+uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
+                              const int32_t* shares, uint32_t flags, bool cells) {
+    const Plan P = compile_plan(q, order, !(flags & HC_NO_REWRITE));
+    constexpr double kCap = (double)((int64_t)1 << 27);   // frontier entries / pool elements per chunk
+    int K = 0;
+    for (int v = 0; v < P.n_vars; ++v) K += shares ? shares[v] : 0;
+    auto op_max = [&](const PlanOp& o) -> double {
+        const hc_coco* c = atoms[o.atom];
+        return o.kind == OP_CHILD ? (double)c->max_children[0] : (double)c->level_len[0];
+    };
+    double gmax[kMaxGroups];
+    for (int g = 0; g < P.n_groups; ++g) {
+        double m = 1e30;
+        for (int t = 0; t < P.groups[g].n_ops; ++t) m = std::min(m, op_max(P.groups[g].ops[t]));
+        gmax[g] = m;
+    }
+    double E = std::ldexp(1.0, K), bytes = 0;
+    for (int i = 0; i < P.n_vars; ++i) {
+        const PlanLevel& L = P.levels[i];
+        double m = 1e30;
+        for (int t = 0; t < L.n_ops; ++t)
+            m = std::min(m, L.ops[t].kind == OP_TMP ? gmax[L.ops[t].group] : op_max(L.ops[t]));
+        if (q->var_lo && q->var_hi && q->var_hi[L.var] > q->var_lo[L.var])
+            m = std::min(m, (double)q->var_hi[L.var] - (double)q->var_lo[L.var]);
+        const double n = std::min(E, kCap);
+        const Layout Li = make_layout(P, i);
+        bytes += n * 4.0 * Li.W;                               // F_i
+        bytes += n * (8.0 * L.n_ops + 13.0) + 8.0;             // ranges, iterated operand, length, prefix
+        for (int g = 0; g < P.n_groups; ++g) {
+            if (P.groups[g].lift != i) continue;
+            const double pool = std::min(n * gmax[g], kCap);
+            bytes += n * (8.0 * P.groups[g].n_ops + 13.0) + 8.0;
+            bytes += pool * 4.0 * (1 + P.groups[g].n_ops) + (pool / 64 + 1) * 16.0;
+        }
+        const double items = std::min(n * m, 1e18);
+        if (i + 1 < P.n_vars) bytes += (std::min(items, kCap) / 64 + 1) * 16.0;   // match words of a chunk
+        bytes += (items / 2048 + 1) * 8.0 + 64.0;                                  // work-queue chunk table
+        E = std::min(E * m, 1e18);
+    }
+    if (cells) bytes += std::ldexp(8.0, K);
+    return (uint64_t)std::min(bytes, 1.8e19);
 }
 
 }  // namespace hc

@@ -75,6 +75,7 @@ SIGNATURES = {
     "hc_join_count": (ctypes.c_int, [P, P, P, P, P, U32, P, P]),
     "hc_join_emit": (ctypes.c_int, [P, P, P, P, P, U32, P, I64, P]),
     "hc_join_count_cells": (ctypes.c_int, [P, P, P, P, P, U32, P, P]),
+    "hc_join_workspace_bound": (ctypes.c_int, [P, P, P, P, P, U32, I32, P]),
     "hc_plan_describe": (ctypes.c_int, [P, P, U32, P, ctypes.c_size_t]),
     "hc_ctx_set_profiling": (ctypes.c_int, [P, ctypes.c_int]),
     "hc_ctx_get_timing": (ctypes.c_int, [P, P]),
@@ -297,6 +298,19 @@ def join_count_cells(ctx: Context, q: Query, cocos, order, log2_shares, flags: i
     ctx.check(lib().hc_join_count_cells(ctx.h, ctypes.byref(qc), _handles(cocos), order_a.ctypes.data,
                                         sh.ctypes.data, flags, cells.ctypes.data, ctypes.byref(cnt)))
     return cells, int(cnt.value)
+
+
+def join_workspace_bound(ctx: Context, q: Query, cocos, order, log2_shares=None, flags: int = 0,
+                         per_cell: bool = False) -> int:
+    """Upper bound (bytes) of the device memory one count call allocates."""
+    order_a = _i32(order)
+    sh = _i32(log2_shares) if log2_shares is not None else None
+    out = ctypes.c_uint64(0)
+    qc = q.c()
+    ctx.check(lib().hc_join_workspace_bound(ctx.h, ctypes.byref(qc), _handles(cocos), order_a.ctypes.data,
+                                            sh.ctypes.data if sh is not None else None, flags, int(per_cell),
+                                            ctypes.byref(out)))
+    return int(out.value)
 
 
 def join_emit(ctx: Context, q: Query, cocos, order, log2_shares=None, flags: int = 0, capacity: int = None,
