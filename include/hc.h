@@ -238,22 +238,42 @@ hc_status hc_join_count_cells(hc_ctx* ctx, const hc_query* q, const hc_coco* con
                               uint64_t* cell_counts, uint64_t* count_out);
 
 /*
+ * Many instances of one query in one pass (the served workload fuses the
+ * queued requests of one shape over one resident CoCo set): instance t is q
+ * with its first variable (var_order[0]) restricted to raw ids in
+ * [first_var_ranges[2t], first_var_ranges[2t+1]) (an empty or inverted range
+ * selects nothing); any var_lo/var_hi of q apply to every instance.  Frontier
+ * F_0 of Generic Join (Section 5) holds one entry per instance instead of one
+ * per HyperCube cell; no shares are taken.  counts_out (host, n_queries
+ * entries) receives each instance's count, equal to hc_join_count of that
+ * instance alone.  first_var_ranges is host memory, [n_queries][2] int64.
+ * Errors: HC_ERR_INVALID for a bad query, order, NULL argument, negative
+ * n_queries, more than 2^24 instances or segmented CoCos; otherwise as
+ * hc_join_count.
+ */
+hc_status hc_join_count_multi(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
+                              const int32_t* var_order, uint32_t flags, int64_t n_queries,
+                              const int64_t* first_var_ranges, uint64_t* counts_out);
+
+/*
  * Memory estimate for admission control (the served workload keeps CoCos
- * resident and admits a query while its estimate fits the free budget): an
- * upper bound, in bytes, of the device memory one hc_join_count
- * (per_cell = 0) or hc_join_count_cells (per_cell != 0) call with these
- * arguments allocates through the context's allocator.  Host-only: it reads
- * the CoCos' statistics (level lengths, longest child list) and launches
- * nothing.  The bound follows the level-by-level frontiers of Generic Join
- * (Section 5): entries of F_{i+1} are at most those of F_i times the longest
- * list of level i's shortest operand (an id-range predicate on the variable
- * caps it by the range width), and each frontier chunk, pool and table by the
- * library's chunking cap of 2^27 entries.  bytes_out (host) receives it.
- * Errors: HC_ERR_INVALID for a bad query, order or NULL argument.
+ * resident and admits work while its estimate fits the free budget): an upper
+ * bound, in bytes, of the device memory one call allocates through the
+ * context's allocator -- hc_join_count / hc_join_count_cells with these
+ * arguments when n_queries = 0, or hc_join_count_multi with n_queries
+ * instances whose first-variable ranges are at most first_width ids wide
+ * (0: unbounded; log2_shares is then ignored).  Host-only: it reads the CoCos'
+ * statistics (level lengths, longest child list) and launches nothing.  The
+ * bound follows the level-by-level frontiers of Generic Join (Section 5):
+ * entries of F_{i+1} are at most those of F_i times the longest list of level
+ * i's shortest operand (an id range on the variable caps it by the range
+ * width), and each frontier chunk, pool and table by the library's chunking
+ * cap of 2^27 entries.  bytes_out (host) receives it.  Errors: HC_ERR_INVALID
+ * for a bad query, order, NULL argument or negative count or width.
  */
 hc_status hc_join_workspace_bound(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
                                   const int32_t* var_order, const int32_t* log2_shares, uint32_t flags,
-                                  int32_t per_cell, uint64_t* bytes_out);
+                                  int64_t n_queries, int64_t first_width, uint64_t* bytes_out);
 
 /*
  * Materialise Q(D) (Section 5: each cell writes its own outputs, then they are

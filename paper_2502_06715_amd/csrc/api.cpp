@@ -286,13 +286,29 @@ hc_status hc_join_count_cells(hc_ctx* ctx, const hc_query* q, const hc_coco* con
 
 hc_status hc_join_workspace_bound(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
                                   const int32_t* var_order, const int32_t* log2_shares, uint32_t flags,
-                                  int32_t per_cell, uint64_t* bytes_out) {
+                                  int64_t n_queries, int64_t first_width, uint64_t* bytes_out) {
     if (!ctx) return HC_ERR_INVALID;
     return guarded(ctx, [&] {
         check_query_ptrs(q);
         HC_REQUIRE(atom_index && var_order && bytes_out, HC_ERR_INVALID, "NULL argument");
+        HC_REQUIRE(n_queries >= 0 && first_width >= 0, HC_ERR_INVALID, "negative n_queries or first_width");
         for (int j = 0; j < q->n_atoms; ++j) HC_REQUIRE(atom_index[j] != nullptr, HC_ERR_INVALID, "atom CoCo handle is NULL");
-        *bytes_out = hc::join_workspace_bound(q, atom_index, var_order, log2_shares, flags, per_cell != 0);
+        *bytes_out = hc::join_workspace_bound(q, atom_index, var_order, log2_shares, flags, n_queries, first_width);
+    });
+}
+
+hc_status hc_join_count_multi(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
+                              const int32_t* var_order, uint32_t flags, int64_t n_queries,
+                              const int64_t* first_var_ranges, uint64_t* counts_out) {
+    if (!ctx) return HC_ERR_INVALID;
+    return guarded(ctx, [&] {
+        check_query_ptrs(q);
+        HC_REQUIRE(atom_index && var_order && first_var_ranges && counts_out, HC_ERR_INVALID, "NULL argument");
+        HC_REQUIRE(n_queries >= 0, HC_ERR_INVALID, "negative n_queries");
+        if (n_queries == 0) return;
+        uint64_t total = 0;
+        hc::join_run(ctx, q, atom_index, var_order, nullptr, flags, false, &total, nullptr, nullptr, 0, nullptr,
+                     counts_out, n_queries, first_var_ranges);
     });
 }
 

@@ -213,8 +213,9 @@ void choose_shares(const hc_query* q, const std::vector<AtomStats>& st, int K, u
 // ---------------------------------------------------------------- join (join.hip)
 void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
               const int32_t* shares, uint32_t flags, bool emit, uint64_t* count, uint64_t* digest,
-              void* out, int64_t capacity, int64_t* n_out, uint64_t* cell_counts = nullptr);
+              void* out, int64_t capacity, int64_t* n_out, uint64_t* cell_counts = nullptr,
+              int64_t n_multi = 0, const int64_t* multi_ranges = nullptr);
 uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
-                              const int32_t* shares, uint32_t flags, bool cells);
+                              const int32_t* shares, uint32_t flags, int64_t n_queries, int64_t first_width);
 
 }  // namespace hc

@@ -71,7 +71,8 @@ struct KStep {
     int32_t k_share;          // log2 share of the variable bound by this step
     int32_t cell_shift;       // bit position of its coordinate in the cell id
     int32_t has_pred;
-    int64_t pred_lo, pred_hi;
+    int64_t pred_lo, pred_hi;     // id range of the variable bound here (all entries)
+    int32_t pred_word;            // >= 0: each entry also carries its own range (lo, hi inclusive) there
     // EXPAND output
     int32_t W_out;
     int32_t n_copy;
@@ -100,6 +101,16 @@ struct Seg {
     uint32_t* m;       // its length (0 if any operand is empty)
     int64_t stride;
 };
+
+// Id predicate on the value bound by a step: the raw id (the key unmixed) must lie
+// in the step's range and, for entries that carry one, in the entry's own range.
+__device__ inline bool pred_ok(const KStep& S, const int32_t* ent, uint32_t key, const Mixer& mix) {
+    const int64_t raw = (int64_t)unmix_key(key, mix);
+    bool ok = raw >= S.pred_lo && raw < S.pred_hi;
+    if (S.pred_word >= 0)
+        ok = ok && raw >= (int64_t)(uint32_t)ent[S.pred_word] && raw <= (int64_t)(uint32_t)ent[S.pred_word + 1];
+    return ok;
+}
 
 __device__ inline const uint32_t* op_array(const KData& D, const KOp& o) {
     if (o.kind == OP_V0) return D.atoms[o.atom].V0;
@@ -254,7 +265,8 @@ struct Probe {
 };
 
 // Evaluate flattened element g: entry, value, and whether every operand holds it.
-__device__ inline void probe_item(const KData& D, const KStep& S, const Seg& G, const uint64_t* prefix, int64_t e,
+__device__ inline void probe_item(const KData& D, const KStep& S, const int32_t* F, const Seg& G,
+                                  const uint64_t* prefix, int64_t e,
                                   uint64_t g, Probe& P) {
     P.e = e;
     const int it = G.iter[e];
@@ -278,10 +290,7 @@ __device__ inline void probe_item(const KData& D, const KStep& S, const Seg& G, 
         P.pos[o] = p;
         found = p < end && arr[p] == a;
     }
-    if (found && S.has_pred) {
-        const int64_t raw = (int64_t)unmix_key(a, D.mix);
-        found = raw >= S.pred_lo && raw < S.pred_hi;
-    }
+    if (found && S.has_pred) found = pred_ok(S, F + e * S.W_in, a, D.mix);
     P.found = found;
 }
 
@@ -308,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void k_probe(KData D, KStep S, const int32_
         P.found = false;
         if (valid) {
             const uint64_t g = item_begin + rel;
-            probe_item(D, S, G, prefix, find_entry(prefix, e_lo, e_hi + 1, g), g, P);
+            probe_item(D, S, F, G, prefix, find_entry(prefix, e_lo, e_hi + 1, g), g, P);
         }
         const uint64_t bal = __ballot(P.found);
         if (MODE == M_BITMAP) {
@@ -741,10 +750,7 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                 }
 #pragma unroll
                 for (int k = 0; k < kSub; ++k) {
-                    if (f[k] && S.has_pred) {
-                        const int64_t raw = (int64_t)unmix_key(a[k], D.mix);
-                        f[k] = raw >= S.pred_lo && raw < S.pred_hi;
-                    }
+                    if (f[k] && S.has_pred) f[k] = pred_ok(S, F + e * S.W_in, a[k], D.mix);
                     const uint64_t bal = __ballot(f[k]);
                     if (kMat) {
                         if (f[k]) {
@@ -800,10 +806,7 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                         pp[o] = q;
                         found = q < el[o] && arr[o][q] == av;
                     }
-                    if (found && S.has_pred) {
-                        const int64_t raw = (int64_t)unmix_key(av, D.mix);
-                        found = raw >= S.pred_lo && raw < S.pred_hi;
-                    }
+                    if (found && S.has_pred) found = pred_ok(S, F + my_e * S.W_in, av, D.mix);
                 }
                 const uint64_t bal = __ballot(found);
                 if (kMat) {
@@ -863,7 +866,7 @@ __global__ __launch_bounds__(kBlock) void k_materialize(KData D, KStep S, const 
         if (!((bal >> lane) & 1ull)) continue;
         const uint64_t g = item_begin + rel;
         Probe P;
-        probe_item(D, S, G, prefix, find_entry(prefix, e_lo, e_hi + 1, g), g, P);
+        probe_item(D, S, F, G, prefix, find_entry(prefix, e_lo, e_hi + 1, g), g, P);
         const int64_t rank = (int64_t)(wprefix[w] + (uint64_t)__popcll(bal & lanemask_lt()));
         write_item(MODE, D, S, F + P.e * S.W_in, P.a, P.pos, rank, out);
     }
@@ -1134,6 +1137,9 @@ struct Runner {
             S.k_share = shares[PL.var];
             S.cell_shift = cell_shift[PL.var];
             S.has_pred = q->var_lo != nullptr;
+            S.pred_lo = 0;
+            S.pred_hi = INT64_MAX;
+            S.pred_word = -1;
             if (S.has_pred) {
                 S.pred_lo = q->var_lo[PL.var];
                 S.pred_hi = q->var_hi[PL.var];
@@ -1204,6 +1210,7 @@ struct Runner {
             S.k_share = shares[PG.var];
             S.cell_shift = cell_shift[PG.var];
             S.has_pred = 0;   // the predicate is applied where the variable is bound
+            S.pred_word = -1;
             S.group = g;
             S.n_src = 0;
             for (int t = 0; t < PG.n_ops; ++t)
@@ -1399,7 +1406,7 @@ void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
 
 void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order, const int32_t* shares,
               uint32_t flags, bool emit, uint64_t* count, uint64_t* digest, void* out, int64_t capacity,
-              int64_t* n_out, uint64_t* cell_counts) {
+              int64_t* n_out, uint64_t* cell_counts, int64_t n_multi, const int64_t* multi_ranges) {
     Runner R(ctx);
     R.P = compile_plan(q, order, !(flags & HC_NO_REWRITE));
     const Plan& P = R.P;
@@ -1444,6 +1451,14 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
             HC_REQUIRE(v == P.order[0] || R.shares[v] == 0, HC_ERR_INVALID,
                        "segmented CoCos: only the first variable of the order may have a share");
     }
+    if (n_multi > 0) {
+        // many queries in one pass: F_0 holds one entry per query (its index and its id
+        // range on the first variable); the per-cell counts are then per-query counts
+        HC_REQUIRE(K == 0 && R.seg_bits == 0, HC_ERR_INVALID, "query batches take no shares and no segmented CoCos");
+        HC_REQUIRE(!emit && cell_counts != nullptr && multi_ranges != nullptr, HC_ERR_INVALID,
+                   "query batches are a per-query counting mode");
+        HC_REQUIRE(n_multi <= ((int64_t)1 << 24), HC_ERR_INVALID, "more than 2^24 queries in one batch");
+    }
     R.K = K;
     {
         // cell id: the first variable of the order in the low bits, the deepest in the
@@ -1476,7 +1491,18 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
     R.split = DevBuf<int64_t>(R.A, 2);
     HC_HIP(hipMemsetAsync(R.acc.p, 0, sizeof(unsigned long long) * 4, R.s));
     R.setup_layouts();
+    // query batches: F_0 entries end with the query's id range (lo, hi inclusive) on
+    // the first variable; word 0 (the cell) is the query index
+    const int range_word = R.lay[0].W;
+    if (n_multi > 0) {
+        R.lay[0].W += 2;
+        HC_REQUIRE(R.lay[0].W <= kMaxW, HC_ERR_UNSUPPORTED, "frontier entry too wide");
+    }
     R.setup_steps(q);
+    if (n_multi > 0) {
+        R.level_step[0].has_pred = 1;
+        R.level_step[0].pred_word = range_word;
+    }
     R.refresh_tmp_ptrs();
     if (ctx->profiling) {
         HC_HIP(hipEventCreate(&R.ev0));
@@ -1488,8 +1514,8 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
         HC_HIP(hipEventCreate(&t1));
         HC_HIP(hipEventRecord(t0, R.s));
     }
-    // F_0: one entry per cell
-    const int64_t ncell = (int64_t)1 << K;
+    // F_0: one entry per cell (per query of a batch)
+    const int64_t ncell = n_multi > 0 ? n_multi : (int64_t)1 << K;
     DevBuf<unsigned long long> cells;
     if (cell_counts) {
         HC_REQUIRE(!emit, HC_ERR_INVALID, "per-cell counts are a counting mode");
@@ -1498,8 +1524,23 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
         R.cell_out = cells.p;
     }
     DevBuf<int32_t> F0(R.A, (size_t)ncell * (size_t)R.lay[0].W);
-    k_init_cells<<<grid_for(ncell), kBlock, 0, R.s>>>(F0.p, ncell, R.lay[0].W);
-    HC_HIP(hipGetLastError());
+    std::vector<int32_t> f0_host;
+    if (n_multi > 0) {
+        const int W0 = R.lay[0].W;
+        f0_host.assign((size_t)ncell * W0, 0);   // lifted-intersection references start empty
+        for (int64_t t = 0; t < ncell; ++t) {
+            const int64_t lo = std::max<int64_t>(multi_ranges[2 * t], 0);
+            const int64_t hi = std::min<int64_t>(multi_ranges[2 * t + 1], (int64_t)1 << 32);
+            int32_t* e = f0_host.data() + (size_t)t * W0;
+            e[0] = (int32_t)t;
+            e[range_word] = (int32_t)(uint32_t)(lo < hi ? lo : 1);       // empty range: lo 1 > hi 0
+            e[range_word + 1] = (int32_t)(uint32_t)(lo < hi ? hi - 1 : 0);
+        }
+        HC_HIP(hipMemcpyAsync(F0.p, f0_host.data(), sizeof(int32_t) * f0_host.size(), hipMemcpyHostToDevice, R.s));
+    } else {
+        k_init_cells<<<grid_for(ncell), kBlock, 0, R.s>>>(F0.p, ncell, R.lay[0].W);
+        HC_HIP(hipGetLastError());
+    }
     R.run_level(0, F0.p, F0.p, ncell);
     unsigned long long a[3] = {0, 0, 0};
     HC_HIP(hipMemcpyAsync(a, R.acc.p, sizeof(a), hipMemcpyDeviceToHost, R.s));
@@ -1539,7 +1580,7 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
 // times the longest list of level i's shortest operand (a predicate bounds it by
 // its id range), and every frontier chunk by the chunking cap.
 uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
-                              const int32_t* shares, uint32_t flags, bool cells) {
+                              const int32_t* shares, uint32_t flags, int64_t n_queries, int64_t first_width) {
     const Plan P = compile_plan(q, order, !(flags & HC_NO_REWRITE));
     constexpr double kCap = (double)((int64_t)1 << 27);   // frontier entries / pool elements per chunk
     int K = 0;
@@ -1554,7 +1595,9 @@ uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, co
         for (int t = 0; t < P.groups[g].n_ops; ++t) m = std::min(m, op_max(P.groups[g].ops[t]));
         gmax[g] = m;
     }
-    double E = std::ldexp(1.0, K), bytes = 0;
+    double E = n_queries > 0 ? (double)n_queries : std::ldexp(1.0, K);
+    double bytes = (double)(1 << 20);   // allocation granularity of the many small buffers
+    bytes += 8.0 * E + (n_queries > 0 ? 12.0 * E : 0.0);   // per-cell (per-query) counts, query ranges
     for (int i = 0; i < P.n_vars; ++i) {
         const PlanLevel& L = P.levels[i];
         double m = 1e30;
@@ -1562,9 +1605,10 @@ uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, co
             m = std::min(m, L.ops[t].kind == OP_TMP ? gmax[L.ops[t].group] : op_max(L.ops[t]));
         if (q->var_lo && q->var_hi && q->var_hi[L.var] > q->var_lo[L.var])
             m = std::min(m, (double)q->var_hi[L.var] - (double)q->var_lo[L.var]);
+        if (i == 0 && n_queries > 0 && first_width > 0) m = std::min(m, (double)first_width);
         const double n = std::min(E, kCap);
         const Layout Li = make_layout(P, i);
-        bytes += n * 4.0 * Li.W;                               // F_i
+        bytes += n * 4.0 * (Li.W + (i == 0 && n_queries > 0 ? 2 : 0));   // F_i
         bytes += n * (8.0 * L.n_ops + 13.0) + 8.0;             // ranges, iterated operand, length, prefix
         for (int g = 0; g < P.n_groups; ++g) {
             if (P.groups[g].lift != i) continue;
@@ -1577,7 +1621,6 @@ uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, co
         bytes += (items / 2048 + 1) * 8.0 + 64.0;                                  // work-queue chunk table
         E = std::min(E * m, 1e18);
     }
-    if (cells) bytes += std::ldexp(8.0, K);
     return (uint64_t)std::min(bytes, 1.8e19);
 }
 

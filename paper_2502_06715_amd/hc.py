@@ -11,7 +11,7 @@ from __future__ import annotations
 import ctypes
 import json
 import os
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 from typing import Optional, Sequence
 
 import numpy as np
@@ -75,7 +75,8 @@ SIGNATURES = {
     "hc_join_count": (ctypes.c_int, [P, P, P, P, P, U32, P, P]),
     "hc_join_emit": (ctypes.c_int, [P, P, P, P, P, U32, P, I64, P]),
     "hc_join_count_cells": (ctypes.c_int, [P, P, P, P, P, U32, P, P]),
-    "hc_join_workspace_bound": (ctypes.c_int, [P, P, P, P, P, U32, I32, P]),
+    "hc_join_workspace_bound": (ctypes.c_int, [P, P, P, P, P, U32, I64, I64, P]),
+    "hc_join_count_multi": (ctypes.c_int, [P, P, P, P, U32, I64, P, P]),
     "hc_plan_describe": (ctypes.c_int, [P, P, U32, P, ctypes.c_size_t]),
     "hc_ctx_set_profiling": (ctypes.c_int, [P, ctypes.c_int]),
     "hc_ctx_get_timing": (ctypes.c_int, [P, P]),
@@ -106,7 +107,6 @@ class Query:
     atoms: Sequence[Sequence[int]]
     var_lo: Optional[Sequence[int]] = None
     var_hi: Optional[Sequence[int]] = None
-    _keep: list = field(default_factory=list, repr=False)
 
     def c(self) -> _Query:
         ar = np.array([len(a) for a in self.atoms], dtype=np.int32)
@@ -118,7 +118,7 @@ class Query:
             hi = np.array(self.var_hi, dtype=np.int64)
             q.var_lo, q.var_hi = lo.ctypes.data, hi.ctypes.data
             keep += [lo, hi]
-        self._keep = keep
+        q._keep = keep   # the arrays live as long as the struct (thread-safe for shared queries)
         return q
 
 
@@ -301,16 +301,29 @@ def join_count_cells(ctx: Context, q: Query, cocos, order, log2_shares, flags: i
 
 
 def join_workspace_bound(ctx: Context, q: Query, cocos, order, log2_shares=None, flags: int = 0,
-                         per_cell: bool = False) -> int:
-    """Upper bound (bytes) of the device memory one count call allocates."""
+                         n_queries: int = 0, first_width: int = 0) -> int:
+    """Upper bound (bytes) of the device memory of one count call (n_queries = 0) or
+    of one join_count_multi call over n_queries ranges at most first_width wide."""
     order_a = _i32(order)
     sh = _i32(log2_shares) if log2_shares is not None else None
     out = ctypes.c_uint64(0)
     qc = q.c()
     ctx.check(lib().hc_join_workspace_bound(ctx.h, ctypes.byref(qc), _handles(cocos), order_a.ctypes.data,
-                                            sh.ctypes.data if sh is not None else None, flags, int(per_cell),
-                                            ctypes.byref(out)))
+                                            sh.ctypes.data if sh is not None else None, flags, int(n_queries),
+                                            int(first_width), ctypes.byref(out)))
     return int(out.value)
+
+
+def join_count_multi(ctx: Context, q: Query, cocos, order, ranges, flags: int = 0) -> np.ndarray:
+    """Counts of q with its first variable restricted to each [lo, hi) of ranges,
+    in one pass (numpy uint64 array)."""
+    order_a = _i32(order)
+    r = np.ascontiguousarray(np.asarray(ranges, dtype=np.int64).reshape(-1, 2))
+    counts = np.zeros(max(r.shape[0], 1), dtype=np.uint64)
+    qc = q.c()
+    ctx.check(lib().hc_join_count_multi(ctx.h, ctypes.byref(qc), _handles(cocos), order_a.ctypes.data, flags,
+                                        r.shape[0], r.ctypes.data, counts.ctypes.data))
+    return counts[: r.shape[0]]
 
 
 def join_emit(ctx: Context, q: Query, cocos, order, log2_shares=None, flags: int = 0, capacity: int = None,

@@ -257,8 +257,9 @@ def batch_graph(spec) -> np.ndarray:
     return rmat(spec["n"].bit_length() - 1, spec["m"], spec["seed"])
 
 
-def batch_graphs(specs, workers: int = 0):
-    """Graphs of a batch, generated in parallel processes (each is a pure function of its spec)."""
+def parallel_graphs(fn, specs, workers: int = 0):
+    """fn(spec) for every spec, in parallel processes (each graph is a pure function
+    of its spec)."""
     import os
     from concurrent.futures import ProcessPoolExecutor
     if workers <= 0:
@@ -266,7 +267,59 @@ def batch_graphs(specs, workers: int = 0):
             workers = min(16, len(os.sched_getaffinity(0)))
         except AttributeError:
             workers = min(16, os.cpu_count() or 1)
-    if workers == 1 or len(specs) < 8:
-        return [batch_graph(s) for s in specs]
-    with ProcessPoolExecutor(max_workers=workers) as ex:
-        return list(ex.map(batch_graph, specs, chunksize=8))
+    if workers == 1 or len(specs) < 2:
+        return [fn(s) for s in specs]
+    with ProcessPoolExecutor(max_workers=min(workers, len(specs))) as ex:
+        return list(ex.map(fn, specs, chunksize=max(1, len(specs) // (4 * workers))))
+
+
+def batch_graphs(specs, workers: int = 0):
+    """Graphs of a batch, generated in parallel processes."""
+    return parallel_graphs(batch_graph, specs, workers)
+
+
+# ---------------------------------------------------------------- served workload
+STREAM_SALT = 0x5354_5245_414D_5121   # separates the request stream from the graph streams
+SERVE_MIX = (("triangle", 0.5), ("cycle4", 0.3), ("clique4", 0.2))
+
+
+def serve_graph_specs(n_graphs: int = 16, log2_lo: float = 16.0, log2_hi: float = 24.0):
+    """The resident graphs of the served workload: R-MAT graph g has
+    m_g = round(2^(log2_lo + (log2_hi - log2_lo) g / (n_graphs - 1))) undirected
+    edges and 2^scale vertices with 2^scale = next_pow2(m_g / 16) (edge factor 16)."""
+    out = []
+    for g in range(n_graphs):
+        t = g / (n_graphs - 1) if n_graphs > 1 else 0.0
+        m = int(round(2.0 ** (log2_lo + (log2_hi - log2_lo) * t)))
+        n = _next_pow2(m / 16.0)
+        out.append({"g": g, "kind": "rmat", "m": m, "n": n, "seed": SEED_SERVE + g})
+    return out
+
+
+def serve_graph(spec) -> np.ndarray:
+    return rmat(spec["n"].bit_length() - 1, spec["m"], spec["seed"])
+
+
+def serve_stream(graph_specs, n_requests: int = 20000, qps: float = 2000.0, seed: int = SEED_SERVE,
+                 max_log2_width: int = 4):
+    """Requests of the served workload, in arrival order.  Request i draws 4 numbers
+    from stream seed ^ STREAM_SALT (draws 4i .. 4i+3): the inter-arrival gap
+    -ln(1 - U)/qps (a Poisson process), the shape (50% triangle, 30% 4-cycle, 20%
+    4-clique), the graph (uniform), and the block of first-variable ids it asks
+    about: width 2^u (u uniform in 0..max_log2_width, from the top 24 bits of draw 3),
+    start uniform over the graph's vertex ids (from its low 40 bits).  Each request counts the query's tuples whose first
+    variable lies in [lo, lo + width)."""
+    r = splitmix64(seed ^ STREAM_SALT, 0, 4 * n_requests).reshape(n_requests, 4)
+    u = _unit_double(r.reshape(-1)).reshape(n_requests, 4)
+    t = np.cumsum(-np.log1p(-u[:, 0]) / qps)
+    cum = np.cumsum([p for _, p in SERVE_MIX])
+    out = []
+    for i in range(n_requests):
+        k = int(np.searchsorted(cum, u[i, 1], side="right"))
+        shape = SERVE_MIX[min(k, len(SERVE_MIX) - 1)][0]
+        g = min(int(u[i, 2] * len(graph_specs)), len(graph_specs) - 1)
+        n = graph_specs[g]["n"]
+        w = 1 << (((int(r[i, 3]) >> 40) * (max_log2_width + 1)) >> 24)
+        lo = int(((int(r[i, 3]) & ((1 << 40) - 1)) * (n - w + 1)) >> 40) if n > w else 0
+        out.append({"id": i, "t": float(t[i]), "query": shape, "graph": g, "lo": lo, "hi": lo + w})
+    return out
