@@ -196,7 +196,8 @@ struct Plan {
 };
 
 // Validates q and order; builds the per-level plan with (optionally) the lift rule.
-Plan compile_plan(const hc_query* q, const int32_t* order, bool rewrite);
+// Intersections that would be lifted to a frontier below min_lift stay where they are.
+Plan compile_plan(const hc_query* q, const int32_t* order, bool rewrite, int min_lift = 0);
 std::string describe_plan(const Plan& p);
 // Validate the query alone (variables covered, arities, repeated variables).
 void validate_query(const hc_query* q, int max_arity);

@@ -59,7 +59,8 @@ struct KOp {
     int32_t word;     // CHILD: entry word of the parent node; TMP: entry word of (offset, length)
     int32_t group;    // TMP
     const int2* v0_range;   // V0 restricted by the cell: table indexed by the coordinate (or null)
-    int32_t rng_shift, rng_k;     // coordinate = (cell >> rng_shift) & (2^rng_k - 1)
+    int32_t rng_shift, rng_k;     // coordinate = (src >> rng_shift) & (2^rng_k - 1), src = the cell id
+    int32_t rng_word;             // or, when >= 0, this word of the entry (a bound key, a query's id range)
     const int32_t* child_range;   // CHILD: per node, start of every coordinate's sub-range (or null)
     int32_t child_stride;         // 2^k + 1 entries per node
 };
@@ -202,7 +203,8 @@ __global__ __launch_bounds__(kBlock) void k_prep(KData D, KStep S, const int32_t
             int64_t beg, end;
             if (op.kind == OP_V0) {
                 if (op.v0_range) {
-                    const int2 r = op.v0_range[(cell >> op.rng_shift) & ((1u << op.rng_k) - 1u)];
+                    const uint32_t src = op.rng_word >= 0 ? (uint32_t)ent[op.rng_word] : cell;
+                    const int2 r = op.v0_range[(src >> op.rng_shift) & ((1u << op.rng_k) - 1u)];
                     beg = r.x;
                     end = r.y;
                 } else {
@@ -1024,6 +1026,7 @@ struct Runner {
     int K;
     bool emit, digest;
     int seg_bits = 0;                        // key bits above the mixed bits (batched queries)
+    int range_word = -1;                     // F_0 word of a query batch's id ranges
     unsigned long long* cell_out = nullptr;  // per-cell counts (device), or null
     int64_t cap_entries;
     DevBuf<unsigned long long> acc;
@@ -1064,7 +1067,7 @@ struct Runner {
         }
     }
 
-    KOp make_op(const PlanOp& po, const Layout& L, int var) {
+    KOp make_op(const PlanOp& po, const Layout& L, int var, int fi) {
         KOp o{};
         o.kind = po.kind;
         o.atom = po.atom;
@@ -1077,16 +1080,27 @@ struct Runner {
         o.child_stride = 0;
         o.rng_shift = 0;
         o.rng_k = 0;
-        int vk = 0, vshift = 0;
+        o.rng_word = -1;
+        int vk = 0, vshift = 0, vword = -1;
         if (po.kind == OP_V0 && shares[var] > 0) {
             vk = shares[var];
             vshift = cell_shift[var];
         } else if (po.kind == OP_V0 && seg_bits > 0) {
-            // segmented keys: every variable stays inside the segment of the first
-            // variable's coordinate (its top seg_bits bits)
-            const int v0 = P.order[0];
+            // segmented keys: every variable stays inside the segment (the key bits
+            // above the mixed bits) of the first variable's value; below F_1 that value
+            // is not bound yet, and the segment comes from the query's id range (a batch
+            // of queries) or from the first variable's cell coordinate
             vk = seg_bits;
-            vshift = cell_shift[v0] + shares[v0] - seg_bits;
+            if (fi >= 1) {
+                vshift = D.mix.b;
+                vword = 1;
+            } else if (range_word >= 0) {
+                vshift = D.mix.b;
+                vword = range_word;
+            } else {
+                const int v0 = P.order[0];
+                vshift = cell_shift[v0] + shares[v0] - seg_bits;
+            }
         }
         if (vk > 0) {
             ranges.emplace_back(A, (size_t)1 << vk);
@@ -1096,6 +1110,7 @@ struct Runner {
             o.v0_range = ranges.back().p;
             o.rng_k = vk;
             o.rng_shift = vshift;
+            o.rng_word = vword;
         }
         if (po.kind == OP_CHILD && shares[var] > 0) {
             // sub-range boundaries of every child list for every coordinate, when the
@@ -1132,7 +1147,7 @@ struct Runner {
             const Layout& Li = lay[i];
             const Layout& Lo = lay[i + 1];
             S.n_ops = PL.n_ops;
-            for (int t = 0; t < PL.n_ops; ++t) S.ops[t] = make_op(PL.ops[t], Li, PL.var);
+            for (int t = 0; t < PL.n_ops; ++t) S.ops[t] = make_op(PL.ops[t], Li, PL.var, i);
             S.W_in = Li.W;
             S.k_share = shares[PL.var];
             S.cell_shift = cell_shift[PL.var];
@@ -1205,7 +1220,7 @@ struct Runner {
             S = KStep{};
             const Layout& L = lay[PG.lift];
             S.n_ops = PG.n_ops;
-            for (int t = 0; t < PG.n_ops; ++t) S.ops[t] = make_op(PG.ops[t], L, PG.var);
+            for (int t = 0; t < PG.n_ops; ++t) S.ops[t] = make_op(PG.ops[t], L, PG.var, PG.lift);
             S.W_in = L.W;
             S.k_share = shares[PG.var];
             S.cell_shift = cell_shift[PG.var];
@@ -1408,7 +1423,9 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
               uint32_t flags, bool emit, uint64_t* count, uint64_t* digest, void* out, int64_t capacity,
               int64_t* n_out, uint64_t* cell_counts, int64_t n_multi, const int64_t* multi_ranges) {
     Runner R(ctx);
-    R.P = compile_plan(q, order, !(flags & HC_NO_REWRITE));
+    // A batch of queries has one F_0 entry per query: an intersection of whole top
+    // levels lifted to F_0 would be recomputed for every query, so it is not lifted.
+    R.P = compile_plan(q, order, !(flags & HC_NO_REWRITE), n_multi > 0 ? 1 : 0);
     const Plan& P = R.P;
     // CoCos: same key width and mixer, columns ordered by the variable order
     int b = -1, mb = -1;
@@ -1442,7 +1459,7 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
     }
     HC_REQUIRE(K <= 24, HC_ERR_INVALID, "more than 2^24 cells");
     R.seg_bits = b - mb;
-    if (R.seg_bits > 0) {
+    if (R.seg_bits > 0 && n_multi <= 0) {
         // segmented keys (batched queries): the first variable's coordinate must name
         // the segment, and no other variable may be split
         HC_REQUIRE(R.shares[P.order[0]] >= R.seg_bits, HC_ERR_INVALID,
@@ -1454,7 +1471,16 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
     if (n_multi > 0) {
         // many queries in one pass: F_0 holds one entry per query (its index and its id
         // range on the first variable); the per-cell counts are then per-query counts
-        HC_REQUIRE(K == 0 && R.seg_bits == 0, HC_ERR_INVALID, "query batches take no shares and no segmented CoCos");
+        HC_REQUIRE(K == 0, HC_ERR_INVALID, "query batches take no shares");
+        if (R.seg_bits > 0) {
+            // with segmented CoCos every query stays inside one segment
+            for (int64_t t = 0; t < n_multi; ++t) {
+                const int64_t lo = std::max<int64_t>(multi_ranges[2 * t], 0);
+                const int64_t hi = std::min<int64_t>(multi_ranges[2 * t + 1], (int64_t)1 << b);
+                HC_REQUIRE(lo >= hi || (lo >> mb) == ((hi - 1) >> mb), HC_ERR_INVALID,
+                           "a query's id range spans two segments (query " + std::to_string(t) + ")");
+            }
+        }
         HC_REQUIRE(!emit && cell_counts != nullptr && multi_ranges != nullptr, HC_ERR_INVALID,
                    "query batches are a per-query counting mode");
         HC_REQUIRE(n_multi <= ((int64_t)1 << 24), HC_ERR_INVALID, "more than 2^24 queries in one batch");
@@ -1495,6 +1521,7 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
     // the first variable; word 0 (the cell) is the query index
     const int range_word = R.lay[0].W;
     if (n_multi > 0) {
+        R.range_word = range_word;
         R.lay[0].W += 2;
         HC_REQUIRE(R.lay[0].W <= kMaxW, HC_ERR_UNSUPPORTED, "frontier entry too wide");
     }
@@ -1581,7 +1608,7 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
 // its id range), and every frontier chunk by the chunking cap.
 uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
                               const int32_t* shares, uint32_t flags, int64_t n_queries, int64_t first_width) {
-    const Plan P = compile_plan(q, order, !(flags & HC_NO_REWRITE));
+    const Plan P = compile_plan(q, order, !(flags & HC_NO_REWRITE), n_queries > 0 ? 1 : 0);
     constexpr double kCap = (double)((int64_t)1 << 27);   // frontier entries / pool elements per chunk
     int K = 0;
     for (int v = 0; v < P.n_vars; ++v) K += shares ? shares[v] : 0;

@@ -52,7 +52,7 @@ static void check_order(const hc_query* q, const int32_t* order) {
 // level i-1 iterates; when two or more exist, their intersection is lifted to
 // frontier F_{max d + 1} (computed once per binding of levels <= max d) and
 // consumed at level i as one temporary operand (Section 6.1).
-Plan compile_plan(const hc_query* q, const int32_t* order, bool rewrite) {
+Plan compile_plan(const hc_query* q, const int32_t* order, bool rewrite, int min_lift) {
     validate_query(q, 2);
     check_order(q, order);
     Plan p;
@@ -102,7 +102,7 @@ Plan compile_plan(const hc_query* q, const int32_t* order, bool rewrite) {
         PlanLevel& L = p.levels[i];
         L.var = x;
         L.n_ops = 0;
-        if (rewrite && n_low >= 2) {
+        if (rewrite && n_low >= 2 && max_low + 1 >= min_lift) {
             HC_REQUIRE(p.n_groups < kMaxGroups, HC_ERR_UNSUPPORTED, "too many lifted intersections");
             PlanGroup& g = p.groups[p.n_groups];
             g.var = x;

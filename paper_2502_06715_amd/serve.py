@@ -54,17 +54,19 @@ class Request:
     batch: int = 0                # size of the pass that answered it
     done: threading.Event = field(default_factory=threading.Event, repr=False)
 
-    @property
-    def key(self) -> Key:
-        return (self.graph, self.query)
 
 
 class GpuEngine:
-    """Resident CoCos and one library context (own stream) per slot."""
+    """Resident CoCos and one library context (own stream) per slot.
 
-    def __init__(self, graphs: List[np.ndarray], n_slots: int, device: int = 0):
+    With ``shared_index`` all graphs live in one segmented CoCo (graph g's ids carry
+    g above the vertex bits), so the waiting requests of one shape over every graph
+    fuse into one pass; otherwise each graph has its own CoCo and a pass covers one
+    (graph, shape)."""
+
+    def __init__(self, graphs: List[np.ndarray], n_slots: int, device: int = 0, shared_index: bool = False):
         import torch
-        from . import hc
+        from . import batch, hc
         self.hc = hc
         self.torch = torch
         self.dev = torch.device("cuda:%d" % device)
@@ -74,30 +76,47 @@ class GpuEngine:
         self.est_ctx = hc.Context(device, stream=self.streams[0])   # estimates run under the scheduler lock
         self.cocos = []
         self.index_bytes = 0
-        self.max_id = []
+        self.shared = shared_index
+        self.mix_bits = 0
         with torch.cuda.stream(self.streams[0]):
-            for g in graphs:
-                t = torch.from_numpy(np.ascontiguousarray(g)).to(self.dev)
-                c = hc.build_coco(self.ctxs[0], t, [0, 1], symmetric=True)
+            if shared_index:
+                self.mix_bits = batch.id_bits(graphs)
+                rel, seg = batch.union_relation(graphs, self.mix_bits)
+                t = torch.from_numpy(rel).to(self.dev)
+                self.cocos.append(hc.build_coco(self.ctxs[0], t, [0, 1], key_bits=self.mix_bits, segment_bits=seg,
+                                                symmetric=True))
                 self.streams[0].synchronize()
                 del t
-                self.cocos.append(c)
-                self.index_bytes += int(c.info.bytes)
-                self.max_id.append(int(g.max()) if g.shape[0] else 0)
+            else:
+                for g in graphs:
+                    t = torch.from_numpy(np.ascontiguousarray(g)).to(self.dev)
+                    self.cocos.append(hc.build_coco(self.ctxs[0], t, [0, 1], symmetric=True))
+                    self.streams[0].synchronize()
+                    del t
+        self.index_bytes = sum(int(c.info.bytes) for c in self.cocos)
         self._q = {name: hc.Query(*inputs.QUERIES[name]) for name in inputs.QUERIES}
 
-    def _args(self, key: Key):
-        g, shape = key
-        n, atoms = inputs.QUERIES[shape]
-        return self._q[shape], [self.cocos[g]] * len(atoms), list(range(n))
+    def group_key(self, r: "Request"):
+        return r.query if self.shared else (r.graph, r.query)
 
-    def estimate(self, key: Key, n: int, width: int) -> int:
+    def _range(self, r: "Request") -> Tuple[int, int]:
+        off = (r.graph << self.mix_bits) if self.shared else 0
+        return off + r.lo, off + r.hi
+
+    def _args(self, key):
+        shape = key if self.shared else key[1]
+        coco = self.cocos[0] if self.shared else self.cocos[key[0]]
+        n, atoms = inputs.QUERIES[shape]
+        return self._q[shape], [coco] * len(atoms), list(range(n))
+
+    def estimate(self, key, n: int, width: int) -> int:
         q, cs, order = self._args(key)
         return self.hc.join_workspace_bound(self.est_ctx, q, cs, order, None, 0, n_queries=n, first_width=width)
 
-    def run(self, slot: int, key: Key, ranges: List[Tuple[int, int]], fused: bool) -> List[int]:
+    def run(self, slot: int, key, reqs: List["Request"], fused: bool) -> List[int]:
         q, cs, order = self._args(key)
         ctx = self.ctxs[slot]
+        ranges = [self._range(r) for r in reqs]
         if fused:
             return [int(c) for c in self.hc.join_count_multi(ctx, q, cs, order, ranges)]
         out = []
@@ -161,8 +180,8 @@ class Server:
         """Under the lock: the next pass (key, batch, reserved bytes), or None."""
         while self.pending:
             head = self.pending[0]
-            key = head.key
-            batch = [r for r in self.pending if r.key == key][: self.max_batch]
+            key = self.engine.group_key(head)
+            batch = [r for r in self.pending if self.engine.group_key(r) == key][: self.max_batch]
             while True:
                 width = max(r.hi - r.lo for r in batch)
                 est = int(self.engine.estimate(key, len(batch), max(width, 1)))
@@ -199,7 +218,7 @@ class Server:
             t_admit = self.clock() - self.t0
             err = None
             try:
-                counts = self.engine.run(slot, key, [(r.lo, r.hi) for r in batch], self.fuse)
+                counts = self.engine.run(slot, key, batch, self.fuse)
             except Exception as e:   # reported per request; the slot keeps serving
                 counts, err = [None] * len(batch), "%s: %s" % (type(e).__name__, e)
             t_done = self.clock() - self.t0

@@ -92,26 +92,47 @@ def test_workspace_bound_covers_the_peak(ctx, graph):
     coco.free()
 
 
-def test_server_mix_equals_alone(ctx):
+@pytest.mark.parametrize("shared", [False, True])
+def test_server_mix_equals_alone(ctx, shared):
     """Requests answered by the serving loop (3 slots on their own streams, fused
-    passes, admission by the workspace bound) equal the same requests run alone,
-    one per launch, and the oracle on a sample."""
+    passes, admission by the workspace bound; one CoCo per graph, or all graphs in
+    one segmented CoCo) equal the same requests run alone, one per launch on
+    per-graph CoCos, and the oracle on a sample."""
     specs = inputs.serve_graph_specs(n_graphs=3, log2_lo=11.0, log2_hi=13.0)
     graphs = [inputs.serve_graph(s) for s in specs]
     stream = inputs.serve_stream(specs, 400, qps=20000.0, seed=inputs.SEED_SERVE + 99)
-    eng = serve.GpuEngine(graphs, n_slots=3)
+    eng = serve.GpuEngine(graphs, n_slots=3, shared_index=shared)
+    ref = serve.GpuEngine(graphs, n_slots=1) if shared else eng
     srv = serve.Server(eng, budget_bytes=16 << 30, n_slots=3, max_batch=64)
     reqs = serve.requests_from_stream(stream)
     wall = serve.replay(srv, reqs)
     summ = serve.summarize(reqs, wall)
-    log("served %s" % summ)
+    log("served (shared index %s) %s" % (shared, summ))
     assert summ["answered"] == len(reqs) and summ["mean_batch"] > 1.0
     for r in reqs:
-        alone = eng.run(0, r.key, [(r.lo, r.hi)], fused=False)[0]
+        alone = ref.run(0, ref.group_key(r), [r], fused=False)[0]
         assert r.count == alone, (r, alone)
     for r in reqs[:40]:
         n, atoms = inputs.QUERIES[r.query]
         exp = oracle.gj(n, atoms, [graphs[r.graph]] * len(atoms), lo=[r.lo] + [0] * (n - 1),
                         hi=[r.hi] + [BIG] * (n - 1)).count
         assert r.count == exp
+    if shared:
+        ref.close()
     eng.close()
+
+
+def test_batch_ranges_must_stay_in_one_segment(ctx):
+    import torch
+    from paper_2502_06715_amd import batch
+    gs = [inputs.rmat(8, 600, 5), inputs.rmat(8, 700, 6)]
+    mb = batch.id_bits(gs)
+    rel, seg = batch.union_relation(gs, mb)
+    c = hc.build_coco(ctx, torch.from_numpy(rel).to("cuda:0"), [0, 1], key_bits=mb, segment_bits=seg,
+                      symmetric=True)
+    q = hc.Query(*inputs.QUERIES["triangle"])
+    with pytest.raises(hc.HCError):
+        hc.join_count_multi(ctx, q, [c] * 3, [0, 1, 2], [((1 << mb) - 4, (1 << mb) + 4)])
+    got = hc.join_count_multi(ctx, q, [c] * 3, [0, 1, 2], [(0, 1 << mb), (1 << mb, 2 << mb)])
+    assert [int(x) for x in got] == [6 * oracle.textbook_triangles(g) for g in gs]
+    c.free()

@@ -22,10 +22,15 @@ class FakeEngine:
         self.reserved_now = 0
         self.est_of = {}
 
+    def group_key(self, r):
+        return (r.graph, r.query)
+
     def estimate(self, key, n, width):
         return self.per_query * n + width
 
-    def run(self, slot, key, ranges, fused):
+    def run(self, slot, key, reqs, fused):
+        assert all(self.group_key(r) == key for r in reqs)
+        ranges = [(r.lo, r.hi) for r in reqs]
         with self.lock:
             self.passes.append((slot, key, list(ranges), fused))
         if self.delay:
@@ -50,7 +55,6 @@ def test_every_request_answered_with_its_own_count():
     wall = serve.replay(srv, reqs)
     assert all(r.error is None and r.count == r.lo * 7 + r.hi for r in reqs)
     # a pass only holds requests of one (graph, shape)
-    by_id = {(r.lo, r.hi, r.key): r for r in reqs}
     for slot, key, ranges, fused in eng.passes:
         assert fused and len(ranges) <= 64
     assert sum(len(p[2]) for p in eng.passes) == len(reqs)
