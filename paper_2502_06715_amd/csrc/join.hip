@@ -418,7 +418,7 @@ constexpr int kSub = 4;         // 64-element chunks per cursor step
 constexpr int kTiny = 24;       // counting modes: entries shorter than this take the per-lane path
 constexpr uint64_t kChunk = 2048;       // elements per work-queue chunk
 constexpr int kXcd = 8;                 // XCDs of an MI355X
-constexpr uint64_t kPersistBlocks = 2048;
+constexpr uint64_t kPersistBlocks = 2048;   // 8 workgroups of 4 waves per CU: 8 waves per SIMD
 
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -543,7 +543,7 @@ __device__ inline int32_t lower_bound32(const uint32_t* __restrict__ B, int32_t 
 }
 
 template <int MODE, int NOPS>
-__global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32_t* __restrict__ F, Seg G,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_probe2(KData D, KStep S, const int32_t* __restrict__ F, Seg G,
                                                    const uint64_t* __restrict__ prefix, int64_t e_begin,
                                                    int64_t e_end, uint64_t item_begin, uint64_t n_items,
                                                    const int64_t* __restrict__ chunk_entry,
@@ -598,13 +598,45 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                 cur[o] = beg[o];
             }
         };
+        // the descriptor of the entry after e, loaded one step ahead so that its
+        // latency hides behind the current step
+        uint64_t nx_pe1 = 0;
+        int32_t nx_it = 0, nx_beg[NOPS], nx_end[NOPS];
+        auto prefetch_next = [&](int64_t ee) {
+            nx_pe1 = 0;
+            if (ee + 1 < e_end) {
+                nx_pe1 = prefix[ee + 2];
+                nx_it = G.iter[ee + 1];
+#pragma unroll
+                for (int o = 0; o < NOPS; ++o) {
+                    nx_beg[o] = G.seg[(2 * o) * stride + ee + 1];
+                    nx_end[o] = G.seg[(2 * o + 1) * stride + ee + 1];
+                }
+            }
+        };
         load_entry(e);
+        prefetch_next(e);
         uint64_t rc = r_begin;
         while (rc < r_end) {
             const uint64_t g = item_begin + rc;
             if (pe1 <= g) {   // move to the entry holding g
-                e = (int64_t)uni64((uint64_t)advance_entry(prefix, e + 1, e_end, g));
-                load_entry(e);
+                const uint64_t np1 = uni64(nx_pe1);
+                if (np1 > g) {   // the next entry holds g (the usual case): use the prefetch
+                    ++e;
+                    pe0 = pe1;
+                    pe1 = np1;
+                    it = uni(nx_it);
+#pragma unroll
+                    for (int o = 0; o < NOPS; ++o) {
+                        beg[o] = uni(nx_beg[o]);
+                        end[o] = uni(nx_end[o]);
+                        cur[o] = beg[o];
+                    }
+                } else {
+                    e = (int64_t)uni64((uint64_t)advance_entry(prefix, e + 1, e_end, g));
+                    load_entry(e);
+                }
+                prefetch_next(e);
             }
             const uint64_t left_wave = r_end - rc;
             const uint64_t left_entry = pe1 - g;
@@ -690,65 +722,81 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                         }
                         continue;
                     }
-                    // ---- long operand: a window of the list from the cursor on
+                    // ---- long operand: the step's values a_first .. a_last have their lower
+                    // bounds in [lo, hi], found by two wave searches from the cursor.  The
+                    // range is staged in LDS when it fits; otherwise every s-th element
+                    // is (fences), and each value finishes with a search of its s-element
+                    // bucket in place.
 #pragma unroll
                     for (int u = 0; u < NOPS; ++u) wc_ptr[u] = nullptr;   // the window overwrites every region
+                    uint32_t a_last = 0;
+#pragma unroll
+                    for (int k = 0; k < kSub; ++k) {
+                        const uint32_t t = __shfl(a[k], last & 63, 64);
+                        if (k == (last >> 6)) a_last = t;
+                    }
+                    a_last = (uint32_t)uni((int32_t)a_last);
                     const int32_t lo = uni(wave_search(B, cur[o], end[o], a_first, lane));
-                    const int32_t avail = end[o] - lo;
-                    // window sized by this step's share of the entry's remaining elements
-                    uint64_t est = (uint64_t)nsc * (uint64_t)avail / (pe1 - g);
-                    est += (est >> 2) + 64;
-                    int32_t len = avail < kWin - 4 ? avail : kWin - 4;
-                    if ((int64_t)est < len) len = (int32_t)est;
-                    len = uni(len);
-                    // The window starts at the 16-byte boundary below lo (16-byte loads);
-                    // its first sh slots hold zero so that it stays sorted, and positions
-                    // below sh are never reported.  It is padded to a power of two with
-                    // the largest key, which is never below a searched value.
-                    const int32_t lo_al = lo & ~3;
-                    const int32_t sh = lo - lo_al;
-                    const int32_t len_al = len + sh;
-                    int32_t p2 = 4;
-                    while (p2 < len_al) p2 <<= 1;
-                    stage_window(win, B, lo_al, sh, len_al, p2, lane);
-                    wave_sync();
-                    const uint32_t wmax = len > 0 ? win[len_al - 1] : 0u;
-                    int32_t p[kSub];
+                    const int32_t hi = uni(wave_search(B, lo, end[o], a_last, lane));
+                    const int32_t cover = (hi < end[o] ? hi + 1 : end[o]) - lo;
+                    if (cover <= kWin - 4) {
+                        // The window starts at the 16-byte boundary below lo (16-byte
+                        // loads); its first sh slots hold zero so that it stays sorted and
+                        // positions below sh are never reported.  It is padded to a power
+                        // of two with the largest key, never below a searched value.
+                        const int32_t lo_al = lo & ~3;
+                        const int32_t sh = lo - lo_al;
+                        const int32_t len_al = cover + sh;
+                        int32_t p2 = 4;
+                        while (p2 < len_al) p2 <<= 1;
+                        stage_window(win, B, lo_al, sh, len_al, p2, lane);
+                        wave_sync();
+                        int32_t p[kSub];
 #pragma unroll
-                    for (int k = 0; k < kSub; ++k) p[k] = 0;
-                    // branch-free lower bound of every value in the window (all kSub searches
-                    // advance together)
-                    for (int32_t step = p2 >> 1; step > 0; step >>= 1) {
+                        for (int k = 0; k < kSub; ++k) p[k] = 0;
+                        // branch-free lower bound of every value (all kSub searches advance together)
+                        for (int32_t step = p2 >> 1; step > 0; step >>= 1) {
 #pragma unroll
-                        for (int k = 0; k < kSub; ++k)
-                            if (win[p[k] + step - 1] < a[k]) p[k] += step;
-                    }
-#pragma unroll
-                    for (int k = 0; k < kSub; ++k) {
-                        if (win[p[k]] < a[k]) p[k] += 1;
-                        if (p[k] < sh) p[k] = sh;
-                        if (v[k]) {
-                            bool fo;
-                            if (len > 0 && a[k] <= wmax) {
-                                fo = win[p[k]] == a[k];
-                            } else {   // beyond the window: search the rest in place
-                                const int32_t q = lower_bound32(B, lo_al + len_al, end[o], a[k]);
-                                p[k] = q - lo_al;
-                                fo = q < end[o] && B[q] == a[k];
-                            }
-                            f[k] = f[k] && fo;
+                            for (int k = 0; k < kSub; ++k)
+                                if (win[p[k] + step - 1] < a[k]) p[k] += step;
                         }
-                        if (kMat) pos[o][k] = lo_al + p[k];
+#pragma unroll
+                        for (int k = 0; k < kSub; ++k) {
+                            if (win[p[k]] < a[k]) p[k] += 1;
+                            if (p[k] < sh) p[k] = sh;
+                            if (v[k]) f[k] = f[k] && p[k] < len_al && win[p[k]] == a[k];
+                            if (kMat) pos[o][k] = lo_al + p[k];
+                        }
+                    } else {
+                        const int32_t sp = (cover + (kWin - 4) - 1) / (kWin - 4);   // fence spacing
+                        const int32_t nf = (cover + sp - 1) / sp;
+                        int32_t p2 = 4;
+                        while (p2 < nf) p2 <<= 1;
+                        for (int q = lane; q < p2; q += 64) win[q] = q < nf ? B[lo + q * sp] : 0xFFFFFFFFu;
+                        wave_sync();
+                        int32_t p[kSub];
+#pragma unroll
+                        for (int k = 0; k < kSub; ++k) p[k] = 0;
+                        for (int32_t step = p2 >> 1; step > 0; step >>= 1) {
+#pragma unroll
+                            for (int k = 0; k < kSub; ++k)
+                                if (win[p[k] + step - 1] < a[k]) p[k] += step;
+                        }
+#pragma unroll
+                        for (int k = 0; k < kSub; ++k) {
+                            if (win[p[k]] < a[k]) p[k] += 1;   // fences below the value
+                            int32_t q = lo;
+                            if (v[k] && p[k] > 0) {
+                                const int32_t l = lo + (p[k] - 1) * sp + 1;
+                                const int32_t r = lo + p[k] * sp < end[o] ? lo + p[k] * sp : end[o];
+                                q = lower_bound32(B, l, r, a[k]);
+                            }
+                            if (v[k]) f[k] = f[k] && q < end[o] && B[q] == a[k];
+                            if (kMat) pos[o][k] = q;
+                        }
                     }
                     wave_sync();
-                    // cursor: lower bound of the step's last element
-                    int32_t rl = 0;
-#pragma unroll
-                    for (int k = 0; k < kSub; ++k) {
-                        const int32_t tt = __shfl(p[k], last & 63, 64);
-                        if (k == (last >> 6)) rl = tt;
-                    }
-                    cur[o] = uni(lo_al + rl);
+                    cur[o] = hi;   // lower bound of the step's last value
                 }
 #pragma unroll
                 for (int k = 0; k < kSub; ++k) {
@@ -827,6 +875,7 @@ __global__ __launch_bounds__(kBlock) void k_probe2(KData D, KStep S, const int32
                 // continue inside the last entry touched (its cursors restart)
                 e = e_hi;
                 load_entry(e);
+                prefetch_next(e);
                 rc += chunk;
             }
         }
