@@ -165,6 +165,7 @@ struct PlanOp {
     int32_t kind;
     int32_t atom;     // atom index (V0 / CHILD)
     int32_t group;    // lifted group (TMP)
+    int32_t lvl;      // CoCo level of the operand (V0: 0; CHILD: 1 .. arity-1)
 };
 
 struct PlanGroup {           // a lifted intersection (Section 6.1)
@@ -190,6 +191,7 @@ struct Plan {
     int32_t atom_arity[kMaxAtoms];
     int32_t atom_first[kMaxAtoms];   // variable at CoCo level 0
     int32_t atom_second[kMaxAtoms];  // variable at CoCo level 1 (-1 for unary)
+    int32_t atom_lvl_var[kMaxAtoms][4];   // variable at every CoCo level (columns in variable order)
     int32_t n_groups = 0;
     PlanGroup groups[kMaxGroups];
     PlanLevel levels[kMaxVars];

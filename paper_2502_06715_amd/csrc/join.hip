@@ -4,9 +4,10 @@
 // variables of the order, tagged with the HyperCube cell it belongs to:
 //   word 0          cell id (coordinates of every variable packed together)
 //   words 1..i      the bound values (mixed keys)
-//   node words      for every binary atom whose first variable is bound and
-//                   whose second is not: the index of the bound value in the
-//                   atom's top level (its child list is O0[node]..O0[node+1])
+//   node words      for every atom and CoCo level r whose variable is bound
+//                   while the variable of level r+1 is not: the index of the
+//                   bound prefix in level r (its child list is
+//                   O_r[node]..O_r[node+1] in level r+1)
 //   tmp words       (offset, length) of the lifted intersections that are live
 // F_0 holds one entry per cell, so every cell runs its own Generic Join
 // restricted to the key range of its coordinates (Section 5); the key range of
@@ -38,10 +39,9 @@ namespace hc {
 constexpr int kMaxW = 32;   // words per frontier entry
 
 struct DAtom {
-    const uint32_t* V0;
-    const int32_t* O0;
-    const uint32_t* V1;
-    int64_t l0;
+    const uint32_t* V[4];   // CoCo levels: keys
+    const int32_t* O[3];    // child offsets of levels 0..arity-2
+    int64_t len[4];         // level lengths
 };
 
 struct KData {
@@ -58,6 +58,7 @@ struct KOp {
     int32_t atom;
     int32_t word;     // CHILD: entry word of the parent node; TMP: entry word of (offset, length)
     int32_t group;    // TMP
+    int32_t lvl;      // CoCo level read (V0: 0; CHILD: the children's level)
     const int2* v0_range;   // V0 restricted by the cell: table indexed by the coordinate (or null)
     int32_t rng_shift, rng_k;     // coordinate = (src >> rng_shift) & (2^rng_k - 1), src = the cell id
     int32_t rng_word;             // or, when >= 0, this word of the entry (a bound key, a query's id range)
@@ -114,8 +115,8 @@ __device__ inline bool pred_ok(const KStep& S, const int32_t* ent, uint32_t key,
 }
 
 __device__ inline const uint32_t* op_array(const KData& D, const KOp& o) {
-    if (o.kind == OP_V0) return D.atoms[o.atom].V0;
-    if (o.kind == OP_CHILD) return D.atoms[o.atom].V1;
+    if (o.kind == OP_V0) return D.atoms[o.atom].V[0];
+    if (o.kind == OP_CHILD) return D.atoms[o.atom].V[o.lvl];
     return D.tmp_val[o.group];
 }
 
@@ -209,11 +210,11 @@ __global__ __launch_bounds__(kBlock) void k_prep(KData D, KStep S, const int32_t
                     end = r.y;
                 } else {
                     beg = 0;
-                    end = D.atoms[op.atom].l0;
+                    end = D.atoms[op.atom].len[0];
                 }
             } else if (op.kind == OP_CHILD) {
                 const int32_t node = ent[op.word];
-                const int32_t* O = D.atoms[op.atom].O0;
+                const int32_t* O = D.atoms[op.atom].O[op.lvl - 1];
                 beg = O[node];
                 end = O[node + 1];
                 if (restrict_ && op.child_range) {
@@ -221,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(KData D, KStep S, const int32_t
                     beg = cr[0];
                     end = cr[1];
                 } else if (restrict_) {
-                    const uint32_t* A = D.atoms[op.atom].V1;
+                    const uint32_t* A = D.atoms[op.atom].V[op.lvl];
                     const int64_t b2 = lower_bound_u32(A, beg, end, (uint32_t)lo);
                     end = hi >= (1ull << 32) ? end : lower_bound_u32(A, b2, end, (uint32_t)hi);
                     beg = b2;
@@ -1035,7 +1036,7 @@ static unsigned grid_waves(int64_t n_words, int64_t cap = 8192) {
 
 struct Layout {
     int W;
-    int node_word[kMaxAtoms];
+    int node_word[kMaxAtoms][3];   // per atom and CoCo level of the node
     int tmp_word[kMaxGroups];
 };
 
@@ -1045,13 +1046,14 @@ struct Layout {
 static Layout make_layout(const Plan& P, int i) {
     Layout L;
     int w = 1 + i;
-    for (int j = 0; j < kMaxAtoms; ++j) L.node_word[j] = -1;
+    for (int j = 0; j < kMaxAtoms; ++j)
+        for (int r = 0; r < 3; ++r) L.node_word[j][r] = -1;
     for (int g = 0; g < kMaxGroups; ++g) L.tmp_word[g] = -1;
-    for (int j = 0; j < P.n_atoms; ++j) {
-        if (P.atom_second[j] < 0) continue;
-        const int pf = P.pos[P.atom_first[j]], ps = P.pos[P.atom_second[j]];
-        if (pf < i && i <= ps) L.node_word[j] = w++;
-    }
+    for (int j = 0; j < P.n_atoms; ++j)
+        for (int r = 0; r + 1 < P.atom_arity[j]; ++r) {
+            const int pr = P.pos[P.atom_lvl_var[j][r]], pn = P.pos[P.atom_lvl_var[j][r + 1]];
+            if (pr < i && i <= pn) L.node_word[j][r] = w++;
+        }
     for (int g = 0; g < P.n_groups; ++g)
         if (P.groups[g].lift <= i && i <= P.groups[g].consumer) {
             L.tmp_word[g] = w;
@@ -1123,7 +1125,8 @@ struct Runner {
         o.group = po.group;
         o.word = -1;
         o.v0_range = nullptr;
-        if (po.kind == OP_CHILD) o.word = L.node_word[po.atom];
+        o.lvl = po.lvl;
+        if (po.kind == OP_CHILD) o.word = L.node_word[po.atom][po.lvl - 1];
         if (po.kind == OP_TMP) o.word = L.tmp_word[po.group];
         o.child_range = nullptr;
         o.child_stride = 0;
@@ -1154,7 +1157,7 @@ struct Runner {
         if (vk > 0) {
             ranges.emplace_back(A, (size_t)1 << vk);
             const DAtom& a = D.atoms[po.atom];
-            k_v0_ranges<<<grid_for((int64_t)1 << vk), kBlock, 0, s>>>(a.V0, a.l0, D.b, vk, ranges.back().p);
+            k_v0_ranges<<<grid_for((int64_t)1 << vk), kBlock, 0, s>>>(a.V[0], a.len[0], D.b, vk, ranges.back().p);
             HC_HIP(hipGetLastError());
             o.v0_range = ranges.back().p;
             o.rng_k = vk;
@@ -1167,17 +1170,18 @@ struct Runner {
             const int k = shares[var];
             const DAtom& a = D.atoms[po.atom];
             const int64_t stride = ((int64_t)1 << k) + 1;
-            if (a.l0 * stride <= ((int64_t)1 << 27)) {
-                const uint64_t key = ((uint64_t)po.atom << 8) | (uint64_t)k;
+            const int64_t nodes = a.len[po.lvl - 1];
+            if (nodes * stride <= ((int64_t)1 << 27)) {
+                const uint64_t key = ((uint64_t)po.atom << 16) | ((uint64_t)po.lvl << 8) | (uint64_t)k;
                 int found = -1;
                 for (size_t t = 0; t < child_key.size(); ++t)
                     if (child_key[t] == key) found = (int)t;
                 if (found < 0) {
-                    child_tab.emplace_back(A, (size_t)(a.l0 * stride + 1));
+                    child_tab.emplace_back(A, (size_t)(nodes * stride + 1));
                     child_key.push_back(key);
                     found = (int)child_tab.size() - 1;
-                    k_child_ranges<<<grid_for(a.l0 * stride), kBlock, 0, s>>>(a.O0, a.V1, a.l0, D.b, k,
-                                                                               child_tab.back().p);
+                    k_child_ranges<<<grid_for(nodes * stride), kBlock, 0, s>>>(a.O[po.lvl - 1], a.V[po.lvl],
+                                                                                nodes, D.b, k, child_tab.back().p);
                     HC_HIP(hipGetLastError());
                 }
                 o.child_range = child_tab[found].p;
@@ -1186,6 +1190,10 @@ struct Runner {
         }
         return o;
     }
+
+    // Operands of a lifted intersection whose positions the pool keeps: those with a
+    // further CoCo level below (their position becomes a node of a later level).
+    bool is_source(const PlanOp& o) const { return o.lvl + 1 < P.atom_arity[o.atom]; }
 
     void setup_steps(const hc_query* q) {
         const int n = P.n_vars;
@@ -1219,37 +1227,40 @@ struct Runner {
             S.val_word = i + 1;
             S.n_new = 0;
             S.n_zero = 0;
-            for (int j = 0; j < P.n_atoms; ++j) {
-                if (Lo.node_word[j] < 0) continue;
-                if (Li.node_word[j] >= 0) {
-                    copy(Li.node_word[j], Lo.node_word[j]);
-                    continue;
-                }
-                // new node: the atom's first variable is bound at this level
-                int op = -1, src = -1;
-                for (int t = 0; t < PL.n_ops; ++t)
-                    if (PL.ops[t].kind == OP_V0 && PL.ops[t].atom == j) op = t;
-                if (op < 0) {
+            for (int j = 0; j < P.n_atoms; ++j)
+                for (int r = 0; r + 1 < P.atom_arity[j]; ++r) {
+                    if (Lo.node_word[j][r] < 0) continue;
+                    if (Li.node_word[j][r] >= 0) {
+                        copy(Li.node_word[j][r], Lo.node_word[j][r]);
+                        continue;
+                    }
+                    // new node: the atom's level-r variable is bound at this level; its
+                    // position comes from the level's operand on that CoCo level, or
+                    // from the lifted intersection that holds it
+                    int op = -1, src = -1;
                     for (int t = 0; t < PL.n_ops; ++t)
-                        if (PL.ops[t].kind == OP_TMP) {
-                            const PlanGroup& g = P.groups[PL.ops[t].group];
-                            int sidx = 0;
-                            for (int u = 0; u < g.n_ops; ++u) {
-                                if (g.ops[u].kind != OP_V0) continue;
-                                if (g.ops[u].atom == j) {
-                                    op = t;
-                                    src = sidx;
+                        if (PL.ops[t].kind != OP_TMP && PL.ops[t].atom == j && PL.ops[t].lvl == r) op = t;
+                    if (op < 0) {
+                        for (int t = 0; t < PL.n_ops; ++t)
+                            if (PL.ops[t].kind == OP_TMP) {
+                                const PlanGroup& g = P.groups[PL.ops[t].group];
+                                int sidx = 0;
+                                for (int u = 0; u < g.n_ops; ++u) {
+                                    if (!is_source(g.ops[u])) continue;
+                                    if (g.ops[u].atom == j && g.ops[u].lvl == r) {
+                                        op = t;
+                                        src = sidx;
+                                    }
+                                    ++sidx;
                                 }
-                                ++sidx;
                             }
-                        }
+                    }
+                    HC_REQUIRE(op >= 0, HC_ERR_DEVICE, "plan: no source for a node");
+                    S.new_word[S.n_new] = (int8_t)Lo.node_word[j][r];
+                    S.new_op[S.n_new] = (int8_t)op;
+                    S.new_src[S.n_new] = (int8_t)(src < 0 ? 0 : src);
+                    ++S.n_new;
                 }
-                HC_REQUIRE(op >= 0, HC_ERR_DEVICE, "plan: no source for a node");
-                S.new_word[S.n_new] = (int8_t)Lo.node_word[j];
-                S.new_op[S.n_new] = (int8_t)op;
-                S.new_src[S.n_new] = (int8_t)(src < 0 ? 0 : src);
-                ++S.n_new;
-            }
             for (int g = 0; g < P.n_groups; ++g) {
                 if (Lo.tmp_word[g] < 0) continue;
                 if (Li.tmp_word[g] >= 0) {
@@ -1278,7 +1289,7 @@ struct Runner {
             S.group = g;
             S.n_src = 0;
             for (int t = 0; t < PG.n_ops; ++t)
-                if (PG.ops[t].kind == OP_V0) S.src_op[S.n_src++] = (int8_t)t;
+                if (is_source(PG.ops[t])) S.src_op[S.n_src++] = (int8_t)t;
         }
     }
 
@@ -1492,12 +1503,17 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
         }
         HC_REQUIRE(c->key_bits == b && c->mix_seed == seed && c->mix_bits == mb, HC_ERR_INVALID,
                    "all CoCos of a join must share key_bits and mix_seed");
-        if (c->arity == 2) {
+        if (c->arity >= 2 && !(c->symmetric && c->arity == 2)) {
+            // level r of the CoCo must hold the atom's column of its r-th variable in order
             int off = 0;
             for (int t = 0; t < j; ++t) off += q->atom_arity[t];
-            const int first_col = q->atom_vars[off] == P.atom_first[j] ? 0 : 1;
-            HC_REQUIRE(c->symmetric || c->col_order[0] == first_col, HC_ERR_INVALID,
-                       "CoCo column order does not follow the variable order for atom " + std::to_string(j));
+            for (int r = 0; r < c->arity; ++r) {
+                int col = -1;
+                for (int cc = 0; cc < c->arity; ++cc)
+                    if (q->atom_vars[off + cc] == P.atom_lvl_var[j][r]) col = cc;
+                HC_REQUIRE(c->col_order[r] == col, HC_ERR_INVALID,
+                           "CoCo column order does not follow the variable order for atom " + std::to_string(j));
+            }
         }
     }
     int K = 0;
@@ -1548,10 +1564,11 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
     R.D = KData{};
     for (int j = 0; j < P.n_atoms; ++j) {
         const hc_coco* c = atoms[j];
-        R.D.atoms[j].V0 = c->V[0];
-        R.D.atoms[j].O0 = c->arity == 2 ? c->O[0] : nullptr;
-        R.D.atoms[j].V1 = c->arity == 2 ? c->V[1] : nullptr;
-        R.D.atoms[j].l0 = c->level_len[0];
+        for (int r = 0; r < 4; ++r) {
+            R.D.atoms[j].V[r] = r < c->arity ? c->V[r] : nullptr;
+            R.D.atoms[j].len[r] = r < c->arity ? c->level_len[r] : 0;
+        }
+        for (int r = 0; r < 3; ++r) R.D.atoms[j].O[r] = r + 1 < c->arity ? c->O[r] : nullptr;
     }
     R.D.mix = make_mixer(mb, seed, b);
     R.D.b = b;
@@ -1663,7 +1680,7 @@ uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, co
     for (int v = 0; v < P.n_vars; ++v) K += shares ? shares[v] : 0;
     auto op_max = [&](const PlanOp& o) -> double {
         const hc_coco* c = atoms[o.atom];
-        return o.kind == OP_CHILD ? (double)c->max_children[0] : (double)c->level_len[0];
+        return o.kind == OP_CHILD ? (double)c->max_children[o.lvl - 1] : (double)c->level_len[0];
     };
     double gmax[kMaxGroups];
     for (int g = 0; g < P.n_groups; ++g) {

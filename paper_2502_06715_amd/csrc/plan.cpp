@@ -53,7 +53,7 @@ static void check_order(const hc_query* q, const int32_t* order) {
 // frontier F_{max d + 1} (computed once per binding of levels <= max d) and
 // consumed at level i as one temporary operand (Section 6.1).
 Plan compile_plan(const hc_query* q, const int32_t* order, bool rewrite, int min_lift) {
-    validate_query(q, 2);
+    validate_query(q, 4);
     check_order(q, order);
     Plan p;
     p.n_vars = q->n_vars;
@@ -66,15 +66,14 @@ Plan compile_plan(const hc_query* q, const int32_t* order, bool rewrite, int min
     for (int j = 0; j < q->n_atoms; ++j) {
         const int k = q->atom_arity[j];
         p.atom_arity[j] = k;
-        if (k == 1) {
-            p.atom_first[j] = q->atom_vars[off];
-            p.atom_second[j] = -1;
-        } else {
-            const int a = q->atom_vars[off], b = q->atom_vars[off + 1];
-            const bool a_first = p.pos[a] < p.pos[b];
-            p.atom_first[j] = a_first ? a : b;
-            p.atom_second[j] = a_first ? b : a;
-        }
+        // CoCo levels of an atom follow the variable order (Section 4)
+        int lv[4];
+        for (int c = 0; c < k; ++c) lv[c] = q->atom_vars[off + c];
+        for (int x = 1; x < k; ++x)
+            for (int y = x; y > 0 && p.pos[lv[y]] < p.pos[lv[y - 1]]; --y) std::swap(lv[y], lv[y - 1]);
+        for (int r = 0; r < 4; ++r) p.atom_lvl_var[j][r] = r < k ? lv[r] : -1;
+        p.atom_first[j] = lv[0];
+        p.atom_second[j] = k > 1 ? lv[1] : -1;
         off += k;
     }
     p.n_groups = 0;
@@ -84,12 +83,15 @@ Plan compile_plan(const hc_query* q, const int32_t* order, bool rewrite, int min
         int dep[kMaxAtoms];
         int n = 0;
         for (int j = 0; j < q->n_atoms; ++j) {
-            if (p.atom_first[j] == x) {
-                ops[n] = PlanOp{OP_V0, j, -1};
-                dep[n++] = -1;
-            } else if (p.atom_second[j] == x) {
-                ops[n] = PlanOp{OP_CHILD, j, -1};
-                dep[n++] = p.pos[p.atom_first[j]];
+            for (int r = 0; r < p.atom_arity[j]; ++r) {
+                if (p.atom_lvl_var[j][r] != x) continue;
+                if (r == 0) {
+                    ops[n] = PlanOp{OP_V0, j, -1, 0};
+                    dep[n++] = -1;
+                } else {   // children of the atom's node at level r-1, bound at its parent's level
+                    ops[n] = PlanOp{OP_CHILD, j, -1, r};
+                    dep[n++] = p.pos[p.atom_lvl_var[j][r - 1]];
+                }
             }
         }
         HC_REQUIRE(n <= kMaxOps, HC_ERR_UNSUPPORTED, "more than 8 atoms share one variable");
@@ -112,14 +114,15 @@ Plan compile_plan(const hc_query* q, const int32_t* order, bool rewrite, int min
             for (int t = 0; t < n; ++t)
                 if (dep[t] < i - 1) g.ops[g.n_ops++] = ops[t];
                 else L.ops[L.n_ops++] = ops[t];
-            L.ops[L.n_ops++] = PlanOp{OP_TMP, -1, p.n_groups};
+            L.ops[L.n_ops++] = PlanOp{OP_TMP, -1, p.n_groups, 0};
             ++p.n_groups;
         } else {
             for (int t = 0; t < n; ++t) L.ops[L.n_ops++] = ops[t];
         }
         L.n_new_nodes = 0;
         for (int j = 0; j < q->n_atoms; ++j)
-            if (p.atom_first[j] == x && p.atom_second[j] >= 0) L.new_node_atom[L.n_new_nodes++] = j;
+            for (int r = 0; r + 1 < p.atom_arity[j]; ++r)
+                if (p.atom_lvl_var[j][r] == x) L.new_node_atom[L.n_new_nodes++] = j;
     }
     return p;
 }
@@ -186,8 +189,10 @@ static LevelCost level_costs(const hc_query* q, const std::vector<AtomStats>& st
     auto avg_n = [&](const PlanOp& o, int var) {
         const AtomStats& a = st[o.atom];
         if (o.kind == OP_V0) return std::max(1.0, a.distinct[col_of(o.atom, var)]);
-        const double parent = std::max(1.0, a.distinct[col_of(o.atom, p.atom_first[o.atom])]);
-        return std::max(1.0, a.rows / parent);
+        // children per node of level lvl-1: rows over the distinct prefixes of length lvl
+        double parents = 1.0;
+        for (int r = 0; r < o.lvl; ++r) parents *= std::max(1.0, a.distinct[col_of(o.atom, p.atom_lvl_var[o.atom][r])]);
+        return std::max(1.0, a.rows / std::max(1.0, std::min(parents, a.rows)));
     };
     auto cost_of = [](int nops, double bind, double mn, double mx) {
         if (nops <= 1) return bind * mn;

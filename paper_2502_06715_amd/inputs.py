@@ -221,6 +221,9 @@ QUERIES = {
     "diamond4": (4, [(0, 1), (0, 2), (1, 3), (2, 3), (1, 2)]),                   # Q4
     "clique4": (4, [(0, 1), (0, 2), (1, 3), (2, 3), (1, 2), (0, 3)]),            # Q6
     "twotriangle": (5, [(0, 1), (0, 2), (1, 2), (2, 3), (2, 4), (3, 4)]),        # Q8
+    # ternary atoms (the tensor-kernel queries of the query table)
+    "lw": (4, [(0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3)]),                     # Loomis-Whitney
+    "ct": (4, [(0, 1, 2), (0, 1, 3), (0, 2, 3)]),                                # clover-triangle
 }
 
 GRAPH_SALT = 0x4752_4150_4853_4544   # separates a query's graph stream from its spec draws

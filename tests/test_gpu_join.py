@@ -38,7 +38,7 @@ def _atom_cocos(ctx, atoms, rels, var_order, b):
     pos = {v: i for i, v in enumerate(var_order)}
     out = []
     for a, r in zip(atoms, rels):
-        co = [0] if len(a) == 1 else ([0, 1] if pos[a[0]] < pos[a[1]] else [1, 0])
+        co = sorted(range(len(a)), key=lambda c: pos[a[c]])
         out.append(_coco(ctx, r, co, b))
     return out
 
@@ -73,7 +73,9 @@ def test_config1_triangle_all_orders_shares(ctx):
 def test_random_relations_all_queries(ctx, name):
     n, atoms = inputs.QUERIES[name]
     for trial in range(3):
-        rels = [inputs.random_relation(300 + 50 * j, 40, 500 + 31 * trial + j) for j in range(len(atoms))]
+        ternary = any(len(a) > 2 for a in atoms)
+        rels = [inputs.random_relation(300 + 50 * j, 9 if ternary else 40, 500 + 31 * trial + j, arity=len(atoms[j]))
+                for j in range(len(atoms))]
         exp = oracle.gj(n, atoms, rels, emit=True)
         for k, order in enumerate(itertools.islice(itertools.permutations(range(n)), 0, None, 7)):
             order = list(order)
@@ -238,3 +240,37 @@ def test_config3_emit_capacity_2_28(ctx):
         hc.join_emit(ctx, q, [c] * 6, [0, 1, 2, 3], [6, 6, 0, 0], capacity=1 << 28)
     assert ei.value.status == hc.HC_ERR_OVERFLOW
     assert ei.value.n_out == GOLD["3"]["count"]
+
+
+@pytest.mark.parametrize("name", ["lw", "ct"])
+def test_ternary_dense_cubes_closed_form(ctx, name):
+    """Full Cartesian products: Loomis-Whitney over four [N]^3 cubes has N^4 tuples;
+    the clover-triangle over U x [N] x [N] relations has |U| N^3."""
+    n, atoms = inputs.QUERIES[name]
+    N, U = 24, 3
+    g = np.stack(np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij"), -1).reshape(-1, 3)
+    if name == "ct":
+        g = g[g[:, 0] < U]
+    rels = [g.astype(np.int32)] * len(atoms)
+    expect = N ** 4 if name == "lw" else U * N ** 3
+    for order in [[0, 1, 2, 3], [3, 2, 1, 0], [1, 3, 0, 2]]:
+        cocos = _atom_cocos(ctx, atoms, rels, order, 0)
+        for shares in [[0, 0, 0, 0], [2, 1, 0, 1]]:
+            for flags in [0, hc.HC_NO_REWRITE]:
+                log("%s cubes order=%s shares=%s flags=%d" % (name, order, shares, flags))
+                assert hc.join_count(ctx, hc.Query(n, atoms), cocos, order, shares, flags=flags) == expect
+
+
+def test_ternary_mixed_arity_query(ctx):
+    """Atoms of arity 1, 2 and 3 in one query (unary filter, binary edge, ternary
+    hyperedge), every order, against the oracle's emitted rows."""
+    n, atoms = 4, [(0, 1, 2), (2, 3), (1,), (0, 3)]
+    rels = [inputs.random_relation(900, 10, 71, 3), inputs.random_relation(60, 10, 72, 2),
+            inputs.random_relation(6, 10, 73, 1), inputs.random_relation(50, 10, 74, 2)]
+    exp = oracle.gj(n, atoms, rels, emit=True)
+    assert exp.count > 0
+    for order in itertools.permutations(range(n)):
+        order = list(order)
+        cocos = _atom_cocos(ctx, atoms, rels, order, 5)
+        rows, n_out = _emit_sorted(ctx, hc.Query(n, atoms), cocos, order, [1, 0, 1, 0], exp.count + 1)
+        assert n_out == exp.count and np.array_equal(rows, exp.rows)

@@ -60,7 +60,7 @@ def test_plan_matches_oracle_lift_rule_all_orders(name):
     (3, [(0, 1), (1, 0)]),          # variable 2 in no atom
     (2, [(0, 0)]),                  # repeated variable (unsupported)
     (2, [(0, 5)]),                  # variable out of range
-    (3, [(0, 1, 2)]),               # ternary atom: join engine is binary
+    (5, [(0, 1, 2, 3, 4)]),         # arity 5: CoCo levels go up to 4
 ])
 def test_plan_rejects_bad_queries(bad):
     n, atoms = bad

@@ -53,8 +53,9 @@ def test_gj_equals_brute_force_random(name):
         rels = []
         for j, _ in enumerate(atoms):
             rows = 0 if (trial == 5 and j == 1) else 12 + 3 * j   # one case with an empty relation
-            rels.append(inputs.random_relation(rows, 5, rng_seed + 17 * trial + j) if rows else
-                        np.zeros((0, 2), np.int32))
+            k = len(atoms[j])
+            rels.append(inputs.random_relation(rows * (1 + 2 * (k > 2)), 5, rng_seed + 17 * trial + j, arity=k)
+                        if rows else np.zeros((0, k), np.int32))
         expect = brute.brute(n, atoms, rels)
         for order in itertools.islice(itertools.permutations(range(n)), 0, None, 5):
             r = oracle.gj(n, atoms, rels, order=order, emit=True)
@@ -315,3 +316,18 @@ def test_batch_spec_deterministic_and_mixed():
     for s in a[:16]:
         g = inputs.batch_graph(s)
         assert g.shape[0] == 2 * s["m"] and int(g.max()) < s["n"]
+
+
+def test_ternary_closed_forms():
+    """Loomis-Whitney over four full [N]^3 cubes: N^4 tuples; clover-triangle over
+    three full U x [N] x [N] relations: |U| N^3; one missing hyperedge of R1 removes
+    exactly the N tuples that extend it."""
+    N, U = 5, 2
+    g = np.stack(np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij"), -1).reshape(-1, 3)
+    n, atoms = Q["lw"]
+    assert oracle.gj(n, atoms, [g] * 4).count == N ** 4
+    r1 = g[~((g[:, 0] == 1) & (g[:, 1] == 2) & (g[:, 2] == 3))]
+    assert oracle.gj(n, atoms, [r1, g, g, g]).count == N ** 4 - N
+    n, atoms = Q["ct"]
+    gu = g[g[:, 0] < U]
+    assert oracle.gj(n, atoms, [gu] * 3).count == U * N ** 3
