@@ -326,3 +326,68 @@ def serve_stream(graph_specs, n_requests: int = 20000, qps: float = 2000.0, seed
         lo = int(((int(r[i, 3]) & ((1 << 40) - 1)) * (n - w + 1)) >> 40) if n > w else 0
         out.append({"id": i, "t": float(t[i]), "query": shape, "graph": g, "lo": lo, "hi": lo + w})
     return out
+
+
+# ---------------------------------------------------------------- tensor workloads
+SEED_TENSOR = 0x4843_3000_0000
+TENSOR_U = (0, 1)   # first-attribute domain of the clover-triangle relations (reading of a garbled passage)
+
+
+def full_product(*sizes) -> np.ndarray:
+    """Every tuple of [s_1] x ... x [s_k] (0-based ids), rows in lexicographic order."""
+    g = np.stack(np.meshgrid(*[np.arange(s, dtype=np.int32) for s in sizes], indexing="ij"), -1)
+    return g.reshape(-1, len(sizes))
+
+
+def st_dense(n: int = 512, m: int = 4096):
+    """ST-Dense: R1..R4 are the full cube [n]^3 (one array serves all four); R5..R7
+    are the full U x [m] x [m] with U = TENSOR_U."""
+    cube = full_product(n, n, n)
+    ct = full_product(m, m)
+    ct = np.concatenate([np.concatenate([np.full((ct.shape[0], 1), u, np.int32), ct], 1) for u in TENSOR_U])
+    return {"lw": [cube] * 4, "ct": [ct] * 3}
+
+
+def random_tuples(n_rows: int, sizes, seed: int) -> np.ndarray:
+    """n_rows distinct tuples drawn uniformly from [s_1] x ... x [s_k]: candidate i
+    takes draw i of stream `seed` and splits it into the k coordinates by
+    multiply-shift of successive 21-bit fields; the first n_rows distinct
+    candidates in draw order are kept, then rows are shuffled."""
+    k = len(sizes)
+    out = np.zeros((0, k), np.int64)
+    seen = np.zeros(0, np.int64)
+    start = 0
+    mult = [int(np.prod(sizes[c + 1:])) for c in range(k)]
+    while out.shape[0] < n_rows:
+        cnt = max(1024, int((n_rows - out.shape[0]) * 1.3))
+        r = splitmix64(seed, start, cnt)
+        start += cnt
+        cols = [(((r >> np.uint64(21 * c)) & np.uint64((1 << 21) - 1)) * np.uint64(sizes[c]) >> np.uint64(21))
+                .astype(np.int64) for c in range(k)]
+        key = sum(cols[c] * mult[c] for c in range(k))
+        allk = np.concatenate([seen, key])
+        _, first = np.unique(allk, return_index=True)
+        keep = np.zeros(allk.size, bool)
+        keep[first] = True
+        new = keep[seen.size:]
+        add = np.stack(cols, 1)[new]
+        add = add[np.argsort(np.flatnonzero(new), kind="stable")]
+        out = np.concatenate([out, add])[:n_rows]
+        seen = np.concatenate([seen, key[new]])
+    rnd = splitmix64(seed ^ SHUFFLE_SALT, 0, out.shape[0])
+    return out[np.argsort(rnd, kind="stable")].astype(np.int32)
+
+
+def st_sparse(n: int = 5120, rows: int = 512 ** 3, m: int = 40960, rows2: int = 4096 ** 2):
+    """ST-Sparse: R1..R4 each `rows` distinct random tuples of [n]^3 (density
+    rows / n^3 = 0.001 at full size); R5..R7 each `rows2` distinct random pairs of
+    [m]^2 under every first-attribute value of TENSOR_U (density 0.01)."""
+    lw = [random_tuples(rows, (n, n, n), SEED_TENSOR + j) for j in range(4)]
+    ct = []
+    for j in range(3):
+        parts = []
+        for u in TENSOR_U:
+            p = random_tuples(rows2, (m, m), SEED_TENSOR + 16 + 4 * j + u)
+            parts.append(np.concatenate([np.full((p.shape[0], 1), u, np.int32), p], 1))
+        ct.append(np.concatenate(parts))
+    return {"lw": lw, "ct": ct}

@@ -274,3 +274,22 @@ def test_ternary_mixed_arity_query(ctx):
         cocos = _atom_cocos(ctx, atoms, rels, order, 5)
         rows, n_out = _emit_sorted(ctx, hc.Query(n, atoms), cocos, order, [1, 0, 1, 0], exp.count + 1)
         assert n_out == exp.count and np.array_equal(rows, exp.rows)
+
+
+@pytest.mark.parametrize("name", ["lw", "ct"])
+def test_st_sparse_small_against_oracle(ctx, name):
+    """The ST-Sparse recipe at small domains (LW: 4 distinct random relations at density
+    0.22; CT: 3 relations of random pairs under both first-attribute values)."""
+    ds = inputs.st_sparse(n=30, rows=6000, m=120, rows2=2500)
+    n, atoms = inputs.QUERIES[name]
+    rels = ds[name]
+    exp = oracle.gj(n, atoms, rels, emit=True)
+    assert exp.count > 0
+    for order in [[0, 1, 2, 3], [2, 0, 3, 1]]:
+        cocos = _atom_cocos(ctx, atoms, rels, order, 0)
+        q = hc.Query(n, atoms)
+        for shares in [[0, 0, 0, 0], [1, 1, 1, 0]]:
+            log("st_sparse %s order=%s shares=%s" % (name, order, shares))
+            assert hc.join_count(ctx, q, cocos, order, shares) == exp.count
+        rows, n_out = _emit_sorted(ctx, q, cocos, order, [1, 0, 1, 0], exp.count + 1)
+        assert n_out == exp.count and np.array_equal(rows, exp.rows)
