@@ -113,20 +113,28 @@ def bench_batch(args):
         rel, seg = batch.union_relation(gs, mb)
         groups[shape] = dict(idx=idx, mb=mb, seg=seg, rel=torch.from_numpy(rel).to(dev), n=len(gs))
     torch.cuda.synchronize()
+    # the autotuner times candidates on every 8th query of each shape
     tune = batch.Autotune()
     for shape, g in groups.items():
-        c = hc.build_coco(ctx, g["rel"], [0, 1], key_bits=g["mb"], segment_bits=g["seg"], symmetric=True)
-        tune.pick(shape, lambda x: batch.count_batched(ctx, shape, g["rel"], g["n"], g["mb"], g["seg"],
-                                                       extra_bits=x, coco=c))
+        sub = [graphs[i] for i in g["idx"][::8]]
+        srel, sseg = batch.union_relation(sub, g["mb"])
+        sdev = torch.from_numpy(srel).to(dev)
+        c = hc.build_coco(ctx, sdev, [0, 1], key_bits=g["mb"], segment_bits=sseg, symmetric=True)
+        tune.pick(shape, lambda x, m: batch.count_batched(ctx, shape, sdev, len(sub), g["mb"], sseg,
+                                                          extra_bits=x, coco=c, method=m))
         c.free()
-        g["extra"] = tune.choice[shape]
-        print("# autotune %s: extra split bits %d" % (shape, g["extra"]), file=sys.stderr, flush=True)
+        del sdev
+        g["extra"], g["method"] = tune.choice[shape]
+        print("# autotune %s: extra split bits %d, search %s (timings %s)"
+              % (shape, g["extra"], g["method"],
+                 {"%d/%s" % k[1]: round(v, 3) for k, v in tune.timings.items() if k[0] == shape}),
+              file=sys.stderr, flush=True)
 
     def step():
         got = np.zeros(len(specs), dtype=np.uint64)
         for shape, g in groups.items():
             got[g["idx"]] = batch.count_batched(ctx, shape, g["rel"], g["n"], g["mb"], g["seg"],
-                                                extra_bits=g["extra"])
+                                                extra_bits=g["extra"], method=g["method"])
         return got
 
     for _ in range(args.warmup):
@@ -172,7 +180,8 @@ def bench_batch(args):
                                "R-MAT graph, undirected edges log-uniform in [2^10, 2^18], int32 ids",
                    "queries": {s: int(g["n"]) for s, g in groups.items()},
                    "tuples": int(sum(g["rel"].shape[0] for g in groups.values())),
-                   "extra_split_bits": {s: int(g["extra"]) for s, g in groups.items()}},
+                   "extra_split_bits": {s: int(g["extra"]) for s, g in groups.items()},
+                   "search": {s: g["method"] for s, g in groups.items()}},
         "one_query_per_launch": {"value": nq / (ms_seq / 1000.0), "unit": "queries/s",
                                  "ms_total": round(ms_seq, 3)},
         "speedup_vs_one_query_per_launch": round(ms_seq / ms_batched, 3),

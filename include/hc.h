@@ -77,8 +77,22 @@ typedef void (*hc_free_fn)(void* ptr, void* user);
 
 /* Flags of hc_compute_shares / hc_join_count / hc_join_emit */
 #define HC_NO_REWRITE     0x1u    /* disable the Section 6.1 lift */
-#define HC_FORCE_MERGE    0x2u    /* reserved: search method selection */
-#define HC_FORCE_GALLOP   0x4u    /* reserved: search method selection */
+#define HC_FORCE_MERGE    0x2u    /* reserved */
+#define HC_FORCE_GALLOP   0x4u    /* reserved */
+/* hc_join_*: how the operands a level does not iterate are searched (Section 5).
+ * HC_SEARCH_WINDOW (0, default): wave-cooperative -- the step's candidate range
+ * is staged in LDS and searched there.  The others are the paper's per-element
+ * methods, one search per lane: exponential (galloping), quadratic (fixed jumps
+ * of a 128-byte line, applied at two levels, then a scan), linear (a scan), or
+ * chosen per step by the candidate range's size (<= 32: linear, <= 4096:
+ * quadratic, else exponential).  Results do not depend on the method. */
+#define HC_SEARCH_SHIFT       8
+#define HC_SEARCH_MASK        0x700u
+#define HC_SEARCH_WINDOW      0x000u
+#define HC_SEARCH_EXPONENTIAL 0x100u
+#define HC_SEARCH_QUADRATIC   0x200u
+#define HC_SEARCH_LINEAR      0x300u
+#define HC_SEARCH_BY_SIZE     0x400u
 #define HC_KEEP_ORDER     0x8u    /* hc_compute_shares: use var_order_inout as given */
 
 /*

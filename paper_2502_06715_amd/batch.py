@@ -40,29 +40,41 @@ def id_bits(graphs) -> int:
 
 
 class Autotune:
-    """Measured choice of the extra split of every query's first variable (2^extra
-    cells per query), cached per batch signature."""
+    """Measured choice of a batch's launch parameters, cached per batch signature:
+    the extra split of every query's first variable (2^extra cells per query) and
+    the search method of the intersections (the LDS windows or one of Section 5's
+    per-element methods).  Coordinate descent: the split is timed with the
+    default method, then the methods with the chosen split."""
 
-    def __init__(self, candidates=(0, 1, 2, 3)):
-        self.candidates = tuple(candidates)
+    def __init__(self, splits=(0, 1, 2, 3), methods=("window", "exponential", "by_size")):
+        self.splits = tuple(splits)
+        self.methods = tuple(methods)
         self.choice = {}
+        self.timings = {}
+
+    def _best(self, key, cands, run):
+        best, best_t = None, None
+        for c in cands:
+            t0 = time.perf_counter()
+            run(c)
+            dt = time.perf_counter() - t0
+            self.timings[(key, c)] = dt
+            if best_t is None or dt < best_t:
+                best, best_t = c, dt
+        return best
 
     def pick(self, key, run):
+        """run(extra_bits, method) executes the batch once; returns (extra_bits, method)."""
         if key in self.choice:
             return self.choice[key]
-        best, best_t = None, None
-        for x in self.candidates:
-            t0 = time.perf_counter()
-            run(x)
-            dt = time.perf_counter() - t0
-            if best_t is None or dt < best_t:
-                best, best_t = x, dt
+        x = self._best(key, [(s, self.methods[0]) for s in self.splits], lambda c: run(*c))[0]
+        best = self._best(key, [(x, m) for m in self.methods], lambda c: run(*c))
         self.choice[key] = best
         return best
 
 
 def count_batched(ctx: hc.Context, shape: str, rel_dev, n_queries: int, mix_bits: int, seg_bits: int,
-                  extra_bits: int = 0, coco=None):
+                  extra_bits: int = 0, coco=None, method: str = "window"):
     """Per-query counts (uint64 array) of one fused join over a segmented relation."""
     n, atoms = inputs.QUERIES[shape]
     own = coco is None
@@ -71,7 +83,8 @@ def count_batched(ctx: hc.Context, shape: str, rel_dev, n_queries: int, mix_bits
     order = list(range(n))
     shares = [0] * n
     shares[order[0]] = seg_bits + extra_bits
-    cells, _ = hc.join_count_cells(ctx, hc.Query(n, atoms), [coco] * len(atoms), order, shares)
+    cells, _ = hc.join_count_cells(ctx, hc.Query(n, atoms), [coco] * len(atoms), order, shares,
+                                   flags=hc.SEARCH_METHODS[method])
     if own:
         coco.free()
     per_query = cells.reshape(-1, 1 << extra_bits).sum(axis=1)

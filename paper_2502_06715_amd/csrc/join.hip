@@ -75,6 +75,7 @@ struct KStep {
     int32_t has_pred;
     int64_t pred_lo, pred_hi;     // id range of the variable bound here (all entries)
     int32_t pred_word;            // >= 0: each entry also carries its own range (lo, hi inclusive) there
+    int32_t search;               // SEARCH_*: how the other operands are searched
     // EXPAND output
     int32_t W_out;
     int32_t n_copy;
@@ -94,6 +95,9 @@ struct KStep {
 };
 
 enum Mode { M_COUNT = 0, M_DIGEST = 1, M_BITMAP = 2, M_EXPAND = 3, M_TMPW = 4, M_EMIT = 5, M_CELLS = 6 };
+// How a step searches the operands it does not iterate: wave-cooperative LDS
+// windows (the default), or one of the per-element methods of Section 5.
+enum Search { SEARCH_WINDOW = 0, SEARCH_EXPONENTIAL = 1, SEARCH_QUADRATIC = 2, SEARCH_LINEAR = 3, SEARCH_BY_SIZE = 4 };
 // modes that write every match at its rank (from the match words and their prefix)
 constexpr bool mat_mode(int m) { return m == M_EXPAND || m == M_TMPW || m == M_EMIT; }
 
@@ -543,6 +547,44 @@ __device__ inline int32_t lower_bound32(const uint32_t* __restrict__ B, int32_t 
     return l;
 }
 
+// ---- the per-element search methods of Section 5 (one search per lane), each
+// returning the first p in [l, h) with B[p] >= v (h if none):
+//   exponential: jumps of 1, 2, 4, ... from l until one overshoots, then binary search;
+//   quadratic:   fixed jumps of 32 elements (one 128-byte line) from l, applied at two
+//                levels (32 lines, then one line), then a scan of the last line;
+//   linear:      a scan from l.
+// SEARCH_BY_SIZE picks linear / quadratic / exponential from the candidate range's
+// length (at most 32, at most 4096, more), the size-based reading of Section 5.
+__device__ inline int32_t exp_search32(const uint32_t* __restrict__ B, int32_t l, int32_t h, uint32_t v) {
+    if (l >= h || B[l] >= v) return l;
+    int32_t lo = l, step = 1;   // B[lo] < v
+    while (lo + step < h && B[lo + step] < v) {
+        lo += step;
+        step <<= 1;
+    }
+    return lower_bound32(B, lo + 1, lo + step < h ? lo + step : h, v);
+}
+__device__ inline int32_t quad_search32(const uint32_t* __restrict__ B, int32_t l, int32_t h, uint32_t v) {
+    constexpr int32_t kLine = 32, kBig = 32 * kLine;
+    int32_t p = l;   // invariant: every position below p holds a value < v
+    while (p + kBig < h && B[p + kBig - 1] < v) p += kBig;
+    while (p + kLine < h && B[p + kLine - 1] < v) p += kLine;
+    while (p < h && B[p] < v) ++p;
+    return p;
+}
+__device__ inline int32_t lin_search32(const uint32_t* __restrict__ B, int32_t l, int32_t h, uint32_t v) {
+    while (l < h && B[l] < v) ++l;
+    return l;
+}
+__device__ inline int32_t lane_search(int method, const uint32_t* __restrict__ B, int32_t l, int32_t h, uint32_t v) {
+    if (method == SEARCH_BY_SIZE) method = h - l <= 32 ? SEARCH_LINEAR : (h - l <= 4096 ? SEARCH_QUADRATIC
+                                                                                      : SEARCH_EXPONENTIAL);
+    if (method == SEARCH_LINEAR) return lin_search32(B, l, h, v);
+    if (method == SEARCH_QUADRATIC) return quad_search32(B, l, h, v);
+    if (method == SEARCH_EXPONENTIAL) return exp_search32(B, l, h, v);
+    return lower_bound32(B, l, h, v);
+}
+
 template <int MODE, int NOPS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_probe2(KData D, KStep S, const int32_t* __restrict__ F, Seg G,
                                                    const uint64_t* __restrict__ prefix, int64_t e_begin,
@@ -688,6 +730,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                     // shallower level repeats over long runs of entries)
                     constexpr int kReg = NOPS <= 2 ? kWin : kWin / 4;
                     uint32_t* rw = win + (NOPS <= 2 ? 0 : o * kReg);
+                    if (S.search != SEARCH_WINDOW) {
+                        // ---- one search per element (Section 5's methods) from the cursor
+                        int32_t q[kSub];
+#pragma unroll
+                        for (int k = 0; k < kSub; ++k) {
+                            q[k] = v[k] ? lane_search(S.search, B, cur[o], end[o], a[k]) : cur[o];
+                            if (v[k]) f[k] = f[k] && q[k] < end[o] && B[q[k]] == a[k];
+                            if (kMat) pos[o][k] = q[k];
+                        }
+                        int32_t ql = cur[o];
+#pragma unroll
+                        for (int k = 0; k < kSub; ++k) {
+                            const int32_t t = __shfl(q[k], last & 63, 64);
+                            if (k == (last >> 6)) ql = t;
+                        }
+                        cur[o] = uni(ql);   // lower bound of the step's last element
+                        continue;
+                    }
                     if (full <= kReg - 4) {
                         const int32_t base = beg[o] & ~3;
                         const int32_t sh = beg[o] - base;
@@ -853,7 +913,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
 #pragma unroll
                     for (int o = 0; o < NOPS; ++o) {
                         if (o == il || !found) continue;
-                        const int32_t q = lower_bound32(arr[o], bl[o], el[o], av);
+                        const int32_t q = lane_search(S.search, arr[o], bl[o], el[o], av);
                         pp[o] = q;
                         found = q < el[o] && arr[o][q] == av;
                     }
@@ -1078,6 +1138,7 @@ struct Runner {
     bool emit, digest;
     int seg_bits = 0;                        // key bits above the mixed bits (batched queries)
     int range_word = -1;                     // F_0 word of a query batch's id ranges
+    int search_mode = SEARCH_WINDOW;
     unsigned long long* cell_out = nullptr;  // per-cell counts (device), or null
     int64_t cap_entries;
     DevBuf<unsigned long long> acc;
@@ -1208,6 +1269,7 @@ struct Runner {
             S.W_in = Li.W;
             S.k_share = shares[PL.var];
             S.cell_shift = cell_shift[PL.var];
+            S.search = search_mode;
             S.has_pred = q->var_lo != nullptr;
             S.pred_lo = 0;
             S.pred_hi = INT64_MAX;
@@ -1286,6 +1348,7 @@ struct Runner {
             S.cell_shift = cell_shift[PG.var];
             S.has_pred = 0;   // the predicate is applied where the variable is bound
             S.pred_word = -1;
+            S.search = search_mode;
             S.group = g;
             S.n_src = 0;
             for (int t = 0; t < PG.n_ops; ++t)
@@ -1582,6 +1645,8 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
     R.acc = DevBuf<unsigned long long>(R.A, 4);
     R.split = DevBuf<int64_t>(R.A, 2);
     HC_HIP(hipMemsetAsync(R.acc.p, 0, sizeof(unsigned long long) * 4, R.s));
+    R.search_mode = (int)((flags & HC_SEARCH_MASK) >> HC_SEARCH_SHIFT);
+    HC_REQUIRE(R.search_mode <= SEARCH_BY_SIZE, HC_ERR_INVALID, "unknown search method in flags");
     R.setup_layouts();
     // query batches: F_0 entries end with the query's id range (lo, hi inclusive) on
     // the first variable; word 0 (the cell) is the query index

@@ -26,6 +26,13 @@ HC_NO_REWRITE = 0x1
 HC_FORCE_MERGE = 0x2
 HC_FORCE_GALLOP = 0x4
 HC_KEEP_ORDER = 0x8
+HC_SEARCH_WINDOW = 0x000
+HC_SEARCH_EXPONENTIAL = 0x100
+HC_SEARCH_QUADRATIC = 0x200
+HC_SEARCH_LINEAR = 0x300
+HC_SEARCH_BY_SIZE = 0x400
+SEARCH_METHODS = {"window": HC_SEARCH_WINDOW, "exponential": HC_SEARCH_EXPONENTIAL,
+                  "quadratic": HC_SEARCH_QUADRATIC, "linear": HC_SEARCH_LINEAR, "by_size": HC_SEARCH_BY_SIZE}
 
 _STATUS = {1: "HC_ERR_INVALID", 2: "HC_ERR_OOM", 3: "HC_ERR_OVERFLOW", 4: "HC_ERR_DEVICE", 5: "HC_ERR_UNSUPPORTED"}
 

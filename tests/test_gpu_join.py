@@ -293,3 +293,30 @@ def test_st_sparse_small_against_oracle(ctx, name):
             assert hc.join_count(ctx, q, cocos, order, shares) == exp.count
         rows, n_out = _emit_sorted(ctx, q, cocos, order, [1, 0, 1, 0], exp.count + 1)
         assert n_out == exp.count and np.array_equal(rows, exp.rows)
+
+
+@pytest.mark.parametrize("method", ["window", "exponential", "quadratic", "linear", "by_size"])
+def test_search_methods_agree(ctx, method):
+    """Section 5's search methods (and the LDS windows) only change how operands are
+    searched: counts, digests and emitted rows are identical."""
+    flags = hc.SEARCH_METHODS[method]
+    E = inputs.chung_lu(2048, 12000, 77)
+    c = _coco(ctx, E, b=11, symmetric=True)
+    for name in ["triangle", "cycle4", "clique4"]:
+        n, atoms = inputs.QUERIES[name]
+        exp = oracle.gj(n, atoms, [E] * len(atoms), digest=True)
+        for shares in [[0] * n, [2] + [1] * (n - 1)]:
+            log("search %s %s shares=%s" % (method, name, shares))
+            got = hc.join_count(ctx, hc.Query(n, atoms), [c] * len(atoms), list(range(n)), shares, flags=flags,
+                                digest=True)
+            assert got == (exp.count, exp.digest)
+    n, atoms = inputs.QUERIES["lw"]
+    rels = [inputs.random_relation(500, 9, 900 + j, 3) for j in range(4)]
+    exp = oracle.gj(n, atoms, rels, emit=True)
+    cocos = _atom_cocos(ctx, atoms, rels, list(range(n)), 0)
+    rows, n_out = _emit_sorted(ctx, hc.Query(n, atoms), cocos, list(range(n)), [1, 0, 1, 0], exp.count + 1,
+                               flags=flags)
+    assert n_out == exp.count and np.array_equal(rows, exp.rows)
+    if method == "window":
+        with pytest.raises(hc.HCError):
+            hc.join_count(ctx, hc.Query(*inputs.QUERIES["triangle"]), [c] * 3, [0, 1, 2], flags=0x700)
