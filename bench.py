@@ -380,6 +380,127 @@ def bench_tensor(args):
     print(json.dumps(out), flush=True)
 
 
+def _spearman(a, b):
+    ra = np.argsort(np.argsort(a)).astype(np.float64)
+    rb = np.argsort(np.argsort(b)).astype(np.float64)
+    if ra.std() == 0 or rb.std() == 0:
+        return None
+    return float(np.corrcoef(ra, rb)[0, 1])
+
+
+def bench_order_sweep(args):
+    """Every variable order of the 4-clique query Q6 on a directed graph (the
+    workload-3 Chung-Lu graph with every edge oriented from the smaller to the larger
+    id), shares from the model for each order (P = 2^log2_cells): measured join
+    time against the cost model's Eq. (total cost), with the optimizer's own pick
+    (default and joint search) marked."""
+    import itertools
+    import torch
+    from paper_2502_06715_amd import hc, inputs
+
+    E = inputs.config_graph(3)
+    E = np.ascontiguousarray(E[E[:, 0] < E[:, 1]])
+    n, atoms = inputs.QUERIES["clique4"]
+    q = hc.Query(n, atoms)
+    ctx = hc.Context(0)
+    t = torch.from_numpy(E).to("cuda:0")
+    fwd = hc.build_coco(ctx, t, [0, 1])
+    bwd = hc.build_coco(ctx, t, [1, 0])
+    torch.cuda.synchronize()
+
+    def cocos_for(order):
+        pos = {v: i for i, v in enumerate(order)}
+        return [fwd if pos[a[0]] < pos[a[1]] else bwd for a in atoms]
+
+    rows = []
+    for order in itertools.permutations(range(n)):
+        order = list(order)
+        cs = cocos_for(order)
+        _, shares = hc.compute_shares(ctx, q, cs, args.log2_cells, order=order)
+        cost, _ = hc.plan_cost_from_info(q, [c.info for c in cs], order, shares)
+        hc.join_count(ctx, q, cs, order, shares)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cnt = hc.join_count(ctx, q, cs, order, shares)
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t0)
+        rows.append({"order": order, "log2_shares": shares, "count": cnt, "join_ms": round(ms, 3),
+                     "model_cost": cost})
+        print("# order %s shares %s: %.1f ms, model %.3g" % (order, shares, ms, cost), file=sys.stderr, flush=True)
+    if len({r["count"] for r in rows}) != 1:
+        print("counts differ across orders", file=sys.stderr)
+        sys.exit(1)
+    picks = {}
+    for name, flags in [("default", 0), ("joint_search", hc.HC_JOINT_SEARCH),
+                        ("pessimistic", hc.HC_PESSIMISTIC)]:
+        o, sh = hc.compute_shares(ctx, q, cocos_for(list(range(n))), args.log2_cells, flags=flags)
+        picks[name] = {"order": o, "log2_shares": sh}
+    ms = [r["join_ms"] for r in rows]
+    best = min(ms)
+    for name, pk in picks.items():
+        hit = [r for r in rows if r["order"] == pk["order"]]
+        pk["order_join_ms"] = hit[0]["join_ms"] if hit else None
+        pk["order_rank"] = sorted(ms).index(hit[0]["join_ms"]) + 1 if hit else None
+    out = {"metric": "variable-order sweep of the 4-clique query (Q6) on a directed graph",
+           "value": best, "unit": "ms (fastest order)", "n_gpus": 1, "higher_is_better": False,
+           "data": "synthetic", "dtype": "u32", "vs_baseline": None,
+           "config": {"workload": "Q6 over the workload-3 Chung-Lu graph oriented small id -> large id (%d edges)"
+                                  % E.shape[0], "log2_cells": args.log2_cells},
+           "count": rows[0]["count"], "orders": rows, "optimizer": picks,
+           "spearman_model_vs_time": _spearman([r["model_cost"] for r in rows], ms), "roofline": None}
+    fwd.free()
+    bwd.free()
+    print(json.dumps(out), flush=True)
+
+
+def bench_share_sweep(args):
+    """Every power-of-two factorisation P_a x P_b x P_c = 2^10 of the triangle query
+    on the R-MAT scale-20 graph (order a,b,c, CoCo built once): measured join time
+    against the model, with the optimizer's picks marked."""
+    import torch
+    from paper_2502_06715_amd import hc, inputs
+
+    E = inputs.config_graph(2)
+    n, atoms = inputs.QUERIES["triangle"]
+    q = hc.Query(n, atoms)
+    ctx = hc.Context(0)
+    c = hc.build_coco(ctx, torch.from_numpy(E).to("cuda:0"), [0, 1], key_bits=20)
+    torch.cuda.synchronize()
+    K = 10
+    rows = []
+    for ka in range(K + 1):
+        for kb in range(K + 1 - ka):
+            sh = [ka, kb, K - ka - kb]
+            cost, _ = hc.plan_cost_from_info(q, [c.info] * 3, [0, 1, 2], sh)
+            hc.join_count(ctx, q, [c] * 3, [0, 1, 2], sh)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cnt = hc.join_count(ctx, q, [c] * 3, [0, 1, 2], sh)
+            torch.cuda.synchronize()
+            ms = 1000.0 * (time.perf_counter() - t0)
+            rows.append({"log2_shares": sh, "count": cnt, "join_ms": round(ms, 3), "model_cost": cost})
+            print("# shares %s: %.1f ms, model %.3g" % (sh, ms, cost), file=sys.stderr, flush=True)
+    if len({r["count"] for r in rows}) != 1:
+        print("counts differ across share vectors", file=sys.stderr)
+        sys.exit(1)
+    ms = [r["join_ms"] for r in rows]
+    picks = {}
+    for name, flags in [("default", 0), ("joint_search", hc.HC_JOINT_SEARCH), ("pessimistic", hc.HC_PESSIMISTIC)]:
+        o, sh = hc.compute_shares(ctx, q, [c] * 3, K, flags=flags | hc.HC_KEEP_ORDER, order=[0, 1, 2])
+        hit = [r for r in rows if r["log2_shares"] == sh]
+        picks[name] = {"log2_shares": sh, "join_ms": hit[0]["join_ms"],
+                       "rank": sorted(ms).index(hit[0]["join_ms"]) + 1}
+    best = min(rows, key=lambda r: r["join_ms"])
+    out = {"metric": "share sweep (all factorisations of 2^10) of the triangle query on R-MAT scale 20",
+           "value": best["join_ms"], "unit": "ms (fastest share vector)", "n_gpus": 1, "higher_is_better": False,
+           "data": "synthetic", "dtype": "u32", "vs_baseline": None,
+           "config": {"workload": "triangle, R-MAT scale 20, 2^24 edges, order a,b,c, P = 2^10"},
+           "count": rows[0]["count"], "fastest": best, "optimizer": picks, "shares": rows,
+           "spearman_model_vs_time": _spearman([r["model_cost"] for r in rows], ms), "roofline": None}
+    c.free()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -418,6 +539,10 @@ def main():
         return bench_serve(args)
     if args.config == 6:
         return bench_tensor(args)
+    if args.config == 7:
+        return bench_order_sweep(args)
+    if args.config == 8:
+        return bench_share_sweep(args)
 
     import torch
     from paper_2502_06715_amd import hc, inputs

@@ -94,6 +94,8 @@ typedef void (*hc_free_fn)(void* ptr, void* user);
 #define HC_SEARCH_LINEAR      0x300u
 #define HC_SEARCH_BY_SIZE     0x400u
 #define HC_KEEP_ORDER     0x8u    /* hc_compute_shares: use var_order_inout as given */
+#define HC_JOINT_SEARCH   0x10u   /* hc_compute_shares: search orders and shares jointly */
+#define HC_PESSIMISTIC    0x20u   /* cost model: upper-bound cardinality estimator */
 
 /*
  * Create a context on HIP device `device`, ordering work on `hip_stream` (a
@@ -198,6 +200,11 @@ hc_status hc_partition_sizes(hc_ctx* ctx, const hc_coco* coco, const int32_t* lo
  * C_i (Eq. (total cost)).  Vectors costing more than twice the unpartitioned
  * cost, or with a share P_v such that |Dom(X_v)| < 3 P_v ln P_v, are pruned;
  * the minimum evenness E = sum_i P_sigma(i) * max(1 - i/100, 3/4) wins.
+ * With HC_JOINT_SEARCH (and not HC_KEEP_ORDER) orders and share vectors are
+ * searched together: a vector of any order is feasible when it costs at most
+ * twice the best unpartitioned cost over all orders.  HC_PESSIMISTIC bounds
+ * the prefix bindings from above (longest lists, whole atoms inside the
+ * prefix) instead of chaining average list sizes.
  *   atom_index       host array of n_atoms CoCo handles (may repeat)
  *   var_order_inout  host [n_vars]; if HC_KEEP_ORDER is set it is the order to
  *                    use, else it receives the chosen order
@@ -214,6 +221,19 @@ hc_status hc_compute_shares(hc_ctx* ctx, const hc_query* q, const hc_coco* const
  */
 hc_status hc_compute_shares_from_info(const hc_query* q, const hc_coco_info* infos, int32_t log2_total_P,
                                       uint32_t flags, int32_t* var_order_inout, int32_t* log2_shares_out);
+
+/*
+ * The cost model's figure for one plan (host-only, from statistics): Eq. (total
+ * cost) of Section 6.3 for the order var_order and the shares log2_shares
+ * (NULL: all zero) -- the per-level costs of Section 6.2 bounded with the
+ * Lemma, each multiplied by the product of the shares of the later variables.
+ * flags: HC_NO_REWRITE, HC_PESSIMISTIC.  per_level_out (host [n_vars] in
+ * level order, may be NULL) receives the replicated per-level costs,
+ * total_out (host) their sum.  Errors: HC_ERR_INVALID.
+ */
+hc_status hc_plan_cost_from_info(const hc_query* q, const hc_coco_info* infos, const int32_t* var_order,
+                                 const int32_t* log2_shares, uint32_t flags, double* per_level_out,
+                                 double* total_out);
 
 /*
  * Count |Q(D)| (Section 5): every HyperCube cell (s_1..s_n), s_v in

@@ -208,6 +208,21 @@ hc_status hc_partition_sizes(hc_ctx* ctx, const hc_coco* c, const int32_t* log2_
     });
 }
 
+static std::vector<hc::AtomStats> stats_of_info(const hc_query* q, const hc_coco_info* infos) {
+    std::vector<hc::AtomStats> st((size_t)q->n_atoms);
+    for (int j = 0; j < q->n_atoms; ++j) {
+        HC_REQUIRE(infos[j].arity == q->atom_arity[j], HC_ERR_INVALID, "info arity does not match its atom");
+        st[j].rows = (double)infos[j].n_unique;
+        st[j].arity = infos[j].arity;
+        st[j].dom_bits = infos[j].key_bits;
+        for (int k = 0; k < 4; ++k) {
+            st[j].distinct[k] = (double)infos[j].distinct[k];
+            st[j].maxdeg[k] = (double)infos[j].max_children[k];
+        }
+    }
+    return st;
+}
+
 static std::vector<hc::AtomStats> stats_of(const hc_query* q, const hc_coco* const* atoms) {
     std::vector<hc::AtomStats> st((size_t)q->n_atoms);
     for (int j = 0; j < q->n_atoms; ++j) {
@@ -217,7 +232,10 @@ static std::vector<hc::AtomStats> stats_of(const hc_query* q, const hc_coco* con
         st[j].rows = (double)c->n_unique;
         st[j].arity = c->arity;
         st[j].dom_bits = c->key_bits;
-        for (int k = 0; k < 4; ++k) st[j].distinct[k] = (double)c->distinct[k];
+        for (int k = 0; k < 4; ++k) {
+            st[j].distinct[k] = (double)c->distinct[k];
+            st[j].maxdeg[k] = (double)c->max_children[k];
+        }
     }
     return st;
 }
@@ -243,15 +261,22 @@ hc_status hc_compute_shares_from_info(const hc_query* q, const hc_coco_info* inf
         HC_REQUIRE(infos && var_order_inout && log2_shares_out, HC_ERR_INVALID, "NULL argument");
         HC_REQUIRE(log2_total_P >= 0 && log2_total_P <= 24, HC_ERR_INVALID, "log2_total_P must be 0..24");
         hc::validate_query(q, 4);
-        std::vector<hc::AtomStats> st((size_t)q->n_atoms);
-        for (int j = 0; j < q->n_atoms; ++j) {
-            HC_REQUIRE(infos[j].arity == q->atom_arity[j], HC_ERR_INVALID, "info arity does not match its atom");
-            st[j].rows = (double)infos[j].n_unique;
-            st[j].arity = infos[j].arity;
-            st[j].dom_bits = infos[j].key_bits;
-            for (int k = 0; k < 4; ++k) st[j].distinct[k] = (double)infos[j].distinct[k];
-        }
-        hc::choose_shares(q, st, log2_total_P, flags, var_order_inout, log2_shares_out);
+        hc::choose_shares(q, stats_of_info(q, infos), log2_total_P, flags, var_order_inout, log2_shares_out);
+        return HC_OK;
+    } catch (const hc::Error& e) {
+        return e.st;
+    } catch (...) {
+        return HC_ERR_INVALID;
+    }
+}
+
+hc_status hc_plan_cost_from_info(const hc_query* q, const hc_coco_info* infos, const int32_t* var_order,
+                                 const int32_t* log2_shares, uint32_t flags, double* per_level_out,
+                                 double* total_out) {
+    try {
+        check_query_ptrs(q);
+        HC_REQUIRE(infos && var_order && total_out, HC_ERR_INVALID, "NULL argument");
+        *total_out = hc::plan_cost(q, stats_of_info(q, infos), var_order, log2_shares, flags, per_level_out);
         return HC_OK;
     } catch (const hc::Error& e) {
         return e.st;

@@ -207,11 +207,16 @@ void validate_query(const hc_query* q, int max_arity);
 struct AtomStats {
     double rows;           // |R_j| (unique)
     double distinct[4];    // distinct values per original column
+    double maxdeg[4];      // longest child list below CoCo level r (0 if unknown)
     int32_t arity;
     int32_t dom_bits;
 };
 void choose_shares(const hc_query* q, const std::vector<AtomStats>& st, int K, uint32_t flags,
                    int32_t* order_inout, int32_t* shares_out);
+// Cost of one (order, shares) plan under the model: per-level costs (n entries,
+// already multiplied by the replication of Eq. (total cost)) and their sum.
+double plan_cost(const hc_query* q, const std::vector<AtomStats>& st, const int32_t* order, const int32_t* shares,
+                 uint32_t flags, double* per_level);
 
 // ---------------------------------------------------------------- join (join.hip)
 void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order,

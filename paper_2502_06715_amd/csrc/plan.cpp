@@ -176,7 +176,15 @@ struct LevelCost {
     double total;
 };
 
-static LevelCost level_costs(const hc_query* q, const std::vector<AtomStats>& st, const Plan& p) {
+// Pessimistic variant (HC_PESSIMISTIC, an upper bound in place of the averages'
+// chain, in the role of the estimator the paper cites): the bindings of the prefix
+// X_1..X_i are at most those of X_1..X_{i-1} times the longest list of the level's
+// shortest operand, and at most |R_j| times the domains of the prefix variables
+// outside R_j for every atom R_j whose variables all lie in the prefix; Sum min N
+// of the Lemma is that bound, and the ratio inside the logarithm keeps the
+// averages of the worked example.
+static LevelCost level_costs(const hc_query* q, const std::vector<AtomStats>& st, const Plan& p,
+                             bool pessimistic = false) {
     LevelCost lc{};
     // column index of a variable inside atom j
     auto col_of = [&](int j, int v) {
@@ -198,6 +206,38 @@ static LevelCost level_costs(const hc_query* q, const std::vector<AtomStats>& st
         if (nops <= 1) return bind * mn;
         return (double)nops * bind * mn * std::log2(1.0 + mx / mn);
     };
+    // longest list an operand can offer (pessimistic estimator)
+    auto max_n = [&](const PlanOp& o, int var) {
+        const AtomStats& a = st[o.atom];
+        if (o.kind == OP_V0) return std::max(1.0, a.distinct[col_of(o.atom, var)]);
+        const double md = a.maxdeg[o.lvl - 1];
+        return md > 0 ? md : std::max(1.0, a.rows);
+    };
+    std::vector<double> dom(p.n_vars, 1e300);
+    {
+        int off = 0;
+        for (int j = 0; j < q->n_atoms; ++j) {
+            for (int c = 0; c < q->atom_arity[j]; ++c)
+                dom[q->atom_vars[off + c]] = std::min(dom[q->atom_vars[off + c]], std::max(1.0, st[j].distinct[c]));
+            off += q->atom_arity[j];
+        }
+    }
+    auto prefix_cap = [&](int i) {   // bound on |Q(X_sigma(1..i+1))| from whole atoms inside the prefix
+        double cap = 1e300;
+        for (int j = 0; j < q->n_atoms; ++j) {
+            bool inside = true;
+            for (int r = 0; r < p.atom_arity[j]; ++r) inside = inside && p.pos[p.atom_lvl_var[j][r]] <= i;
+            if (!inside) continue;
+            double b = std::max(1.0, st[j].rows);
+            for (int t = 0; t <= i; ++t) {
+                bool in_atom = false;
+                for (int r = 0; r < p.atom_arity[j]; ++r) in_atom = in_atom || p.atom_lvl_var[j][r] == p.order[t];
+                if (!in_atom) b *= dom[p.order[t]];
+            }
+            cap = std::min(cap, b);
+        }
+        return cap;
+    };
     double bind = 1.0;   // bindings of the prefix at the current level
     double tmp_size[kMaxGroups];
     for (int i = 0; i < p.n_vars; ++i) {
@@ -215,15 +255,22 @@ static LevelCost level_costs(const hc_query* q, const std::vector<AtomStats>& st
             tmp_size[g] = mn;
             extra += cost_of(p.groups[g].n_ops, bind, mn, mx);
         }
-        double mn = 1e300, mx = 0;
+        double mn = 1e300, mx = 0, mn_max = 1e300;
         for (int t = 0; t < L.n_ops; ++t) {
             const double n = L.ops[t].kind == OP_TMP ? tmp_size[L.ops[t].group] : avg_n(L.ops[t], L.var);
             mn = std::min(mn, n);
             mx = std::max(mx, n);
+            if (L.ops[t].kind != OP_TMP) mn_max = std::min(mn_max, max_n(L.ops[t], L.var));
         }
-        // lifted work is charged to the level where it runs
-        lc.C[i] = cost_of(L.n_ops, bind, mn, mx) + extra;
-        bind = bind * mn;
+        if (!pessimistic) {
+            // lifted work is charged to the level where it runs
+            lc.C[i] = cost_of(L.n_ops, bind, mn, mx) + extra;
+            bind = bind * mn;
+        } else {
+            const double next = std::min(bind * std::min(mn_max, 1e300), prefix_cap(i));   // Sum min N bound
+            lc.C[i] = (L.n_ops <= 1 ? next : (double)L.n_ops * next * std::log2(1.0 + mx / mn)) + extra;
+            bind = next;
+        }
     }
     lc.total = 0;
     for (int i = 0; i < p.n_vars; ++i) lc.total += lc.C[i];
@@ -243,10 +290,124 @@ static double share_cost(const Plan& p, const LevelCost& lc, const int* k_of_var
     return tot;
 }
 
+// |Dom(X_v)|: the fewest distinct values any atom holding v offers; key bits bound the share
+static void domains(const hc_query* q, const std::vector<AtomStats>& st, std::vector<double>& dom,
+                    std::vector<int>& maxbits) {
+    dom.assign(q->n_vars, 1e300);
+    maxbits.assign(q->n_vars, 32);
+    int off = 0;
+    for (int j = 0; j < q->n_atoms; ++j) {
+        for (int c = 0; c < q->atom_arity[j]; ++c) {
+            const int v = q->atom_vars[off + c];
+            dom[v] = std::min(dom[v], st[j].distinct[c]);
+            maxbits[v] = std::min(maxbits[v], st[j].dom_bits);
+        }
+        off += q->atom_arity[j];
+    }
+}
+
+static bool share_feasible(const std::vector<int>& kv, const std::vector<double>& dom, const std::vector<int>& maxbits) {
+    for (size_t v = 0; v < kv.size(); ++v) {
+        if (kv[v] > maxbits[v]) return false;
+        if (kv[v] > 0) {
+            const double P = std::ldexp(1.0, kv[v]);
+            if (dom[v] < 3.0 * P * std::log(P)) return false;
+        }
+    }
+    return true;
+}
+
+// Joint search (HC_JOINT_SEARCH): every order and every share vector of the plan
+// decision of Section 6.3; a vector is feasible when its Eq. (total cost) is at most
+// twice the best unpartitioned cost over all orders and it passes the domain rule;
+// the minimum evenness wins, then the lower cost, then the earlier order.
+static void joint_search(const hc_query* q, const std::vector<AtomStats>& st, int K, uint32_t flags,
+                         int32_t* order_out, int32_t* shares_out) {
+    const int n = q->n_vars;
+    const bool rewrite = !(flags & HC_NO_REWRITE);
+    const bool pess = (flags & HC_PESSIMISTIC) != 0;
+    std::vector<std::vector<int32_t>> orders;
+    std::vector<Plan> plans;
+    std::vector<LevelCost> costs;
+    std::vector<int32_t> o(n);
+    std::iota(o.begin(), o.end(), 0);
+    double base = 1e308;
+    do {
+        orders.push_back(o);
+        plans.push_back(compile_plan(q, o.data(), rewrite));
+        costs.push_back(level_costs(q, st, plans.back(), pess));
+        base = std::min(base, costs.back().total);
+    } while (std::next_permutation(o.begin(), o.end()));
+    std::vector<double> dom;
+    std::vector<int> maxbits;
+    domains(q, st, dom, maxbits);
+    bool found = false, fb_found = false;
+    double best_E = 1e308, best_c = 1e308, fb_c = 1e308;
+    std::vector<int> best_k(n, 0), fb_k(n, 0), k(n, 0), kv(n, 0);
+    size_t best_o = 0, fb_o = 0;
+    for (size_t t = 0; t < orders.size(); ++t) {
+        const Plan& p = plans[t];
+        std::function<void(int, int)> rec = [&](int lvl, int left) {
+            if (lvl < n - 1) {
+                for (int x = 0; x <= left; ++x) {
+                    k[lvl] = x;
+                    rec(lvl + 1, left - x);
+                }
+                return;
+            }
+            k[lvl] = left;
+            for (int i = 0; i < n; ++i) kv[p.order[i]] = k[i];
+            if (!share_feasible(kv, dom, maxbits)) return;
+            const double c = share_cost(p, costs[t], kv.data());
+            if (c < fb_c) {
+                fb_c = c;
+                fb_k = kv;
+                fb_o = t;
+                fb_found = true;
+            }
+            if (c > 2.0 * base) return;
+            double E = 0;
+            for (int i = 0; i < n; ++i) E += std::ldexp(1.0, k[i]) * std::max(1.0 - (i + 1) / 100.0, 0.75);
+            if (!found || E < best_E - 1e-9 || (std::fabs(E - best_E) <= 1e-9 && c < best_c * (1 - 1e-12))) {
+                found = true;
+                best_E = E;
+                best_c = c;
+                best_k = kv;
+                best_o = t;
+            }
+        };
+        rec(0, K);
+    }
+    const size_t ot = found ? best_o : fb_o;
+    const std::vector<int>& pick = found ? best_k : (fb_found ? fb_k : std::vector<int>(n, 0));
+    for (int i = 0; i < n; ++i) order_out[i] = orders[ot][i];
+    for (int v = 0; v < n; ++v) shares_out[v] = pick[v];
+}
+
+double plan_cost(const hc_query* q, const std::vector<AtomStats>& st, const int32_t* order, const int32_t* shares,
+                 uint32_t flags, double* per_level) {
+    validate_query(q, 4);
+    const Plan p = compile_plan(q, order, !(flags & HC_NO_REWRITE));
+    const LevelCost lc = level_costs(q, st, p, (flags & HC_PESSIMISTIC) != 0);
+    double tot = 0;
+    for (int i = 0; i < p.n_vars; ++i) {
+        double rep = 1;
+        for (int j = i + 1; j < p.n_vars; ++j) rep *= std::ldexp(1.0, shares ? shares[p.order[j]] : 0);
+        if (per_level) per_level[i] = rep * lc.C[i];
+        tot += rep * lc.C[i];
+    }
+    return tot;
+}
+
 void choose_shares(const hc_query* q, const std::vector<AtomStats>& st, int K, uint32_t flags, int32_t* order_inout,
                    int32_t* shares_out) {
     const int n = q->n_vars;
     const bool rewrite = !(flags & HC_NO_REWRITE);
+    const bool pess = (flags & HC_PESSIMISTIC) != 0;
+    if ((flags & HC_JOINT_SEARCH) && !(flags & HC_KEEP_ORDER)) {
+        joint_search(q, st, K, flags, order_inout, shares_out);
+        return;
+    }
     std::vector<int32_t> best_order(n);
     if (flags & HC_KEEP_ORDER) {
         check_order(q, order_inout);
@@ -259,7 +420,7 @@ void choose_shares(const hc_query* q, const std::vector<AtomStats>& st, int K, u
         double best = 1e308;
         do {
             Plan p = compile_plan(q, o.data(), rewrite);
-            const double c = level_costs(q, st, p).total;
+            const double c = level_costs(q, st, p, pess).total;
             if (c < best * (1 - 1e-12)) {
                 best = c;
                 best_order = o;
@@ -268,21 +429,10 @@ void choose_shares(const hc_query* q, const std::vector<AtomStats>& st, int K, u
     }
     for (int i = 0; i < n; ++i) order_inout[i] = best_order[i];
     Plan p = compile_plan(q, best_order.data(), rewrite);
-    const LevelCost lc = level_costs(q, st, p);
-    // |Dom(X_v)|: the fewest distinct values any atom holding v offers
-    std::vector<double> dom(n, 1e300);
-    std::vector<int> maxbits(n, 32);
-    {
-        int off = 0;
-        for (int j = 0; j < q->n_atoms; ++j) {
-            for (int c = 0; c < q->atom_arity[j]; ++c) {
-                const int v = q->atom_vars[off + c];
-                dom[v] = std::min(dom[v], st[j].distinct[c]);
-                maxbits[v] = std::min(maxbits[v], st[j].dom_bits);
-            }
-            off += q->atom_arity[j];
-        }
-    }
+    const LevelCost lc = level_costs(q, st, p, pess);
+    std::vector<double> dom;
+    std::vector<int> maxbits;
+    domains(q, st, dom, maxbits);
     // enumerate all power-of-two share vectors with sum k_v = K (shares by level)
     std::vector<int> k(n, 0), kv(n, 0), best_k(n, 0);
     double best_E = 1e308, best_cost = 1e308;
@@ -302,15 +452,7 @@ void choose_shares(const hc_query* q, const std::vector<AtomStats>& st, int K, u
             return;
         }
         for (int i = 0; i < n; ++i) kv[p.order[i]] = k[i];
-        bool dom_ok = true;
-        for (int v = 0; v < n; ++v) {
-            if (kv[v] > maxbits[v]) dom_ok = false;
-            if (kv[v] > 0) {
-                const double P = std::ldexp(1.0, kv[v]);
-                if (dom[v] < 3.0 * P * std::log(P)) dom_ok = false;
-            }
-        }
-        if (!dom_ok) return;
+        if (!share_feasible(kv, dom, maxbits)) return;
         const double c = share_cost(p, lc, kv.data());
         if (c < fb_cost) {
             fb_cost = c;

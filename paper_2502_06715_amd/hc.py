@@ -26,6 +26,8 @@ HC_NO_REWRITE = 0x1
 HC_FORCE_MERGE = 0x2
 HC_FORCE_GALLOP = 0x4
 HC_KEEP_ORDER = 0x8
+HC_JOINT_SEARCH = 0x10
+HC_PESSIMISTIC = 0x20
 HC_SEARCH_WINDOW = 0x000
 HC_SEARCH_EXPONENTIAL = 0x100
 HC_SEARCH_QUADRATIC = 0x200
@@ -85,6 +87,7 @@ SIGNATURES = {
     "hc_join_workspace_bound": (ctypes.c_int, [P, P, P, P, P, U32, I64, I64, P]),
     "hc_join_count_multi": (ctypes.c_int, [P, P, P, P, U32, I64, P, P]),
     "hc_plan_describe": (ctypes.c_int, [P, P, U32, P, ctypes.c_size_t]),
+    "hc_plan_cost_from_info": (ctypes.c_int, [P, P, P, P, U32, P, P]),
     "hc_ctx_set_profiling": (ctypes.c_int, [P, ctypes.c_int]),
     "hc_ctx_get_timing": (ctypes.c_int, [P, P]),
 }
@@ -357,6 +360,22 @@ def join_emit(ctx: Context, q: Query, cocos, order, log2_shares=None, flags: int
         raise e
     ctx.check(st)
     return out[: n_out.value], int(n_out.value)
+
+
+def plan_cost_from_info(q: Query, infos, order, log2_shares=None, flags: int = 0):
+    """(total, per-level costs) of one plan under the cost model (host-only)."""
+    arr = (CocoInfo * len(infos))(*infos)
+    order_a = _i32(order)
+    sh = _i32(log2_shares) if log2_shares is not None else None
+    per = np.zeros(q.n_vars, dtype=np.float64)
+    tot = ctypes.c_double(0)
+    qc = q.c()
+    st = lib().hc_plan_cost_from_info(ctypes.byref(qc), arr, order_a.ctypes.data,
+                                      sh.ctypes.data if sh is not None else None, flags, per.ctypes.data,
+                                      ctypes.byref(tot))
+    if st != HC_OK:
+        raise HCError(st, "hc_plan_cost_from_info failed")
+    return float(tot.value), per
 
 
 def plan_describe(q: Query, order, flags: int = 0) -> dict:

@@ -128,3 +128,69 @@ def test_cost_rule_and_evenness_hand_example():
     info = _info(1 << 20, 1 << 20, 24)
     order, shares = hc.compute_shares_from_info(hc.Query(n, atoms), [info] * 3, 9, order=[0, 1, 2])
     assert shares == [5, 4, 0]
+
+
+def test_plan_cost_hand_example():
+    """The same degree-1 triangle: C_a = 2N, C_b = 2N log2(1+N), C_c = 2N, and Eq.
+    (total cost) replicates level i by the shares of the later variables."""
+    n, atoms = inputs.QUERIES["triangle"]
+    N = 1 << 20
+    info = _info(N, N, 24)
+    q = hc.Query(n, atoms)
+    tot, per = hc.plan_cost_from_info(q, [info] * 3, [0, 1, 2])
+    exp = [2 * N, 2 * N * math.log2(1 + N), 2 * N]
+    assert np.allclose(per, exp) and math.isclose(tot, sum(exp))
+    tot2, per2 = hc.plan_cost_from_info(q, [info] * 3, [0, 1, 2], [5, 4, 0])
+    assert np.allclose(per2, [16 * exp[0], exp[1], exp[2]]) and math.isclose(tot2, sum(per2))
+
+
+def test_pessimistic_estimator_bounds_prefix_bindings():
+    """HC_PESSIMISTIC: a path query R(a,b), S(b,c) over a star (one centre of degree
+    d): with one operand per level the level cost is the binding bound itself, and
+    it must not be below the true number of prefix bindings (a: d+1 values;
+    (a,b): 2d edges; (a,b,c): paths of length 2 = d^2 + d)."""
+    d = 50
+    n, atoms = 3, [(0, 1), (1, 2)]
+    info = _info(2 * d, d + 1, 8)
+    info.max_children[0] = d
+    q = hc.Query(n, atoms)
+    _, per = hc.plan_cost_from_info(q, [info] * 2, [0, 1, 2], flags=hc.HC_PESSIMISTIC)
+    assert per[0] >= d + 1
+    # levels with two operands multiply the bound by |S| log2(1 + max/min) >= 2 * 1
+    assert per[2] >= d * d + d
+
+
+@pytest.mark.parametrize("name,K", [("triangle", 8), ("clique4", 6), ("cycle4", 5)])
+def test_joint_search_is_the_minimum_evenness_feasible_plan(name, K):
+    """HC_JOINT_SEARCH against an independent enumeration of every order and share
+    vector through the cost function: the chosen plan is feasible (cost at most twice
+    the best unpartitioned cost, domain rule) and no feasible plan has a smaller
+    evenness."""
+    n, atoms = inputs.QUERIES[name]
+    info = _info(1 << 22, 200000, 18)
+    info.max_children[0] = 5000
+    q = hc.Query(n, atoms)
+    infos = [info] * len(atoms)
+    order, shares = hc.compute_shares_from_info(q, infos, K, flags=hc.HC_JOINT_SEARCH)
+    base = min(hc.plan_cost_from_info(q, infos, list(o))[0] for o in itertools.permutations(range(n)))
+
+    def evenness(o, sh):
+        return sum(2 ** sh[o[i]] * max(1 - (i + 1) / 100, 0.75) for i in range(n))
+
+    def feasible(o, sh):
+        for s in sh:
+            if s and 200000 < 3 * 2 ** s * math.log(2 ** s):
+                return False
+        return hc.plan_cost_from_info(q, infos, list(o), sh)[0] <= 2 * base * (1 + 1e-12)
+
+    assert sum(shares) == K and feasible(order, shares)
+    e_star = evenness(order, shares)
+    for o in itertools.permutations(range(n)):
+        for comp in itertools.product(range(K + 1), repeat=n):
+            if sum(comp) != K:
+                continue
+            sh = [0] * n
+            for i in range(n):
+                sh[o[i]] = comp[i]
+            if feasible(o, sh):
+                assert evenness(o, sh) >= e_star - 1e-9
