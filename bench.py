@@ -614,7 +614,7 @@ def main():
                 traffic = t.get("bytes_per_launch")
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_probe<M_COUNT> (deepest level)", "avg_launch_ms": round(avg_ms, 3),
+                "kernel": "k_probe2<M_COUNT, 2> (deepest level)", "avg_launch_ms": round(avg_ms, 3),
                 "launches_per_step": launches / args.steps,
                 "algorithmic_bytes_per_launch": per_launch}
     out = {
