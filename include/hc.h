@@ -42,7 +42,8 @@ typedef enum {
     HC_ERR_OOM = 2,          /* the allocator refused a request */
     HC_ERR_OVERFLOW = 3,     /* emit: more result rows than the capacity */
     HC_ERR_DEVICE = 4,       /* a HIP runtime call or a device-side check failed */
-    HC_ERR_UNSUPPORTED = 5   /* valid but outside what this build implements */
+    HC_ERR_UNSUPPORTED = 5,  /* valid but outside what this build implements */
+    HC_ERR_CANCELLED = 6     /* the context's cancel request stopped the call */
 } hc_status;
 
 typedef enum { HC_I32 = 0, HC_I64 = 1 } hc_dtype;
@@ -344,6 +345,18 @@ typedef struct {
     uint64_t leaf_items;        /* smallest-operand elements visited at the deepest level */
 } hc_timing;
 hc_status hc_ctx_set_profiling(hc_ctx* ctx, int on);
+
+/*
+ * Cancel request (for callers that bound a request's time, e.g. a serving loop):
+ * on != 0 raises it, on = 0 withdraws it.  While it is raised, every join call on
+ * this context returns HC_ERR_CANCELLED: a call already running notices it
+ * between its launches and inside the intersection kernels, whose waves read
+ * the request (a word of pinned host memory the context owns) every 64 work
+ * chunks and leave; the call's outputs are then unspecified.  Safe to call from
+ * another thread while a join runs on ctx: it is a plain store, no stream
+ * operation.  Errors: HC_ERR_INVALID (NULL ctx).
+ */
+hc_status hc_ctx_cancel(hc_ctx* ctx, int32_t on);
 hc_status hc_ctx_get_timing(const hc_ctx* ctx, hc_timing* t);
 
 #ifdef __cplusplus

@@ -92,11 +92,32 @@ hc_status hc_ctx_create(int device, void* hip_stream, hc_alloc_fn alloc, hc_free
         return HC_ERR_DEVICE;
     }
     c->num_cus = prop.multiProcessorCount;
+    // The cancel word lives in coherent pinned host memory: the host sets it with a
+    // plain store while kernels run (no stream operation that would queue behind them).
+    if (hipHostMalloc((void**)&c->h_cancel, sizeof(int), hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&c->d_cancel, c->h_cancel, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        hc_ctx_destroy(c);
+        return HC_ERR_DEVICE;
+    }
+    __atomic_store_n(c->h_cancel, 0, __ATOMIC_SEQ_CST);
     *out = c;
     return HC_OK;
 }
 
-void hc_ctx_destroy(hc_ctx* ctx) { delete ctx; }
+void hc_ctx_destroy(hc_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->h_cancel) (void)hipHostFree(ctx->h_cancel);
+    delete ctx;
+}
+
+hc_status hc_ctx_cancel(hc_ctx* ctx, int32_t on) {
+    if (!ctx) return HC_ERR_INVALID;
+    ctx->cancel.store(on ? 1 : 0);
+    __atomic_store_n(ctx->h_cancel, on ? 1 : 0, __ATOMIC_SEQ_CST);
+    return HC_OK;
+}
 
 const char* hc_last_error(const hc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -114,6 +115,9 @@ struct hc_ctx {
     int profiling = 0;
     hc_timing timing{};
     int num_cus = 256;
+    std::atomic<int> cancel{0};            // cancel request (host view)
+    int* h_cancel = nullptr;               // the same request in coherent pinned host memory,
+    int* d_cancel = nullptr;               // read by kernels through this device address
 };
 
 struct hc_coco {

@@ -51,6 +51,7 @@ struct KData {
     Mixer mix;
     int32_t b;
     int32_t dtype64;
+    const int* cancel;   // nonzero: the caller cancelled the call (polled between work chunks)
 };
 
 struct KOp {
@@ -618,9 +619,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
     }
     const int xcd = (int)(blockIdx.x % kXcd);
     const uint64_t c_lo = n_chunks * (uint64_t)xcd / kXcd, c_hi = n_chunks * (uint64_t)(xcd + 1) / kXcd;
+    int polls = 0;
     for (;;) {
         unsigned long long t = 0;
-        if (lane == 0) t = atomicAdd(&queue[xcd], 1ull);
+        int stop = 0;
+        if (lane == 0) {
+            t = atomicAdd(&queue[xcd], 1ull);
+            // the cancel word is host memory: read it every 64th chunk
+            if ((polls++ & 63) == 0) stop = __atomic_load_n(D.cancel, __ATOMIC_RELAXED);
+        }
+        if (uni(stop)) break;
         const uint64_t c = c_lo + uni64(t);
         if (c >= c_hi) break;
         const uint64_t r_begin = c * kChunk;
@@ -1169,8 +1177,11 @@ struct Runner {
         uint64_t v = 0;
         HC_HIP(hipMemcpyAsync(&v, p, sizeof(v), hipMemcpyDeviceToHost, s));
         HC_HIP(hipStreamSynchronize(s));
+        check_cancel();
         return v;
     }
+    // every level and chunk reads sizes back, so a cancel request stops the call there
+    void check_cancel() const { HC_REQUIRE(!ctx->cancel.load(), HC_ERR_CANCELLED, "cancelled"); }
 
     void setup_layouts() {
         for (int i = 0; i <= P.n_vars; ++i) {
@@ -1633,8 +1644,10 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
         }
         for (int r = 0; r < 3; ++r) R.D.atoms[j].O[r] = r + 1 < c->arity ? c->O[r] : nullptr;
     }
+    HC_REQUIRE(!ctx->cancel.load(), HC_ERR_CANCELLED, "cancelled");
     R.D.mix = make_mixer(mb, seed, b);
     R.D.b = b;
+    R.D.cancel = ctx->d_cancel;
     R.D.dtype64 = dtype64;
     R.emit = emit;
     R.digest = digest != nullptr;
@@ -1705,6 +1718,7 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
     if (cell_counts)
         HC_HIP(hipMemcpyAsync(cell_counts, cells.p, sizeof(unsigned long long) * ncell, hipMemcpyDeviceToHost, R.s));
     HC_HIP(hipStreamSynchronize(R.s));
+    R.check_cancel();   // a kernel may have left early
     if (emit) {
         *count = (uint64_t)R.out_count;
         if (n_out) *n_out = R.out_count;

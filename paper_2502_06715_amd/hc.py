@@ -19,7 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhc.so")
 
-HC_OK, HC_ERR_INVALID, HC_ERR_OOM, HC_ERR_OVERFLOW, HC_ERR_DEVICE, HC_ERR_UNSUPPORTED = range(6)
+HC_OK, HC_ERR_INVALID, HC_ERR_OOM, HC_ERR_OVERFLOW, HC_ERR_DEVICE, HC_ERR_UNSUPPORTED, HC_ERR_CANCELLED = range(7)
 HC_I32, HC_I64 = 0, 1
 HC_BUILD_SYMMETRIC = 0x1
 HC_NO_REWRITE = 0x1
@@ -36,7 +36,8 @@ HC_SEARCH_BY_SIZE = 0x400
 SEARCH_METHODS = {"window": HC_SEARCH_WINDOW, "exponential": HC_SEARCH_EXPONENTIAL,
                   "quadratic": HC_SEARCH_QUADRATIC, "linear": HC_SEARCH_LINEAR, "by_size": HC_SEARCH_BY_SIZE}
 
-_STATUS = {1: "HC_ERR_INVALID", 2: "HC_ERR_OOM", 3: "HC_ERR_OVERFLOW", 4: "HC_ERR_DEVICE", 5: "HC_ERR_UNSUPPORTED"}
+_STATUS = {1: "HC_ERR_INVALID", 2: "HC_ERR_OOM", 3: "HC_ERR_OVERFLOW", 4: "HC_ERR_DEVICE", 5: "HC_ERR_UNSUPPORTED",
+           6: "HC_ERR_CANCELLED"}
 
 
 class HCError(RuntimeError):
@@ -89,6 +90,7 @@ SIGNATURES = {
     "hc_plan_describe": (ctypes.c_int, [P, P, U32, P, ctypes.c_size_t]),
     "hc_plan_cost_from_info": (ctypes.c_int, [P, P, P, P, U32, P, P]),
     "hc_ctx_set_profiling": (ctypes.c_int, [P, ctypes.c_int]),
+    "hc_ctx_cancel": (ctypes.c_int, [P, I32]),
     "hc_ctx_get_timing": (ctypes.c_int, [P, P]),
 }
 
@@ -139,7 +141,10 @@ def _i32(a) -> np.ndarray:
 class Context:
     """hc_ctx on a torch device and stream, allocating through torch's caching allocator."""
 
-    def __init__(self, device: int = 0, stream=None, use_torch_allocator: bool = True):
+    def __init__(self, device: int = 0, stream=None, use_torch_allocator: bool = True, max_bytes: int = 0):
+        """max_bytes > 0 caps the device memory this context's calls may hold at once
+        (through torch's allocator): a request beyond it is refused, and the call
+        fails with HC_ERR_OOM."""
         import torch
         self._torch = torch
         self.device = device
@@ -148,14 +153,22 @@ class Context:
         self.stream = stream
         sptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
         self._sptr = sptr
+        self.max_bytes = int(max_bytes)
+        self.live = {}
         if use_torch_allocator:
             def _alloc(nbytes, user):
+                if self.max_bytes and sum(self.live.values()) + int(nbytes) > self.max_bytes:
+                    return None
                 try:
-                    return torch.cuda.caching_allocator_alloc(int(nbytes), device, sptr)
+                    p = torch.cuda.caching_allocator_alloc(int(nbytes), device, sptr)
                 except Exception:
                     return None
+                if self.max_bytes:
+                    self.live[p] = int(nbytes)
+                return p
 
             def _free(ptr, user):
+                self.live.pop(ptr, None)
                 torch.cuda.caching_allocator_delete(ptr)
 
             self._cb = (_ALLOC(_alloc), _FREE(_free))
@@ -170,6 +183,12 @@ class Context:
     def check(self, st: int):
         if st != HC_OK:
             raise HCError(st, lib().hc_last_error(self.h).decode())
+
+    def cancel(self, on: bool = True):
+        """Raise (or withdraw) the context's cancel request; safe from another thread."""
+        st = lib().hc_ctx_cancel(self.h, 1 if on else 0)
+        if st != HC_OK:
+            raise HCError(st, "hc_ctx_cancel failed")
 
     def set_profiling(self, on: bool):
         lib().hc_ctx_set_profiling(self.h, 1 if on else 0)
