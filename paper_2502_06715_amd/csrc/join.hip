@@ -479,23 +479,32 @@ __device__ inline int32_t wave_search(const uint32_t* __restrict__ B, int32_t c,
 // largest key, which no searched value exceeds.
 __device__ inline void stage_window(uint32_t* rw, const uint32_t* __restrict__ B, int32_t base, int32_t sh,
                                     int32_t len_al, int32_t p2, int lane) {
-    for (int q = lane; q < (p2 >> 2); q += 64) {
-        const int32_t k0 = 4 * q;
-        uint4 val;
+    // all loads first, then the LDS stores: the loads of one lane overlap
+    constexpr int kMaxQ = 4;   // p2 <= 1024 keys = 4 x 64 lanes x 16 bytes
+    const int nq = p2 >> 2;
+    uint4 val[kMaxQ];
+#pragma unroll
+    for (int i = 0; i < kMaxQ; ++i) {
+        const int k0 = 4 * (lane + 64 * i);
+        val[i] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
         if (k0 + 4 <= len_al) {
-            val = *reinterpret_cast<const uint4*>(B + base + k0);
-        } else {
-            val.x = k0 + 0 < len_al ? B[base + k0 + 0] : 0xFFFFFFFFu;
-            val.y = k0 + 1 < len_al ? B[base + k0 + 1] : 0xFFFFFFFFu;
-            val.z = k0 + 2 < len_al ? B[base + k0 + 2] : 0xFFFFFFFFu;
-            val.w = k0 + 3 < len_al ? B[base + k0 + 3] : 0xFFFFFFFFu;
+            val[i] = *reinterpret_cast<const uint4*>(B + base + k0);
+        } else if (k0 < len_al) {
+            val[i].x = B[base + k0];
+            if (k0 + 1 < len_al) val[i].y = B[base + k0 + 1];
+            if (k0 + 2 < len_al) val[i].z = B[base + k0 + 2];
         }
-        if (k0 == 0) {
-            if (sh > 0) val.x = 0u;
-            if (sh > 1) val.y = 0u;
-            if (sh > 2) val.z = 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < kMaxQ; ++i) {
+        const int q = lane + 64 * i;
+        if (q >= nq) continue;
+        if (q == 0) {
+            if (sh > 0) val[i].x = 0u;
+            if (sh > 1) val[i].y = 0u;
+            if (sh > 2) val[i].z = 0u;
         }
-        *reinterpret_cast<uint4*>(rw + k0) = val;
+        *reinterpret_cast<uint4*>(rw + 4 * q) = val[i];
     }
 }
 
@@ -538,6 +547,27 @@ __device__ inline int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane
 __device__ inline uint64_t uni64(uint64_t v) {
     return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(v >> 32)) << 32) |
            (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)v);
+}
+
+// Branch-free lower bounds of kSub values in one sorted LDS array of p2 (a power of
+// two) keys.  Every level first issues the kSub reads, then compares, so the four
+// searches' LDS latencies overlap instead of queueing one after another.
+template <int KS>
+__device__ inline void lds_search(const uint32_t* w, int32_t p2, const uint32_t (&a)[KS], int32_t (&p)[KS]) {
+#pragma unroll
+    for (int k = 0; k < KS; ++k) p[k] = 0;
+    for (int32_t step = p2 >> 1; step > 0; step >>= 1) {
+        uint32_t x[KS];
+#pragma unroll
+        for (int k = 0; k < KS; ++k) x[k] = w[p[k] + step - 1];
+#pragma unroll
+        for (int k = 0; k < KS; ++k) p[k] += x[k] < a[k] ? step : 0;
+    }
+    uint32_t x[KS];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) x[k] = w[p[k]];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) p[k] += x[k] < a[k] ? 1 : 0;
 }
 
 __device__ inline int32_t lower_bound32(const uint32_t* __restrict__ B, int32_t l, int32_t h, uint32_t v) {
@@ -775,16 +805,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                             wc_end[o] = end[o];
                         }
                         int32_t p[kSub];
-#pragma unroll
-                        for (int k = 0; k < kSub; ++k) p[k] = 0;
-                        for (int32_t step = p2 >> 1; step > 0; step >>= 1) {
-#pragma unroll
-                            for (int k = 0; k < kSub; ++k)
-                                if (rw[p[k] + step - 1] < a[k]) p[k] += step;
-                        }
+                        lds_search<kSub>(rw, p2, a, p);
 #pragma unroll
                         for (int k = 0; k < kSub; ++k) {
-                            if (rw[p[k]] < a[k]) p[k] += 1;
                             if (p[k] < sh) p[k] = sh;
                             if (v[k]) f[k] = f[k] && p[k] < len_al && rw[p[k]] == a[k];
                             if (kMat) pos[o][k] = base + p[k];
@@ -821,17 +844,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                         stage_window(win, B, lo_al, sh, len_al, p2, lane);
                         wave_sync();
                         int32_t p[kSub];
-#pragma unroll
-                        for (int k = 0; k < kSub; ++k) p[k] = 0;
-                        // branch-free lower bound of every value (all kSub searches advance together)
-                        for (int32_t step = p2 >> 1; step > 0; step >>= 1) {
-#pragma unroll
-                            for (int k = 0; k < kSub; ++k)
-                                if (win[p[k] + step - 1] < a[k]) p[k] += step;
-                        }
+                        lds_search<kSub>(win, p2, a, p);   // all kSub searches advance together
 #pragma unroll
                         for (int k = 0; k < kSub; ++k) {
-                            if (win[p[k]] < a[k]) p[k] += 1;
                             if (p[k] < sh) p[k] = sh;
                             if (v[k]) f[k] = f[k] && p[k] < len_al && win[p[k]] == a[k];
                             if (kMat) pos[o][k] = lo_al + p[k];
@@ -841,19 +856,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                         const int32_t nf = (cover + sp - 1) / sp;
                         int32_t p2 = 4;
                         while (p2 < nf) p2 <<= 1;
-                        for (int q = lane; q < p2; q += 64) win[q] = q < nf ? B[lo + q * sp] : 0xFFFFFFFFu;
+                        {   // fence loads first, then the LDS stores (p2 <= 1024 = 16 x 64 lanes)
+                            uint32_t fv[16];
+#pragma unroll
+                            for (int i = 0; i < 16; ++i) {
+                                const int q = lane + 64 * i;
+                                fv[i] = q < nf ? B[lo + q * sp] : 0xFFFFFFFFu;
+                            }
+#pragma unroll
+                            for (int i = 0; i < 16; ++i)
+                                if (lane + 64 * i < p2) win[lane + 64 * i] = fv[i];
+                        }
                         wave_sync();
                         int32_t p[kSub];
-#pragma unroll
-                        for (int k = 0; k < kSub; ++k) p[k] = 0;
-                        for (int32_t step = p2 >> 1; step > 0; step >>= 1) {
-#pragma unroll
-                            for (int k = 0; k < kSub; ++k)
-                                if (win[p[k] + step - 1] < a[k]) p[k] += step;
-                        }
+                        lds_search<kSub>(win, p2, a, p);   // p[k]: fences below the value
 #pragma unroll
                         for (int k = 0; k < kSub; ++k) {
-                            if (win[p[k]] < a[k]) p[k] += 1;   // fences below the value
                             int32_t q = lo;
                             if (v[k] && p[k] > 0) {
                                 const int32_t l = lo + (p[k] - 1) * sp + 1;
