@@ -626,6 +626,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                                                    const uint64_t* __restrict__ wprefix, MatOut out) {
     constexpr bool kMat = mat_mode(MODE);
     __shared__ __attribute__((aligned(16))) uint32_t win_all[kWaves][kWin];
+    __shared__ uint64_t ps_all[kWaves][64];   // entry starts of a per-lane chunk
     const int lane = threadIdx.x & 63;
     uint32_t* win = win_all[threadIdx.x >> 6];
     const uint32_t* arr[NOPS];
@@ -913,14 +914,42 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                 const int nv = (int)chunk;
                 const bool valid = lane < nv;
                 const uint64_t g_last = g + chunk - 1;
-                const int64_t e_hi = (int64_t)uni64((uint64_t)advance_entry(prefix, e, e_end, g_last));
+                // The starts of entries e .. e+63, one per lane (one coalesced load), go to
+                // LDS; every lane finds its entry there.  The 64 elements span at most 64
+                // non-empty entries, but empty ones in between can push the span further:
+                // then the entries are found by searches in the prefix array.
+                uint64_t* ps = ps_all[threadIdx.x >> 6];
+                {
+                    const int64_t ej = e + lane;
+                    ps[lane] = ej <= e_end ? prefix[ej] : ~0ull;
+                }
+                wave_sync();
+                const bool in_lds = uni64(ps[63]) > g_last;
+                int64_t e_hi;
                 bool found = false;
                 uint32_t av = 0;
                 int64_t my_e = e;
                 int64_t pp[NOPS];
+                uint64_t my_start = 0;
+                if (in_lds) {
+                    const uint64_t gl = g + (lane < nv ? lane : nv - 1);
+                    int32_t pe = 0;   // ps[0] <= g <= gl
+#pragma unroll
+                    for (int32_t st = 32; st > 0; st >>= 1)
+                        if (ps[pe + st] <= gl) pe += st;
+                    my_e = e + pe;
+                    my_start = ps[pe];
+                    e_hi = (int64_t)uni64((uint64_t)__shfl((long long)my_e, nv - 1, 64));
+                } else {
+                    e_hi = (int64_t)uni64((uint64_t)advance_entry(prefix, e, e_end, g_last));
+                    if (valid) {
+                        my_e = find_entry(prefix, e, e_hi + 1, g + lane);
+                        my_start = prefix[my_e];
+                    }
+                }
+                wave_sync();
                 if (valid) {
                     const uint64_t gl = g + lane;
-                    my_e = find_entry(prefix, e, e_hi + 1, gl);
                     const int il = G.iter[my_e];
                     int32_t bl[NOPS], el[NOPS];
 #pragma unroll
@@ -928,7 +957,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                         bl[o] = G.seg[(2 * o) * stride + my_e];
                         el[o] = G.seg[(2 * o + 1) * stride + my_e];
                     }
-                    const int32_t offl = (int32_t)(gl - prefix[my_e]);
+                    const int32_t offl = (int32_t)(gl - my_start);
 #pragma unroll
                     for (int o = 0; o < NOPS; ++o)
                         if (o == il) {
