@@ -421,7 +421,7 @@ __device__ inline void write_item(int mode, const KData& D, const KStep& S, cons
 // several small entries fall back to one search per lane.
 constexpr int kWin = 1024;      // LDS window per wave (elements)
 constexpr int kSub = 4;         // 64-element chunks per cursor step
-constexpr int kTiny = 24;       // counting modes: entries shorter than this take the per-lane path
+constexpr int kTiny = 48;       // counting modes: entries shorter than this take the per-lane path
 constexpr uint64_t kChunk = 4096;       // elements per work-queue chunk (one queue atomic each)
 constexpr int kXcd = 8;                 // XCDs of an MI355X
 constexpr uint64_t kPersistBlocks = 2048;   // 8 workgroups of 4 waves per CU: 8 waves per SIMD
