@@ -120,3 +120,17 @@ def test_partition_sizes_match_oracle(ctx, shares):
     eB, eBp = ococo.partition_sizes(uniq, shares, b, seed)
     assert np.array_equal(B, eB) and np.array_equal(Bp, eBp)
     assert Bp[0] == 0 and Bp[-1] + B[-1] == uniq.shape[0]
+
+
+@pytest.mark.parametrize("b", [1, 7, 16, 20, 24])
+def test_mixer_is_a_bijection_on_the_gpu(ctx, b):
+    """The build's key mix over every id of [0, 2^b): the top level of a unary CoCo
+    holds 2^b distinct keys, i.e. every b-bit key exactly once (the mapping itself is
+    pinned to the oracle's mixer by the bit-exact CoCo tests)."""
+    import torch
+    ids = np.arange(1 << b, dtype=np.int32).reshape(-1, 1)
+    log("mixer bijection b=%d" % b)
+    c = hc.build_coco(ctx, torch.from_numpy(ids).to("cuda:0"), [0], key_bits=b, seed=0xC0FFEE)
+    v, _ = hc.coco_level(ctx, c, 0)
+    assert v.size == 1 << b and np.array_equal(v, np.arange(1 << b, dtype=np.uint32))
+    c.free()

@@ -149,7 +149,7 @@ def test_emit_is_deterministic(ctx):
     c = _coco(ctx, E, b=12, symmetric=True)
     q = hc.Query(n, atoms)
     first = None
-    for _ in range(5):
+    for _ in range(10):
         rows, _ = hc.join_emit(ctx, q, [c] * 3, [0, 1, 2], [2, 3, 1], capacity=GOLD["1"]["count"])
         r = rows.cpu().numpy()
         if first is None:
