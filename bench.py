@@ -222,7 +222,8 @@ def bench_serve(args):
         if closed:
             for r in reqs:
                 r.t_arrival = 0.0
-        srv = serve.Server(e, budget, n_slots=slots, fuse=fuse)
+        srv = serve.Server(e, budget, n_slots=slots, fuse=fuse,
+                           max_weight=(args.max_weight or None) if fuse else None)
         wall = serve.replay(srv, reqs)
         summ = serve.summarize(reqs, wall)
         summ["passes"] = srv.passes
@@ -277,6 +278,7 @@ def bench_serve(args):
                                "16 resident R-MAT graphs with 2^16..2^24 undirected edges (int32), first-variable "
                                "blocks of 1..16 ids, HBM admission budget %.0f GB" % (args.requests, args.budget_gb),
                    "slots": args.slots, "resident_index_gb": round(eng.index_bytes / 1e9, 3),
+                   "max_weight": args.max_weight,
                    "saturation_requests": n_sat},
         "saturation": {"serving_loop": sat_srv, "one_query_per_launch": sat_base,
                        "speedup": round(sat_srv["queries_per_s"] / max(qps_sat, 1e-9), 3)},
@@ -513,6 +515,8 @@ def main():
     ap.add_argument("--requests", type=int, default=20000, help="served workload: requests in the stream")
     ap.add_argument("--slots", type=int, default=4, help="served workload: concurrent passes (streams)")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="served workload: HBM admission budget")
+    ap.add_argument("--max-weight", type=float, default=2e6,
+                    help="served workload: work proxy a fused pass may carry (0: unlimited)")
     ap.add_argument("--tensor-scale", type=int, default=1,
                     help="tensor workloads: divide ST-Sparse's domain sizes by 2^s (densities kept)")
     ap.add_argument("--copy-calibration", action="store_true",

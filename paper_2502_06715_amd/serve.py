@@ -13,6 +13,9 @@ variable.  The server:
   counts them all in one hc_join_count_multi pass, one frontier entry per
   request (requests that arrived while earlier passes ran join the next pass:
   continuous batching rather than fixed batches);
+* with ``max_weight``, packs a pass only up to that much work (the engine's proxy:
+  the bindings of the first level, scaled for the deeper shapes), so that one
+  request on a hub vertex does not hold a whole pass of light ones;
 * admits a pass only while its memory estimate fits: the budget minus the
   resident indexes is the free memory, and a pass reserves
   hc_join_workspace_bound of its batch until it ends.  A batch that does not
@@ -95,6 +98,23 @@ class GpuEngine:
                     del t
         self.index_bytes = sum(int(c.info.bytes) for c in self.cocos)
         self._q = {name: hc.Query(*inputs.QUERIES[name]) for name in inputs.QUERIES}
+        # host-side work proxies: degree prefix sums per graph, and the degree-biased
+        # mean degree of a neighbour (sum deg^2 / sum deg) for the deeper levels
+        self.deg_prefix = []
+        self.kappa = []
+        for g in graphs:
+            deg = np.bincount(g[:, 0], minlength=int(g.max()) + 1 if g.shape[0] else 1).astype(np.float64)
+            self.deg_prefix.append(np.concatenate([[0.0], np.cumsum(deg)]))
+            self.kappa.append(float((deg * deg).sum() / max(deg.sum(), 1.0)))
+
+    def weight(self, r: "Request") -> float:
+        """Work proxy of a request: the bindings of its first level (sum of the degrees
+        of its id block), times the mean degree of a neighbour for the shapes with a
+        fourth variable."""
+        dp = self.deg_prefix[r.graph]
+        lo, hi = min(r.lo, dp.size - 1), min(r.hi, dp.size - 1)
+        e1 = dp[hi] - dp[lo] if hi > lo else 0.0
+        return max(1.0, e1 * (self.kappa[r.graph] if inputs.QUERIES[r.query][0] > 3 else 1.0))
 
     def group_key(self, r: "Request"):
         return r.query if self.shared else (r.graph, r.query)
@@ -135,8 +155,9 @@ class GpuEngine:
 
 class Server:
     def __init__(self, engine, budget_bytes: int, n_slots: int = 4, max_batch: int = 256, fuse: bool = True,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter, max_weight: Optional[float] = None):
         self.engine = engine
+        self.max_weight = max_weight
         self.n_slots = n_slots
         self.max_batch = max_batch if fuse else 1
         self.fuse = fuse
@@ -182,6 +203,17 @@ class Server:
             head = self.pending[0]
             key = self.engine.group_key(head)
             batch = [r for r in self.pending if self.engine.group_key(r) == key][: self.max_batch]
+            if self.max_weight is not None and len(batch) > 1:
+                # a pass carries at most max_weight of work (its first request always):
+                # a heavy request does not hold a whole pass of light ones
+                w, keep = 0.0, []
+                for r in batch:
+                    wr = self.engine.weight(r)
+                    if keep and w + wr > self.max_weight:
+                        continue
+                    keep.append(r)
+                    w += wr
+                batch = keep
             while True:
                 width = max(r.hi - r.lo for r in batch)
                 est = int(self.engine.estimate(key, len(batch), max(width, 1)))

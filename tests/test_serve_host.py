@@ -25,6 +25,9 @@ class FakeEngine:
     def group_key(self, r):
         return (r.graph, r.query)
 
+    def weight(self, r):
+        return float(r.hi - r.lo)
+
     def estimate(self, key, n, width):
         return self.per_query * n + width
 
@@ -119,3 +122,17 @@ def test_serve_stream_is_seeded_and_poisson():
     assert all(0 <= r["lo"] < r["hi"] <= gs[r["graph"]]["n"] for r in a)
     ms = [s["m"] for s in gs]
     assert ms[0] == 1 << 16 and ms[-1] == 1 << 24 and len(gs) == 16
+
+
+def test_weight_budget_keeps_heavy_requests_apart():
+    """With max_weight, a pass carries at most that much work (its first request
+    always): a heavy request runs without the light ones queued behind it."""
+    eng = FakeEngine(delay=0.01)
+    reqs = [serve.Request(id=i, graph=0, query="triangle", lo=0, hi=(100 if i == 3 else 2)) for i in range(12)]
+    srv = serve.Server(eng, budget_bytes=10 ** 9, n_slots=1, max_batch=64, max_weight=10.0)
+    serve.replay(srv, reqs)
+    for slot, key, ranges, fused in eng.passes:
+        w = sum(hi - lo for lo, hi in ranges)
+        assert w <= 10.0 or len(ranges) == 1
+    assert any(ranges == [(0, 100)] for _, _, ranges, _ in eng.passes)
+    assert all(r.count == r.lo * 7 + r.hi for r in reqs)
