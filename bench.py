@@ -533,8 +533,9 @@ def main():
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs the join on a single device "
+              "(cells would be sharded across GPUs by contiguous cell-id ranges); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.config == 4:
