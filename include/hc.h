@@ -24,7 +24,8 @@
  *    any deterministic map partitions the output correctly).  All CoCos used
  *    by one join must share b and the mixer seed.
  *  - Scratch device memory comes from the allocator given to hc_ctx_create.
- *  - A context is not thread-safe; use one context per host thread.
+ *  - A context is not thread-safe (hc_ctx_cancel excepted); use one context
+ *    per host thread.
  */
 #ifndef HC_H
 #define HC_H
@@ -121,7 +122,7 @@ const char* hc_last_error(const hc_ctx* ctx);
  * each entry's children in level r+1; l_r + 1 entries).
  *   tuples     device, row-major [n][arity] of dtype; borrowed for the call
  *   n          rows, 0 <= n < 2^31
- *   arity      1..4 (the join engine currently accepts arity <= 2)
+ *   arity      1..4
  *   col_order  host, permutation of 0..arity-1
  *   key_bits   b in 1..32, or 0 = smallest b covering the largest id;
  *              arity * b <= 64 is required
@@ -252,8 +253,10 @@ hc_status hc_plan_cost_from_info(const hc_query* q, const hc_coco_info* infos, c
  *                (sum and xor over the rows t, in head order with raw ids, of
  *                h(t) = F(...F(F(c ^ (t_0 + G)) ^ (t_1 + 2G))...), F the
  *                SplitMix64 finaliser, c = 0x6A09E667F3BCC909, G = 0x9E3779B97F4A7C15)
+ * flags: HC_NO_REWRITE, HC_SEARCH_*.
  * Errors: HC_ERR_INVALID (bad query, order, shares, or CoCos that do not
- * match), HC_ERR_UNSUPPORTED (atom arity > 2), HC_ERR_OOM, HC_ERR_DEVICE.
+ * match), HC_ERR_UNSUPPORTED (a frontier entry wider than the engine's limit),
+ * HC_ERR_OOM, HC_ERR_CANCELLED (hc_ctx_cancel), HC_ERR_DEVICE.
  */
 hc_status hc_join_count(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
                         const int32_t* var_order, const int32_t* log2_shares, uint32_t flags,
