@@ -432,18 +432,6 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// First p in [c, end) with B[p] >= v; exponential search from c (wave-uniform arguments).
-__device__ inline int64_t gallop_lb(const uint32_t* __restrict__ B, int64_t c, int64_t end, uint32_t v) {
-    if (c >= end || B[c] >= v) return c;
-    int64_t lo = c, step = 1;   // B[lo] < v
-    while (lo + step < end && B[lo + step] < v) {
-        lo += step;
-        step <<= 1;
-    }
-    const int64_t hi = lo + step < end ? lo + step : end;
-    return lower_bound_u32(B, lo + 1, hi, v);
-}
-
 // First p in [c, end) with B[p] >= v (end if none), all 64 lanes cooperating: one
 // probe of the 64 elements at the cursor, then 64-ary narrowing, so a long jump
 // costs about log64 of its length in dependent loads (wave-uniform result).
@@ -518,15 +506,6 @@ __device__ inline int64_t advance_entry(const uint64_t* __restrict__ prefix, int
     }
     const int64_t hi = lo + step < e_end ? lo + step : e_end;
     return find_entry(prefix, lo, hi, g);
-}
-
-__device__ inline int lds_lower_bound(const uint32_t* w, int len, uint32_t a) {
-    int l = 0, h = len;
-    while (l < h) {
-        const int mid = (l + h) >> 1;
-        if (w[mid] < a) l = mid + 1; else h = mid;
-    }
-    return l;
 }
 
 template <int MODE>
