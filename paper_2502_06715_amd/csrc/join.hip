@@ -608,9 +608,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
     __shared__ uint64_t ps_all[kWaves][64];   // entry starts of a per-lane chunk
     const int lane = threadIdx.x & 63;
     uint32_t* win = win_all[threadIdx.x >> 6];
+    // Counting with two operands: every entry is rearranged so that operand 0 is the
+    // one it iterates (arrays, ranges and cursors swapped), which makes the roles
+    // static in the step.  arr0 keeps the operands in plan order.
+    constexpr bool kCanon = NOPS == 2 && (MODE == M_COUNT || MODE == M_DIGEST || MODE == M_CELLS);
+    const uint32_t* arr0[NOPS];
     const uint32_t* arr[NOPS];
 #pragma unroll
-    for (int o = 0; o < NOPS; ++o) arr[o] = op_array(D, S.ops[o]);
+    for (int o = 0; o < NOPS; ++o) arr[o] = arr0[o] = op_array(D, S.ops[o]);
     const int64_t stride = G.stride;
     uint64_t cnt = 0, dsum = 0, dxor = 0;
     CellAcc ca;
@@ -648,6 +653,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         uint64_t pe0, pe1;
         int it;
         int32_t beg[NOPS], end[NOPS], cur[NOPS];
+        auto canon = [&]() {
+            if constexpr (kCanon) {
+                const bool sw = it == 1;
+                arr[0] = sw ? arr0[1] : arr0[0];
+                arr[1] = sw ? arr0[0] : arr0[1];
+                if (sw) {
+                    const int32_t tb = beg[0], te = end[0];
+                    beg[0] = beg[NOPS - 1];
+                    end[0] = end[NOPS - 1];
+                    beg[NOPS - 1] = tb;
+                    end[NOPS - 1] = te;
+                    cur[0] = beg[0];
+                    cur[NOPS - 1] = beg[NOPS - 1];
+                }
+                it = 0;
+            }
+        };
         auto load_entry = [&](int64_t ee) {
             pe0 = uni64(prefix[ee]);
             pe1 = uni64(prefix[ee + 1]);
@@ -658,6 +680,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                 end[o] = uni(G.seg[(2 * o + 1) * stride + ee]);
                 cur[o] = beg[o];
             }
+            canon();
         };
         // the descriptor of the entry after e, loaded one step ahead so that its
         // latency hides behind the current step
@@ -693,6 +716,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                         end[o] = uni(nx_end[o]);
                         cur[o] = beg[o];
                     }
+                    canon();
                 } else {
                     e = (int64_t)uni64((uint64_t)advance_entry(prefix, e + 1, e_end, g));
                     load_entry(e);
@@ -719,6 +743,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                 // ---- uniform step: up to kSub*64 elements of entry e
                 if (n_sc > 64ull * kSub) n_sc = 64ull * kSub;
                 const int nsc = (int)n_sc;
+                const int itc = kCanon ? 0 : it;   // the iterated operand
                 const int32_t off0 = (int32_t)(g - pe0);
                 uint32_t a[kSub];
                 bool v[kSub], f[kSub];
@@ -732,14 +757,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
 #pragma unroll
                     for (int o = 0; o < NOPS; ++o) {
                         pos[o][k] = beg[o] + off0 + j;
-                        if (o == it && v[k]) a[k] = arr[o][beg[o] + off0 + j];
+                        if (o == itc && v[k]) a[k] = arr[o][beg[o] + off0 + j];
                     }
                 }
                 const uint32_t a_first = __shfl(a[0], 0, 64);
                 const int last = nsc - 1;
 #pragma unroll
                 for (int o = 0; o < NOPS; ++o) {
-                    if (o == it) continue;
+                    if (o == itc) continue;
                     const uint32_t* B = arr[o];
                     const int32_t full = end[o] - beg[o];
                     // ---- short operand: its whole list sits in this operand's LDS region,
@@ -941,15 +966,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                     for (int o = 0; o < NOPS; ++o)
                         if (o == il) {
                             pp[o] = bl[o] + offl;
-                            av = arr[o][bl[o] + offl];
+                            av = arr0[o][bl[o] + offl];
                         }
                     found = true;
 #pragma unroll
                     for (int o = 0; o < NOPS; ++o) {
                         if (o == il || !found) continue;
-                        const int32_t q = lane_search(S.search, arr[o], bl[o], el[o], av);
+                        const int32_t q = lane_search(S.search, arr0[o], bl[o], el[o], av);
                         pp[o] = q;
-                        found = q < el[o] && arr[o][q] == av;
+                        found = q < el[o] && arr0[o][q] == av;
                     }
                     if (found && S.has_pred) found = pred_ok(S, F + my_e * S.W_in, av, D.mix);
                 }
