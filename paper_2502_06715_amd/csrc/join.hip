@@ -104,7 +104,7 @@ constexpr bool mat_mode(int m) { return m == M_EXPAND || m == M_TMPW || m == M_E
 
 struct Seg {
     int32_t* seg;      // [2*n_ops][stride]: begin, end per operand
-    uint8_t* iter;     // operand iterated
+    int32_t* iter;     // operand iterated
     uint32_t* m;       // its length (0 if any operand is empty)
     int64_t stride;
 };
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(KData D, KStep S, const int32_t
                 best = o;
             }
         }
-        G.iter[e] = (uint8_t)best;
+        G.iter[e] = best;
         G.m[e] = empty ? 0u : best_len;
     }
 }
@@ -432,23 +432,36 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Load through the constant address space: a wave-uniform address then becomes a
+// scalar load into SGPRs (no vector load, no readfirstlane).  Only for data that no
+// kernel running concurrently writes (the step's prepared arrays).
+template <class T>
+__device__ inline T sload(const T* p) {
+    return *(const __attribute__((address_space(4))) T*)p;
+}
+
 // First p in [c, end) with B[p] >= v (end if none), all 64 lanes cooperating: one
 // probe of the 64 elements at the cursor, then 64-ary narrowing, so a long jump
-// costs about log64 of its length in dependent loads (wave-uniform result).
+// costs about log64 of its length in dependent loads (wave-uniform result).  Lanes
+// past the end reload the last element instead of branching around their load.
+__device__ inline bool probe_lt(const uint32_t* __restrict__ Bc, int32_t n, uint32_t v, uint32_t lane4) {
+    const uint32_t n4 = (uint32_t)(n - 1) * 4u;   // n >= 1
+    const uint32_t x = *(const uint32_t*)((const char*)Bc + (lane4 < n4 ? lane4 : n4));
+    return lane4 <= n4 && x < v;
+}
 __device__ inline int32_t wave_search(const uint32_t* __restrict__ B, int32_t c, int32_t end, uint32_t v,
                                       int lane) {
     if (c >= end) return c;
+    const uint32_t lane4 = (uint32_t)lane * 4u;
     {
-        const int32_t p = c + lane;
-        const bool lt = p < end && B[p] < v;
-        const int k = __popcll(__ballot(lt));
+        const int k = __popcll(__ballot(probe_lt(B + c, end - c, v, lane4)));
         if (k < 64) return c + k;
     }
     int32_t lo = c + 64, hi = end;   // the answer lies in [lo, hi]
     while (hi - lo > 64) {
         const int32_t step = (hi - lo + 63) >> 6;
         const int32_t p = lo + lane * step;
-        const bool lt = p < hi && B[p] < v;
+        const bool lt = p < hi && B[p < hi ? p : hi - 1] < v;
         const int k = __popcll(__ballot(lt));
         if (k == 0) return lo;
         const int32_t nlo = lo + (k - 1) * step + 1;
@@ -456,9 +469,8 @@ __device__ inline int32_t wave_search(const uint32_t* __restrict__ B, int32_t c,
         lo = nlo;
         hi = nhi;
     }
-    const int32_t p = lo + lane;
-    const bool lt = p < hi && B[p] < v;
-    return lo + __popcll(__ballot(lt));
+    if (lo >= hi) return lo;
+    return lo + __popcll(__ballot(probe_lt(B + lo, hi - lo, v, lane4)));
 }
 
 // Stage B[base, base + len_al) in an LDS region with 16-byte loads (base is a
@@ -529,24 +541,44 @@ __device__ inline uint64_t uni64(uint64_t v) {
 }
 
 // Branch-free lower bounds of kSub values in one sorted LDS array of p2 (a power of
-// two) keys.  Every level first issues the kSub reads, then compares, so the four
-// searches' LDS latencies overlap instead of queueing one after another.
-template <int KS>
-__device__ inline void lds_search(const uint32_t* w, int32_t p2, const uint32_t (&a)[KS], int32_t (&p)[KS]) {
-#pragma unroll
-    for (int k = 0; k < KS; ++k) p[k] = 0;
-    for (int32_t step = p2 >> 1; step > 0; step >>= 1) {
-        uint32_t x[KS];
-#pragma unroll
-        for (int k = 0; k < KS; ++k) x[k] = w[p[k] + step - 1];
-#pragma unroll
-        for (int k = 0; k < KS; ++k) p[k] += x[k] < a[k] ? step : 0;
-    }
+// two, at most 1024) keys.  Every level first issues the kSub reads, then compares,
+// so the four searches' LDS latencies overlap instead of queueing one after another.
+// The cursors are LDS pointers and the levels are unrolled, so each read takes its
+// level's distance as the instruction's constant offset: a level costs a compare, a
+// select and an add per value, with no address arithmetic.
+typedef const __attribute__((address_space(3))) uint32_t* lds_cptr;   // 32-bit LDS address
+
+template <int KS, int S>
+__device__ inline void lds_level(int32_t p2, const uint32_t (&a)[KS], lds_cptr (&q)[KS]) {
+    if (p2 < 2 * S) return;   // wave-uniform
     uint32_t x[KS];
 #pragma unroll
-    for (int k = 0; k < KS; ++k) x[k] = w[p[k]];
+    for (int k = 0; k < KS; ++k) x[k] = q[k][S - 1];
 #pragma unroll
-    for (int k = 0; k < KS; ++k) p[k] += x[k] < a[k] ? 1 : 0;
+    for (int k = 0; k < KS; ++k) q[k] += x[k] < a[k] ? S : 0;
+}
+
+template <int KS>
+__device__ inline void lds_search(const uint32_t* w, int32_t p2, const uint32_t (&a)[KS], int32_t (&p)[KS]) {
+    const lds_cptr w3 = (lds_cptr)w;
+    lds_cptr q[KS];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) q[k] = w3;
+    lds_level<KS, 512>(p2, a, q);
+    lds_level<KS, 256>(p2, a, q);
+    lds_level<KS, 128>(p2, a, q);
+    lds_level<KS, 64>(p2, a, q);
+    lds_level<KS, 32>(p2, a, q);
+    lds_level<KS, 16>(p2, a, q);
+    lds_level<KS, 8>(p2, a, q);
+    lds_level<KS, 4>(p2, a, q);
+    lds_level<KS, 2>(p2, a, q);
+    lds_level<KS, 1>(p2, a, q);
+    uint32_t x[KS];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) x[k] = q[k][0];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) p[k] = (int32_t)(q[k] - w3) + (x[k] < a[k] ? 1 : 0);
 }
 
 __device__ inline int32_t lower_bound32(const uint32_t* __restrict__ B, int32_t l, int32_t h, uint32_t v) {
@@ -595,7 +627,9 @@ __device__ inline int32_t lane_search(int method, const uint32_t* __restrict__ B
     return lower_bound32(B, l, h, v);
 }
 
-template <int MODE, int NOPS>
+// SM = 0: the window method only (the default; the per-element methods are compiled
+// out, which keeps their registers out of the hot loop); SM = 1: the method S.search.
+template <int MODE, int NOPS, int SM>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_probe2(KData D, KStep S, const int32_t* __restrict__ F, Seg G,
                                                    const uint64_t* __restrict__ prefix, int64_t e_begin,
                                                    int64_t e_end, uint64_t item_begin, uint64_t n_items,
@@ -604,9 +638,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                                                    uint64_t* __restrict__ words, unsigned long long* acc,
                                                    const uint64_t* __restrict__ wprefix, MatOut out) {
     constexpr bool kMat = mat_mode(MODE);
+    const int search = SM ? S.search : (int)SEARCH_WINDOW;
     __shared__ __attribute__((aligned(16))) uint32_t win_all[kWaves][kWin];
     __shared__ uint64_t ps_all[kWaves][64];   // entry starts of a per-lane chunk
     const int lane = threadIdx.x & 63;
+    const uint32_t lane4 = (uint32_t)lane * 4u;
     uint32_t* win = win_all[threadIdx.x >> 6];
     // Counting with two operands: every entry is rearranged so that operand 0 is the
     // one it iterates (arrays, ranges and cursors swapped), which makes the roles
@@ -647,10 +683,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         const uint64_t c = c_lo + uni64(t);
         if (c >= c_hi) break;
         const uint64_t r_begin = c * kChunk;
-        const uint64_t r_end = r_begin + kChunk < n_items ? r_begin + kChunk : n_items;
+        // Positions inside the chunk are 32-bit offsets from its first item (uniform
+        // 64-bit compares would cost vector instructions); so are the bounds of the
+        // current entry, [lo_rel, hi_rel), the upper one clamped far beyond the chunk.
+        const uint64_t base = item_begin + r_begin;
+        const uint32_t n_c = (uint32_t)(r_begin + kChunk < n_items ? kChunk : n_items - r_begin);
         // current entry and its wave-uniform description
         int64_t e = (int64_t)uni64((uint64_t)chunk_entry[c]);
-        uint64_t pe0, pe1;
+        int32_t lo_rel;
+        uint32_t hi_rel;
         int it;
         int32_t beg[NOPS], end[NOPS], cur[NOPS];
         auto canon = [&]() {
@@ -671,97 +712,73 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
             }
         };
         auto load_entry = [&](int64_t ee) {
-            pe0 = uni64(prefix[ee]);
-            pe1 = uni64(prefix[ee + 1]);
-            it = uni(G.iter[ee]);
+            lo_rel = (int32_t)(int64_t)(sload(prefix + ee) - base);   // > -2^31: one entry's length
+            const uint64_t d1 = sload(prefix + ee + 1) - base;
+            const uint32_t big = (uint32_t)(d1 >> 32) != 0u ? 0xFFFFFFFFu : 0u;   // 32-bit ops only
+            hi_rel = min((uint32_t)d1 | big, 0x7FFFFFFFu);
+            it = sload(G.iter + ee);
 #pragma unroll
             for (int o = 0; o < NOPS; ++o) {
-                beg[o] = uni(G.seg[(2 * o) * stride + ee]);
-                end[o] = uni(G.seg[(2 * o + 1) * stride + ee]);
+                beg[o] = sload(G.seg + (2 * o) * stride + ee);
+                end[o] = sload(G.seg + (2 * o + 1) * stride + ee);
                 cur[o] = beg[o];
             }
             canon();
         };
-        // the descriptor of the entry after e, loaded one step ahead so that its
-        // latency hides behind the current step
-        uint64_t nx_pe1 = 0;
-        int32_t nx_it = 0, nx_beg[NOPS], nx_end[NOPS];
-        auto prefetch_next = [&](int64_t ee) {
-            nx_pe1 = 0;
-            if (ee + 1 < e_end) {
-                nx_pe1 = prefix[ee + 2];
-                nx_it = G.iter[ee + 1];
-#pragma unroll
-                for (int o = 0; o < NOPS; ++o) {
-                    nx_beg[o] = G.seg[(2 * o) * stride + ee + 1];
-                    nx_end[o] = G.seg[(2 * o + 1) * stride + ee + 1];
-                }
-            }
-        };
         load_entry(e);
-        prefetch_next(e);
-        uint64_t rc = r_begin;
-        while (rc < r_end) {
-            const uint64_t g = item_begin + rc;
-            if (pe1 <= g) {   // move to the entry holding g
-                const uint64_t np1 = uni64(nx_pe1);
-                if (np1 > g) {   // the next entry holds g (the usual case): use the prefetch
-                    ++e;
-                    pe0 = pe1;
-                    pe1 = np1;
-                    it = uni(nx_it);
-#pragma unroll
-                    for (int o = 0; o < NOPS; ++o) {
-                        beg[o] = uni(nx_beg[o]);
-                        end[o] = uni(nx_end[o]);
-                        cur[o] = beg[o];
-                    }
-                    canon();
-                } else {
-                    e = (int64_t)uni64((uint64_t)advance_entry(prefix, e + 1, e_end, g));
-                    load_entry(e);
-                }
-                prefetch_next(e);
+        uint32_t rc = 0;
+        while (rc < n_c) {
+            const uint64_t g = base + rc;
+            if (hi_rel <= rc) {   // move to the entry holding g: usually the next one
+                int64_t ne = e + 1;   // ne < e_end, since g < prefix[e_end]
+                if (sload(prefix + ne + 1) <= g) ne = (int64_t)advance_entry(prefix, ne + 1, e_end, g);
+                e = ne;
+                load_entry(e);
             }
-            const uint64_t left_wave = r_end - rc;
-            const uint64_t left_entry = pe1 - g;
-            const uint64_t chunk = left_wave < 64 ? left_wave : 64;
+            const uint32_t left_wave = n_c - rc;
+            const uint32_t left_entry = hi_rel - rc;
+            const uint32_t chunk = left_wave < 64 ? left_wave : 64;
             // Modes that write match words keep every step on 64-element boundaries;
             // counting modes let a step end where its entry ends, so only runs of tiny
             // entries take the per-lane path.
             constexpr bool kAligned = !(MODE == M_COUNT || MODE == M_DIGEST || MODE == M_CELLS);
             bool uniform_step;
-            uint64_t n_sc;
+            uint32_t n_sc;
             if (kAligned) {
                 uniform_step = left_entry >= chunk;
-                n_sc = left_entry >= left_wave ? left_wave : (left_entry & ~63ull);
+                n_sc = left_entry >= left_wave ? left_wave : (left_entry & ~63u);
             } else {
-                uniform_step = left_entry >= (uint64_t)kTiny || left_entry >= left_wave;
+                uniform_step = left_entry >= (uint32_t)kTiny || left_entry >= left_wave;
                 n_sc = left_entry < left_wave ? left_entry : left_wave;
             }
             if (uniform_step) {
                 // ---- uniform step: up to kSub*64 elements of entry e
-                if (n_sc > 64ull * kSub) n_sc = 64ull * kSub;
+                if (n_sc > 64u * kSub) n_sc = 64u * kSub;
                 const int nsc = (int)n_sc;
                 const int itc = kCanon ? 0 : it;   // the iterated operand
-                const int32_t off0 = (int32_t)(g - pe0);
+                const int32_t off0 = (int32_t)rc - lo_rel;
+                // the step's elements: one uniform base and lane offsets, clamped to the
+                // step's last element (lanes past it reload that one: no branches)
+                const uint32_t* ab = arr[itc] + (beg[itc] + off0);
+                const int last = nsc - 1;
+                const uint32_t last4 = (uint32_t)last * 4u;
                 uint32_t a[kSub];
-                bool v[kSub], f[kSub];
+                bool v[kSub];
+                // match masks, one bit per lane and block: each test below ANDs in the
+                // ballot of one compare (a ballot of a plain compare costs nothing more)
+                uint64_t fm[kSub];
                 int32_t pos[NOPS][kSub];   // absolute positions (materialising modes)
 #pragma unroll
                 for (int k = 0; k < kSub; ++k) {
                     const int j = k * 64 + lane;
                     v[k] = j < nsc;
-                    f[k] = v[k];
-                    a[k] = 0;
+                    const int rem = nsc - 64 * k;
+                    fm[k] = rem >= 64 ? ~0ull : (rem > 0 ? (1ull << rem) - 1 : 0ull);
+                    const uint32_t o4 = lane4 + 256u * k;
+                    a[k] = *(const uint32_t*)((const char*)ab + (o4 < last4 ? o4 : last4));
 #pragma unroll
-                    for (int o = 0; o < NOPS; ++o) {
-                        pos[o][k] = beg[o] + off0 + j;
-                        if (o == itc && v[k]) a[k] = arr[o][beg[o] + off0 + j];
-                    }
+                    for (int o = 0; o < NOPS; ++o) pos[o][k] = beg[o] + off0 + j;
                 }
-                const uint32_t a_first = __shfl(a[0], 0, 64);
-                const int last = nsc - 1;
 #pragma unroll
                 for (int o = 0; o < NOPS; ++o) {
                     if (o == itc) continue;
@@ -773,13 +790,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                     // shallower level repeats over long runs of entries)
                     constexpr int kReg = NOPS <= 2 ? kWin : kWin / 4;
                     uint32_t* rw = win + (NOPS <= 2 ? 0 : o * kReg);
-                    if (S.search != SEARCH_WINDOW) {
+                    if (search != SEARCH_WINDOW) {
                         // ---- one search per element (Section 5's methods) from the cursor
                         int32_t q[kSub];
 #pragma unroll
                         for (int k = 0; k < kSub; ++k) {
-                            q[k] = v[k] ? lane_search(S.search, B, cur[o], end[o], a[k]) : cur[o];
-                            if (v[k]) f[k] = f[k] && q[k] < end[o] && B[q[k]] == a[k];
+                            q[k] = v[k] ? lane_search(search, B, cur[o], end[o], a[k]) : cur[o];
+                            const int32_t qc = q[k] < end[o] ? q[k] : end[o] - 1;   // end > cur here
+                            fm[k] &= __ballot(q[k] < end[o]) & __ballot(B[qc] == a[k]);
                             if (kMat) pos[o][k] = q[k];
                         }
                         int32_t ql = cur[o];
@@ -813,9 +831,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                         lds_search<kSub>(rw, p2, a, p);
 #pragma unroll
                         for (int k = 0; k < kSub; ++k) {
-                            if (p[k] < sh) p[k] = sh;
-                            if (v[k]) f[k] = f[k] && p[k] < len_al && rw[p[k]] == a[k];
-                            if (kMat) pos[o][k] = base + p[k];
+                            // slots below sh hold zeros: a lower bound there moves up to sh
+                            const int32_t pc = min(max(p[k], sh), p2 - 1);
+                            fm[k] &= __ballot(pc < len_al) & __ballot(rw[pc] == a[k]);
+                            if (kMat) pos[o][k] = base + pc;
                         }
                         continue;
                     }
@@ -826,13 +845,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                     // bucket in place.
 #pragma unroll
                     for (int u = 0; u < NOPS; ++u) wc_ptr[u] = nullptr;   // the window overwrites every region
-                    uint32_t a_last = 0;
-#pragma unroll
-                    for (int k = 0; k < kSub; ++k) {
-                        const uint32_t t = __shfl(a[k], last & 63, 64);
-                        if (k == (last >> 6)) a_last = t;
-                    }
-                    a_last = (uint32_t)uni((int32_t)a_last);
+                    const uint32_t a_first = sload(ab), a_last = sload(ab + last);
                     const int32_t lo = uni(wave_search(B, cur[o], end[o], a_first, lane));
                     const int32_t hi = uni(wave_search(B, lo, end[o], a_last, lane));
                     const int32_t cover = (hi < end[o] ? hi + 1 : end[o]) - lo;
@@ -852,9 +865,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                         lds_search<kSub>(win, p2, a, p);   // all kSub searches advance together
 #pragma unroll
                         for (int k = 0; k < kSub; ++k) {
-                            if (p[k] < sh) p[k] = sh;
-                            if (v[k]) f[k] = f[k] && p[k] < len_al && win[p[k]] == a[k];
-                            if (kMat) pos[o][k] = lo_al + p[k];
+                            const int32_t pc = min(max(p[k], sh), p2 - 1);
+                            fm[k] &= __ballot(pc < len_al) & __ballot(win[pc] == a[k]);
+                            if (kMat) pos[o][k] = lo_al + pc;
                         }
                     } else {
                         const int32_t sp = (cover + (kWin - 4) - 1) / (kWin - 4);   // fence spacing
@@ -883,7 +896,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                                 const int32_t r = lo + p[k] * sp < end[o] ? lo + p[k] * sp : end[o];
                                 q = lower_bound32(B, l, r, a[k]);
                             }
-                            if (v[k]) f[k] = f[k] && q < end[o] && B[q] == a[k];
+                            const int32_t qc = q < end[o] ? q : end[o] - 1;
+                            fm[k] &= __ballot(q < end[o]) & __ballot(B[qc] == a[k]);
                             if (kMat) pos[o][k] = q;
                         }
                     }
@@ -892,22 +906,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                 }
 #pragma unroll
                 for (int k = 0; k < kSub; ++k) {
-                    if (f[k] && S.has_pred) f[k] = pred_ok(S, F + e * S.W_in, a[k], D.mix);
-                    const uint64_t bal = __ballot(f[k]);
+                    if (S.has_pred) fm[k] &= __ballot(pred_ok(S, F + e * S.W_in, a[k], D.mix));
+                    const uint64_t bal = fm[k];
+                    const bool hit = (bal >> lane) & 1ull;
                     if (kMat) {
-                        if (f[k]) {
+                        if (hit) {
                             int64_t pp[NOPS];
 #pragma unroll
                             for (int o = 0; o < NOPS; ++o) pp[o] = pos[o][k];
                             const int64_t rank =
-                                (int64_t)(wprefix[(rc >> 6) + k] + (uint64_t)__popcll(bal & lanemask_lt()));
+                                (int64_t)(wprefix[((r_begin + rc) >> 6) + k] + (uint64_t)__popcll(bal & lanemask_lt()));
                             write_item(MODE, D, S, F + e * S.W_in, a[k], pp, rank, out);
                         }
                     } else if (MODE == M_BITMAP) {
-                        if (lane == 0 && k * 64 < nsc) words[(rc >> 6) + k] = bal;
+                        if (lane == 0 && k * 64 < nsc) words[((r_begin + rc) >> 6) + k] = bal;
                     } else {
                         cnt += (uint64_t)__popcll(bal);
-                        if (MODE == M_DIGEST && f[k]) digest_add<MODE>(D, S, F + e * S.W_in, a[k], dsum, dxor);
+                        if (MODE == M_DIGEST && hit) digest_add<MODE>(D, S, F + e * S.W_in, a[k], dsum, dxor);
                         if (MODE == M_CELLS)
                             cell_add(out.cells, ca, (uint32_t)uni(F[e * S.W_in]), (uint64_t)__popcll(bal), lane);
                     }
@@ -972,7 +987,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
 #pragma unroll
                     for (int o = 0; o < NOPS; ++o) {
                         if (o == il || !found) continue;
-                        const int32_t q = lane_search(S.search, arr0[o], bl[o], el[o], av);
+                        const int32_t q = lane_search(search, arr0[o], bl[o], el[o], av);
                         pp[o] = q;
                         found = q < el[o] && arr0[o][q] == av;
                     }
@@ -981,11 +996,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                 const uint64_t bal = __ballot(found);
                 if (kMat) {
                     if (found) {
-                        const int64_t rank = (int64_t)(wprefix[rc >> 6] + (uint64_t)__popcll(bal & lanemask_lt()));
+                        const int64_t rank = (int64_t)(wprefix[(r_begin + rc) >> 6] + (uint64_t)__popcll(bal & lanemask_lt()));
                         write_item(MODE, D, S, F + my_e * S.W_in, av, pp, rank, out);
                     }
                 } else if (MODE == M_BITMAP) {
-                    if (lane == 0) words[rc >> 6] = bal;
+                    if (lane == 0) words[(r_begin + rc) >> 6] = bal;
                 } else {
                     cnt += (uint64_t)__popcll(bal);
                     if (MODE == M_DIGEST && found) digest_add<MODE>(D, S, F + my_e * S.W_in, av, dsum, dxor);
@@ -995,7 +1010,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                 // continue inside the last entry touched (its cursors restart)
                 e = e_hi;
                 load_entry(e);
-                prefetch_next(e);
                 rc += chunk;
             }
         }
@@ -1095,8 +1109,14 @@ static void launch_probe(const Alloc& A, const KData& D, const KStep& S, const i
     if (blocks > kPersistBlocks) blocks = kPersistBlocks;
     blocks = ((blocks + kXcd - 1) / kXcd) * kXcd;
 #define HC_PROBE2(N)                                                                                          \
-    k_probe2<MODE, N><<<(unsigned)blocks, kBlock, 0, s>>>(D, S, F, G, prefix, e_begin, e_end, item_begin,     \
-                                                          n_items, ce.p, q.p, n_chunks, words, acc, wprefix, out)
+    if (S.search == SEARCH_WINDOW)                                                                            \
+        k_probe2<MODE, N, 0><<<(unsigned)blocks, kBlock, 0, s>>>(D, S, F, G, prefix, e_begin, e_end,         \
+                                                                 item_begin, n_items, ce.p, q.p, n_chunks,    \
+                                                                 words, acc, wprefix, out);                   \
+    else                                                                                                      \
+        k_probe2<MODE, N, 1><<<(unsigned)blocks, kBlock, 0, s>>>(D, S, F, G, prefix, e_begin, e_end,         \
+                                                                 item_begin, n_items, ce.p, q.p, n_chunks,    \
+                                                                 words, acc, wprefix, out)
     switch (S.n_ops) {
         case 1: HC_PROBE2(1); break;
         case 2: HC_PROBE2(2); break;
@@ -1420,7 +1440,7 @@ struct Runner {
 
     struct StepBufs {
         DevBuf<int32_t> seg;
-        DevBuf<uint8_t> iter;
+        DevBuf<int32_t> iter;
         DevBuf<uint32_t> m;
         DevBuf<uint64_t> prefix;
         Seg G;
@@ -1428,7 +1448,7 @@ struct Runner {
 
     void prep(const KStep& S, const int32_t* F, int64_t e0, int64_t n, StepBufs& B) {
         B.seg = DevBuf<int32_t>(A, (size_t)(2 * S.n_ops) * (size_t)n);
-        B.iter = DevBuf<uint8_t>(A, (size_t)n);
+        B.iter = DevBuf<int32_t>(A, (size_t)n);
         B.m = DevBuf<uint32_t>(A, (size_t)n);
         B.prefix = DevBuf<uint64_t>(A, (size_t)n + 1);
         // index arrays by absolute entry e: shift the base pointers by -e0
