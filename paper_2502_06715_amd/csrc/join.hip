@@ -508,6 +508,28 @@ __device__ inline void stage_window(uint32_t* rw, const uint32_t* __restrict__ B
     }
 }
 
+// The same when B[base, base + p2) lies inside the list: the quads that hold the
+// window are copied whole (the last one's extra elements are later elements of the
+// list, no smaller than any searched value) and the rest of the p2 slots get the
+// largest key, without the per-element tail handling.
+__device__ inline void stage_window_inlist(uint32_t* rw, const uint32_t* __restrict__ B, int32_t base, int32_t sh,
+                                           int32_t len_al, int32_t p2, int lane) {
+    const uint4* src = reinterpret_cast<const uint4*>(B + base);
+    uint4* dst = reinterpret_cast<uint4*>(rw);
+    const int nl = (len_al + 3) >> 2;   // quads holding the window
+    const int nq = p2 >> 2;
+    uint4 val[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        val[i] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+        if (lane + 64 * i < nl) val[i] = src[lane + 64 * i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (lane + 64 * i < nq) dst[lane + 64 * i] = val[i];
+    if (lane < sh) rw[lane] = 0u;
+}
+
 // Largest e' in [e, e_end) with prefix[e'] <= g, given prefix[e] <= g: exponential
 // search forward from e (the next entries are usually close).
 __device__ inline int64_t advance_entry(const uint64_t* __restrict__ prefix, int64_t e, int64_t e_end, uint64_t g) {
@@ -859,7 +881,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                         const int32_t len_al = cover + sh;
                         int32_t p2 = 4;
                         while (p2 < len_al) p2 <<= 1;
-                        stage_window(win, B, lo_al, sh, len_al, p2, lane);
+                        if (lo_al + p2 <= end[o])
+                            stage_window_inlist(win, B, lo_al, sh, len_al, p2, lane);
+                        else
+                            stage_window(win, B, lo_al, sh, len_al, p2, lane);
                         wave_sync();
                         int32_t p[kSub];
                         lds_search<kSub>(win, p2, a, p);   // all kSub searches advance together
