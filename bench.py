@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+CLOCK_HZ = 2.4e9
 
 
 def _source_hash():
@@ -48,7 +49,8 @@ def _workload(cfg):
         return desc, spec["scale"], "triangle"
     if spec["kind"] == "er":
         desc = ("triangle query, R=S=T symmetric edge set of an Erdos-Renyi graph, 2^%d vertices, 2^%d "
-                "undirected edges, count" % (spec["n"].bit_length() - 1, spec["m"].bit_length() - 1))
+                "undirected edges, plain Generic Join (1 share per variable), full output + count"
+                % (spec["n"].bit_length() - 1, spec["m"].bit_length() - 1))
         return desc, spec["n"].bit_length() - 1, "triangle"
     desc = ("4-clique query over 6 atoms on one Chung-Lu graph (beta 2.1), 2^%d vertices, 2^%d undirected "
             "edges, count" % (spec["n"].bit_length() - 1, spec["m"].bit_length() - 1))
@@ -565,15 +567,25 @@ def main():
     ctx.set_profiling(True)
     q = hc.Query(n_vars, atoms)
     stream = torch.cuda.current_stream()
+    # the small Erdos-Renyi workload is plain Generic Join (one share per variable)
+    # with the full output materialised besides the count
+    emit = inputs.CONFIGS[args.config].get("kind") == "er"
+    log2_cells = 0 if emit else args.log2_cells
+    expect_rows = int(gold[str(args.config)]["count"])
+    rows_buf = torch.empty((max(expect_rows, 1), n_vars), dtype=torch.int32, device=dev) if emit else None
 
     def step():
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ev[0].record(stream)
         coco = hc.build_coco(ctx, E_dev, [0, 1], key_bits=b)
         ev[1].record(stream)
-        order, shares = hc.compute_shares(ctx, q, [coco] * len(atoms), args.log2_cells)
+        order, shares = hc.compute_shares(ctx, q, [coco] * len(atoms), log2_cells)
         ev[2].record(stream)
         cnt = hc.join_count(ctx, q, [coco] * len(atoms), order, shares)
+        if emit:
+            _, n_out = hc.join_emit(ctx, q, [coco] * len(atoms), order, shares, out=rows_buf)
+            if n_out != cnt:
+                raise RuntimeError("emitted %d rows for a count of %d" % (n_out, cnt))
         ev[3].record(stream)
         ev[3].synchronize()
         t = ctx.timing()
@@ -612,16 +624,26 @@ def main():
         avg_ms = leaf_ms / launches
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
         traffic = None
+        issue = None
         tf = os.path.join(ROOT, "profiles", "leaf_traffic_config%d.json" % args.config)
         if os.path.exists(tf):
             t = json.load(open(tf))
             if t.get("source_hash") == _source_hash():
                 traffic = t.get("bytes_per_launch")
+                # the kernel is bound by instruction issue rather than HBM: wave64 vector
+                # instructions take one of a CU's 4 SIMDs for 4 cycles, scalar ones the
+                # CU's scalar unit for 1 (256 CUs at 2.4 GHz); counts from the profile,
+                # time from this run
+                if t.get("valu_insts_per_launch"):
+                    sec = avg_ms * 1e-3
+                    issue = {"valu_frac": round(t["valu_insts_per_launch"] * 4 / (1024 * CLOCK_HZ * sec), 3),
+                             "salu_frac": round(t["salu_insts_per_launch"] / (256 * CLOCK_HZ * sec), 3),
+                             "source": t.get("summary")}
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_probe2<M_COUNT, 2> (deepest level)", "avg_launch_ms": round(avg_ms, 3),
                 "launches_per_step": launches / args.steps,
-                "algorithmic_bytes_per_launch": per_launch}
+                "algorithmic_bytes_per_launch": per_launch, "issue": issue}
     out = {
         "metric": "output tuples/s on triangle query" if qname == "triangle" else "output tuples/s",
         "value": count / (ms_per_step / 1000.0),
@@ -636,7 +658,7 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": desc, "tuples": int(E.shape[0]), "count": count, "order": res[-1]["order"],
-                   "log2_shares": res[-1]["shares"], "log2_cells": args.log2_cells},
+                   "log2_shares": res[-1]["shares"], "log2_cells": log2_cells, "emit": emit},
         "phases_ms": {k: round(float(np.mean([r[k] for r in res])), 3)
                       for k in ["build_ms", "shares_ms", "join_ms", "leaf_ms"]},
         "roofline": roof,
