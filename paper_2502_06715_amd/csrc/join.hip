@@ -371,6 +371,10 @@ struct MatOut {
     void* rows;            // emitted rows
     unsigned long long* cells;   // per-cell counts
     int64_t row_base, row_cap;
+    // [n_ops][n_items] positions found in the probed operands, element by element:
+    // the bitmap pass writes them, the materialising pass that follows reads them
+    // instead of searching again (null: search)
+    int32_t* pos;
 };
 
 // Write one match at its slot: a frontier entry (bound values, node indices of
@@ -660,6 +664,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                                                    uint64_t* __restrict__ words, unsigned long long* acc,
                                                    const uint64_t* __restrict__ wprefix, MatOut out) {
     constexpr bool kMat = mat_mode(MODE);
+    constexpr bool kPos = kMat || MODE == M_BITMAP;   // positions in the probed operands are needed
     const int search = SM ? S.search : (int)SEARCH_WINDOW;
     __shared__ __attribute__((aligned(16))) uint32_t win_all[kWaves][kWin];
     __shared__ uint64_t ps_all[kWaves][64];   // entry starts of a per-lane chunk
@@ -801,6 +806,27 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
 #pragma unroll
                     for (int o = 0; o < NOPS; ++o) pos[o][k] = beg[o] + off0 + j;
                 }
+                const uint64_t r0 = r_begin + rc;   // the step's first element, relative to the launch
+                if (kMat && out.pos != nullptr) {
+                    // the bitmap pass left every element's match bit and its positions in
+                    // the probed operands: write the matches without searching
+#pragma unroll
+                    for (int k = 0; k < kSub; ++k) {
+                        if (64 * k >= nsc) break;
+                        const uint64_t bal = sload(words + (r0 >> 6) + k);
+                        if ((bal >> lane) & 1ull) {
+                            int64_t pp[NOPS];
+#pragma unroll
+                            for (int o = 0; o < NOPS; ++o)
+                                pp[o] = o == itc ? pos[o][k] : out.pos[(size_t)o * n_items + r0 + 64 * k + lane];
+                            const int64_t rank =
+                                (int64_t)(wprefix[(r0 >> 6) + k] + (uint64_t)__popcll(bal & lanemask_lt()));
+                            write_item(MODE, D, S, F + e * S.W_in, a[k], pp, rank, out);
+                        }
+                    }
+                    rc += n_sc;
+                    continue;
+                }
 #pragma unroll
                 for (int o = 0; o < NOPS; ++o) {
                     if (o == itc) continue;
@@ -820,7 +846,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                             q[k] = v[k] ? lane_search(search, B, cur[o], end[o], a[k]) : cur[o];
                             const int32_t qc = q[k] < end[o] ? q[k] : end[o] - 1;   // end > cur here
                             fm[k] &= __ballot(q[k] < end[o]) & __ballot(B[qc] == a[k]);
-                            if (kMat) pos[o][k] = q[k];
+                            if (kPos) pos[o][k] = q[k];
                         }
                         int32_t ql = cur[o];
 #pragma unroll
@@ -856,7 +882,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                             // slots below sh hold zeros: a lower bound there moves up to sh
                             const int32_t pc = min(max(p[k], sh), p2 - 1);
                             fm[k] &= __ballot(pc < len_al) & __ballot(rw[pc] == a[k]);
-                            if (kMat) pos[o][k] = base + pc;
+                            if (kPos) pos[o][k] = base + pc;
                         }
                         continue;
                     }
@@ -892,7 +918,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                         for (int k = 0; k < kSub; ++k) {
                             const int32_t pc = min(max(p[k], sh), p2 - 1);
                             fm[k] &= __ballot(pc < len_al) & __ballot(win[pc] == a[k]);
-                            if (kMat) pos[o][k] = lo_al + pc;
+                            if (kPos) pos[o][k] = lo_al + pc;
                         }
                     } else {
                         const int32_t sp = (cover + (kWin - 4) - 1) / (kWin - 4);   // fence spacing
@@ -923,11 +949,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                             }
                             const int32_t qc = q < end[o] ? q : end[o] - 1;
                             fm[k] &= __ballot(q < end[o]) & __ballot(B[qc] == a[k]);
-                            if (kMat) pos[o][k] = q;
+                            if (kPos) pos[o][k] = q;
                         }
                     }
                     wave_sync();
                     cur[o] = hi;   // lower bound of the step's last value
+                }
+                if (MODE == M_BITMAP && out.pos != nullptr) {
+#pragma unroll
+                    for (int k = 0; k < kSub; ++k)
+                        if (v[k]) {
+#pragma unroll
+                            for (int o = 0; o < NOPS; ++o)
+                                if (o != itc) out.pos[(size_t)o * n_items + r0 + 64 * k + lane] = (int32_t)pos[o][k];
+                        }
                 }
 #pragma unroll
                 for (int k = 0; k < kSub; ++k) {
@@ -1009,14 +1044,28 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                             av = arr0[o][bl[o] + offl];
                         }
                     found = true;
+                    const uint64_t r0 = r_begin + rc;
+                    if (kMat && out.pos != nullptr) {
+                        // match bit and positions from the bitmap pass
 #pragma unroll
-                    for (int o = 0; o < NOPS; ++o) {
-                        if (o == il || !found) continue;
-                        const int32_t q = lane_search(search, arr0[o], bl[o], el[o], av);
-                        pp[o] = q;
-                        found = q < el[o] && arr0[o][q] == av;
+                        for (int o = 0; o < NOPS; ++o)
+                            if (o != il) pp[o] = out.pos[(size_t)o * n_items + r0 + lane];
+                        found = (sload(words + (r0 >> 6)) >> lane) & 1ull;
+                    } else {
+#pragma unroll
+                        for (int o = 0; o < NOPS; ++o) {
+                            if (o == il || !found) continue;
+                            const int32_t q = lane_search(search, arr0[o], bl[o], el[o], av);
+                            pp[o] = q;
+                            found = q < el[o] && arr0[o][q] == av;
+                        }
+                        if (found && S.has_pred) found = pred_ok(S, F + my_e * S.W_in, av, D.mix);
+                        if (MODE == M_BITMAP && out.pos != nullptr) {
+#pragma unroll
+                            for (int o = 0; o < NOPS; ++o)
+                                if (o != il) out.pos[(size_t)o * n_items + r0 + lane] = (int32_t)pp[o];
+                        }
                     }
-                    if (found && S.has_pred) found = pred_ok(S, F + my_e * S.W_in, av, D.mix);
                 }
                 const uint64_t bal = __ballot(found);
                 if (kMat) {
@@ -1487,12 +1536,21 @@ struct Runner {
     }
 
     // Items [prefix[ea], prefix[eb]) of a prepared step into match words + their scan.
+    // The bitmap pass over items [ib, ib + ni): match words, their scan (returns the
+    // matches) and, for the cursor kernel, the positions found in the probed operands,
+    // which the materialising pass then reads instead of searching again.
     uint64_t match_words(const KStep& S, const int32_t* F, StepBufs& B, const uint64_t* prefix_abs, int64_t ea,
-                         int64_t eb, uint64_t ib, uint64_t ni, DevBuf<uint64_t>& words, DevBuf<uint64_t>& wpre) {
+                         int64_t eb, uint64_t ib, uint64_t ni, DevBuf<uint64_t>& words, DevBuf<uint64_t>& wpre,
+                         DevBuf<int32_t>& posb) {
         const int64_t nw = (int64_t)((ni + 63) / 64);
         words = DevBuf<uint64_t>(A, (size_t)nw + 1);
         wpre = DevBuf<uint64_t>(A, (size_t)nw + 1);
-        if (nw > 0) launch_probe<M_BITMAP>(A, D, S, F, B.G, prefix_abs, ea, eb, ib, ni, words.p, nullptr, s);
+        MatOut mo{};
+        if (nw > 0 && S.n_ops <= 4) {
+            posb = DevBuf<int32_t>(A, (size_t)S.n_ops * (size_t)ni);
+            mo.pos = posb.p;
+        }
+        if (nw > 0) launch_probe<M_BITMAP>(A, D, S, F, B.G, prefix_abs, ea, eb, ib, ni, words.p, nullptr, s, nullptr, mo);
         scan_popc(A, words.p, wpre.p, nw, s);
         return read_u64(wpre.p + nw);
     }
@@ -1554,10 +1612,12 @@ void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
             HC_REQUIRE(ni <= (uint64_t)tmp_cap[g] || eb == ea + 1, HC_ERR_DEVICE, "tmp chunking failed");
             if (ni > (uint64_t)tmp_cap[g]) grow_tmp(g, (int64_t)ni);   // one entry larger than the pool
             DevBuf<uint64_t> words, wpre;
-            match_words(S, F, gb[t], gb[t].prefix.p, ea, eb, pr[0], ni, words, wpre);
+            DevBuf<int32_t> posb;
+            match_words(S, F, gb[t], gb[t].prefix.p, ea, eb, pr[0], ni, words, wpre, posb);
             const int64_t nw = (int64_t)((ni + 63) / 64);
             if (nw > 0) {
                 MatOut mo{};
+                mo.pos = posb.p;
                 mo.tval = tmp_val[g].p;
                 for (int u = 0; u < S.n_src; ++u) mo.tsrc[u] = tmp_src[g][u].p;
                 launch_probe<M_TMPW>(A, D, S, F, gb[t].G, gb[t].prefix.p, ea, eb, pr[0], ni, words.p, nullptr, s,
@@ -1603,9 +1663,11 @@ void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
                 while (ib < total) {
                     const uint64_t ni = std::min<uint64_t>(total - ib, (uint64_t)cap_entries);
                     DevBuf<uint64_t> words, wpre;
-                    const uint64_t got = match_words(S, F, B, prefix_abs, ea, eb, ib, ni, words, wpre);
+                    DevBuf<int32_t> posb;
+                    const uint64_t got = match_words(S, F, B, prefix_abs, ea, eb, ib, ni, words, wpre, posb);
                     if (got > 0 && out_count < out_cap) {
                         MatOut mo{};
+                        mo.pos = posb.p;
                         mo.rows = out_rows;
                         mo.row_base = out_count;
                         mo.row_cap = out_cap;
@@ -1631,15 +1693,18 @@ void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
                 HC_HIP(hipStreamSynchronize(s));
                 const uint64_t ni = pr[1] - pr[0];
                 DevBuf<uint64_t> words, wpre;
-                const uint64_t got = match_words(S, F, B, prefix_abs, ca, cb, pr[0], ni, words, wpre);
+                DevBuf<int32_t> posb;
+                const uint64_t got = match_words(S, F, B, prefix_abs, ca, cb, pr[0], ni, words, wpre, posb);
                 if (got > 0) {
                     DevBuf<int32_t> Fn(A, (size_t)got * (size_t)lay[i + 1].W);
                     MatOut mo{};
                     mo.F = Fn.p;
+                    mo.pos = posb.p;
                     launch_probe<M_EXPAND>(A, D, S, F, B.G, prefix_abs, ca, cb, pr[0], ni, words.p, nullptr, s,
                                            wpre.p, mo);
                     words.reset();
                     wpre.reset();
+                    posb.reset();
                     run_level(i + 1, Fn.p, Fn.p, (int64_t)got);
                 }
                 ca = cb;
@@ -1877,15 +1942,19 @@ uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, co
         const double n = std::min(E, kCap);
         const Layout Li = make_layout(P, i);
         bytes += n * 4.0 * (Li.W + (i == 0 && n_queries > 0 ? 2 : 0));   // F_i
-        bytes += n * (8.0 * L.n_ops + 13.0) + 8.0;             // ranges, iterated operand, length, prefix
+        bytes += n * (8.0 * L.n_ops + 16.0) + 8.0;             // ranges, iterated operand, length, prefix
         for (int g = 0; g < P.n_groups; ++g) {
             if (P.groups[g].lift != i) continue;
             const double pool = std::min(n * gmax[g], kCap);
-            bytes += n * (8.0 * P.groups[g].n_ops + 13.0) + 8.0;
+            bytes += n * (8.0 * P.groups[g].n_ops + 16.0) + 8.0;
             bytes += pool * 4.0 * (1 + P.groups[g].n_ops) + (pool / 64 + 1) * 16.0;
+            bytes += pool * 4.0 * P.groups[g].n_ops;                       // positions of the bitmap pass
         }
         const double items = std::min(n * m, 1e18);
-        if (i + 1 < P.n_vars) bytes += (std::min(items, kCap) / 64 + 1) * 16.0;   // match words of a chunk
+        if (i + 1 < P.n_vars) {
+            bytes += (std::min(items, kCap) / 64 + 1) * 16.0;   // match words of a chunk
+            bytes += std::min(items, kCap) * 4.0 * L.n_ops;     // positions of the bitmap pass
+        }
         bytes += (items / 2048 + 1) * 8.0 + 64.0;                                  // work-queue chunk table
         E = std::min(E * m, 1e18);
     }
