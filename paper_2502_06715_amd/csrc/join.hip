@@ -1581,19 +1581,23 @@ void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
     for (int g = 0; g < P.n_groups; ++g)
         if (P.groups[g].lift == i) groups.push_back(g);
     std::vector<StepBufs> gb(groups.size());
+    std::vector<uint64_t> gtot(groups.size());
+    bool one_chunk = true;   // every group's elements fit its pool: no chunking, no split round trips
     for (size_t t = 0; t < groups.size(); ++t) {
         const int g = groups[t];
         prep(group_step[g], F, 0, n, gb[t]);
         // The pool of a group lifted at this level is dead between calls of this
         // level and between its chunks, so it is sized here: all of this call's
         // elements, up to tmp_max (the chunking below splits the rest).
-        const uint64_t need = std::max<uint64_t>(1, std::min<uint64_t>(read_u64(gb[t].prefix.p + n), (uint64_t)tmp_max));
+        gtot[t] = read_u64(gb[t].prefix.p + n);
+        const uint64_t need = std::max<uint64_t>(1, std::min<uint64_t>(gtot[t], (uint64_t)tmp_max));
         if (need > (uint64_t)tmp_cap[g]) grow_tmp(g, (int64_t)need);
+        one_chunk = one_chunk && gtot[t] <= (uint64_t)tmp_cap[g];
     }
     int64_t ea = 0;
     while (ea < n) {
         int64_t eb = n;
-        for (size_t t = 0; t < groups.size(); ++t) {
+        for (size_t t = 0; t < groups.size() && !one_chunk; ++t) {
             k_split<<<1, 1, 0, s>>>(gb[t].prefix.p, ea, eb, (uint64_t)tmp_cap[groups[t]], split.p);
             HC_HIP(hipGetLastError());
             int64_t e2 = 0;
@@ -1604,10 +1608,12 @@ void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
         for (size_t t = 0; t < groups.size(); ++t) {
             const int g = groups[t];
             const KStep& S = group_step[g];
-            uint64_t pr[2];
-            HC_HIP(hipMemcpyAsync(&pr[0], gb[t].prefix.p + ea, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-            HC_HIP(hipMemcpyAsync(&pr[1], gb[t].prefix.p + eb, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-            HC_HIP(hipStreamSynchronize(s));
+            uint64_t pr[2] = {0, gtot[t]};
+            if (!one_chunk) {
+                HC_HIP(hipMemcpyAsync(&pr[0], gb[t].prefix.p + ea, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+                HC_HIP(hipMemcpyAsync(&pr[1], gb[t].prefix.p + eb, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+                HC_HIP(hipStreamSynchronize(s));
+            }
             const uint64_t ni = pr[1] - pr[0];
             HC_REQUIRE(ni <= (uint64_t)tmp_cap[g] || eb == ea + 1, HC_ERR_DEVICE, "tmp chunking failed");
             if (ni > (uint64_t)tmp_cap[g]) grow_tmp(g, (int64_t)ni);   // one entry larger than the pool
@@ -1682,15 +1688,17 @@ void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
             // expand in chunks of entries whose elements fit the next frontier
             int64_t ca = ea;
             while (ca < eb) {
-                k_split<<<1, 1, 0, s>>>(prefix_abs, ca, eb, (uint64_t)cap_entries, split.p);
-                HC_HIP(hipGetLastError());
-                int64_t cb = 0;
-                HC_HIP(hipMemcpyAsync(&cb, split.p, sizeof(cb), hipMemcpyDeviceToHost, s));
-                uint64_t pr[2];
-                HC_HIP(hipStreamSynchronize(s));
-                HC_HIP(hipMemcpyAsync(&pr[0], prefix_abs + ca, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-                HC_HIP(hipMemcpyAsync(&pr[1], prefix_abs + cb, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-                HC_HIP(hipStreamSynchronize(s));
+                int64_t cb = eb;
+                uint64_t pr[2] = {0, total};   // prefix_abs[ea] = 0, prefix_abs[eb] = total
+                if (ca != ea || total > (uint64_t)cap_entries) {
+                    k_split<<<1, 1, 0, s>>>(prefix_abs, ca, eb, (uint64_t)cap_entries, split.p);
+                    HC_HIP(hipGetLastError());
+                    HC_HIP(hipMemcpyAsync(&cb, split.p, sizeof(cb), hipMemcpyDeviceToHost, s));
+                    HC_HIP(hipStreamSynchronize(s));
+                    HC_HIP(hipMemcpyAsync(&pr[0], prefix_abs + ca, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+                    HC_HIP(hipMemcpyAsync(&pr[1], prefix_abs + cb, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+                    HC_HIP(hipStreamSynchronize(s));
+                }
                 const uint64_t ni = pr[1] - pr[0];
                 DevBuf<uint64_t> words, wpre;
                 DevBuf<int32_t> posb;
