@@ -458,9 +458,9 @@ def bench_order_sweep(args):
 
 
 def bench_share_sweep(args):
-    """Every power-of-two factorisation P_a x P_b x P_c = 2^10 of the triangle query
-    on the R-MAT scale-20 graph (order a,b,c, CoCo built once): measured join time
-    against the model, with the optimizer's picks marked."""
+    """Every power-of-two factorisation P_a x P_b x P_c = 2^K (K = --log2-cells) of the
+    triangle query on the R-MAT scale-20 graph (order a,b,c, CoCo built once):
+    measured join time against the model, with the optimizer's picks marked."""
     import torch
     from paper_2502_06715_amd import hc, inputs
 
@@ -470,7 +470,7 @@ def bench_share_sweep(args):
     ctx = hc.Context(0)
     c = hc.build_coco(ctx, torch.from_numpy(E).to("cuda:0"), [0, 1], key_bits=20)
     torch.cuda.synchronize()
-    K = 10
+    K = args.log2_cells
     rows = []
     for ka in range(K + 1):
         for kb in range(K + 1 - ka):
@@ -489,16 +489,17 @@ def bench_share_sweep(args):
         sys.exit(1)
     ms = [r["join_ms"] for r in rows]
     picks = {}
-    for name, flags in [("default", 0), ("joint_search", hc.HC_JOINT_SEARCH), ("pessimistic", hc.HC_PESSIMISTIC)]:
+    for name, flags in [("default", 0), ("joint_search", hc.HC_JOINT_SEARCH), ("pessimistic", hc.HC_PESSIMISTIC),
+                        ("cache", hc.HC_CACHE_SHARES)]:
         o, sh = hc.compute_shares(ctx, q, [c] * 3, K, flags=flags | hc.HC_KEEP_ORDER, order=[0, 1, 2])
         hit = [r for r in rows if r["log2_shares"] == sh]
         picks[name] = {"log2_shares": sh, "join_ms": hit[0]["join_ms"],
                        "rank": sorted(ms).index(hit[0]["join_ms"]) + 1}
     best = min(rows, key=lambda r: r["join_ms"])
-    out = {"metric": "share sweep (all factorisations of 2^10) of the triangle query on R-MAT scale 20",
+    out = {"metric": "share sweep (all factorisations of 2^%d) of the triangle query on R-MAT scale 20" % K,
            "value": best["join_ms"], "unit": "ms (fastest share vector)", "n_gpus": 1, "higher_is_better": False,
            "data": "synthetic", "dtype": "u32", "vs_baseline": None,
-           "config": {"workload": "triangle, R-MAT scale 20, 2^24 edges, order a,b,c, P = 2^10"},
+           "config": {"workload": "triangle, R-MAT scale 20, 2^24 edges, order a,b,c, P = 2^%d" % K},
            "count": rows[0]["count"], "fastest": best, "optimizer": picks, "shares": rows,
            "spearman_model_vs_time": _spearman([r["model_cost"] for r in rows], ms), "roofline": None}
     c.free()
@@ -512,6 +513,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--log2-cells", type=int, default=12)
+    ap.add_argument("--share-rule", choices=["cache", "paper"], default="cache",
+                    help="share decision: cheapest vector whose cells fit an XCD's L2 (HC_CACHE_SHARES), "
+                         "or the paper's evenness rule")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--requests", type=int, default=20000, help="served workload: requests in the stream")
@@ -569,6 +573,7 @@ def main():
     stream = torch.cuda.current_stream()
     # the small Erdos-Renyi workload is plain Generic Join (one share per variable)
     # with the full output materialised besides the count
+    share_flags = hc.HC_CACHE_SHARES if args.share_rule == "cache" else 0
     emit = inputs.CONFIGS[args.config].get("kind") == "er"
     log2_cells = 0 if emit else args.log2_cells
     expect_rows = int(gold[str(args.config)]["count"])
@@ -579,7 +584,7 @@ def main():
         ev[0].record(stream)
         coco = hc.build_coco(ctx, E_dev, [0, 1], key_bits=b)
         ev[1].record(stream)
-        order, shares = hc.compute_shares(ctx, q, [coco] * len(atoms), log2_cells)
+        order, shares = hc.compute_shares(ctx, q, [coco] * len(atoms), log2_cells, flags=share_flags)
         ev[2].record(stream)
         cnt = hc.join_count(ctx, q, [coco] * len(atoms), order, shares)
         if emit:
@@ -658,7 +663,8 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": desc, "tuples": int(E.shape[0]), "count": count, "order": res[-1]["order"],
-                   "log2_shares": res[-1]["shares"], "log2_cells": log2_cells, "emit": emit},
+                   "log2_shares": res[-1]["shares"], "log2_cells": log2_cells, "share_rule": args.share_rule,
+                   "emit": emit},
         "phases_ms": {k: round(float(np.mean([r[k] for r in res])), 3)
                       for k in ["build_ms", "shares_ms", "join_ms", "leaf_ms"]},
         "roofline": roof,

@@ -98,6 +98,7 @@ typedef void (*hc_free_fn)(void* ptr, void* user);
 #define HC_KEEP_ORDER     0x8u    /* hc_compute_shares: use var_order_inout as given */
 #define HC_JOINT_SEARCH   0x10u   /* hc_compute_shares: search orders and shares jointly */
 #define HC_PESSIMISTIC    0x20u   /* cost model: upper-bound cardinality estimator */
+#define HC_CACHE_SHARES   0x40u   /* hc_compute_shares: cheapest vector whose cells fit an L2 */
 
 /*
  * Create a context on HIP device `device`, ordering work on `hip_stream` (a
@@ -207,6 +208,13 @@ hc_status hc_partition_sizes(hc_ctx* ctx, const hc_coco* coco, const int32_t* lo
  * twice the best unpartitioned cost over all orders.  HC_PESSIMISTIC bounds
  * the prefix bindings from above (longest lists, whole atoms inside the
  * prefix) instead of chaining average list sizes.
+ * HC_CACHE_SHARES replaces the evenness rule, which balances one cell per CPU
+ * thread, with the GPU's concern: the work queue balances the cells, and a
+ * cell's CoCo slices should fit the 4 MB L2 of the XCD that sweeps it.  Among
+ * the vectors passing the domain rule, those whose every atom slice (4 bytes
+ * per tuple divided by the shares of the atom's variables) fits 4 MB compete
+ * on Eq. (total cost) alone; if none fits, the smallest largest slice wins,
+ * then the lower cost.  Only the order given or chosen as above is searched.
  *   atom_index       host array of n_atoms CoCo handles (may repeat)
  *   var_order_inout  host [n_vars]; if HC_KEEP_ORDER is set it is the order to
  *                    use, else it receives the chosen order

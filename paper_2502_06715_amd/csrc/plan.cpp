@@ -399,6 +399,56 @@ double plan_cost(const hc_query* q, const std::vector<AtomStats>& st, const int3
     return tot;
 }
 
+// HC_CACHE_SHARES: cheapest share vector (Eq. (total cost)) among those whose every
+// atom's per-cell slice fits one XCD's L2; failing that, the smallest largest slice.
+static void cache_shares(const hc_query* q, const std::vector<AtomStats>& st, const Plan& p, const LevelCost& lc,
+                         int K, int32_t* shares_out) {
+    constexpr double kL2 = 4.0 * 1024 * 1024;   // bytes of L2 per XCD
+    const int n = q->n_vars;
+    std::vector<double> dom;
+    std::vector<int> maxbits;
+    domains(q, st, dom, maxbits);
+    std::vector<int> k(n, 0), kv(n, 0), best(n, 0);
+    bool found = false, best_fits = false;
+    double best_c = 1e308, best_slice = 1e308;
+    std::function<void(int, int)> rec = [&](int lvl, int left) {
+        if (lvl < n - 1) {
+            for (int x = 0; x <= left; ++x) {
+                k[lvl] = x;
+                rec(lvl + 1, left - x);
+            }
+            return;
+        }
+        k[lvl] = left;
+        for (int i = 0; i < n; ++i) kv[p.order[i]] = k[i];
+        if (!share_feasible(kv, dom, maxbits)) return;
+        double slice = 0;
+        int off = 0;
+        for (int j = 0; j < q->n_atoms; ++j) {
+            int bits = 0;
+            for (int c = 0; c < q->atom_arity[j]; ++c) bits += kv[q->atom_vars[off + c]];
+            off += q->atom_arity[j];
+            slice = std::max(slice, std::ldexp(4.0 * st[j].rows, -bits));
+        }
+        const double c = share_cost(p, lc, kv.data());
+        const bool fits = slice <= kL2;
+        bool better;
+        if (!found) better = true;
+        else if (fits != best_fits) better = fits;
+        else if (fits) better = c < best_c * (1 - 1e-12);
+        else better = slice < best_slice * (1 - 1e-12) || (slice <= best_slice * (1 + 1e-12) && c < best_c * (1 - 1e-12));
+        if (better) {
+            found = true;
+            best_fits = fits;
+            best_c = c;
+            best_slice = slice;
+            best = kv;
+        }
+    };
+    rec(0, K);
+    for (int v = 0; v < n; ++v) shares_out[v] = found ? best[v] : 0;
+}
+
 void choose_shares(const hc_query* q, const std::vector<AtomStats>& st, int K, uint32_t flags, int32_t* order_inout,
                    int32_t* shares_out) {
     const int n = q->n_vars;
@@ -430,6 +480,10 @@ void choose_shares(const hc_query* q, const std::vector<AtomStats>& st, int K, u
     for (int i = 0; i < n; ++i) order_inout[i] = best_order[i];
     Plan p = compile_plan(q, best_order.data(), rewrite);
     const LevelCost lc = level_costs(q, st, p, pess);
+    if (flags & HC_CACHE_SHARES) {
+        cache_shares(q, st, p, lc, K, shares_out);
+        return;
+    }
     std::vector<double> dom;
     std::vector<int> maxbits;
     domains(q, st, dom, maxbits);

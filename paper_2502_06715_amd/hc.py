@@ -28,6 +28,7 @@ HC_FORCE_GALLOP = 0x4
 HC_KEEP_ORDER = 0x8
 HC_JOINT_SEARCH = 0x10
 HC_PESSIMISTIC = 0x20
+HC_CACHE_SHARES = 0x40
 HC_SEARCH_WINDOW = 0x000
 HC_SEARCH_EXPONENTIAL = 0x100
 HC_SEARCH_QUADRATIC = 0x200

@@ -194,3 +194,43 @@ def test_joint_search_is_the_minimum_evenness_feasible_plan(name, K):
                 sh[o[i]] = comp[i]
             if feasible(o, sh):
                 assert evenness(o, sh) >= e_star - 1e-9
+
+
+@pytest.mark.parametrize("name,rows,K", [("triangle", 1 << 25, 12), ("triangle", 1 << 25, 8), ("clique4", 1 << 23, 12),
+                                         ("cycle4", 1 << 20, 6)])
+def test_cache_shares_is_the_cheapest_vector_that_fits(name, rows, K):
+    """HC_CACHE_SHARES against an independent enumeration: among the share vectors of
+    the chosen order that pass the domain rule, those whose every atom slice (4 bytes
+    per tuple over the product of the shares of its variables) fits 4 MB compete on
+    Eq. (total cost); without any, the smallest largest slice wins."""
+    n, atoms = inputs.QUERIES[name]
+    distinct = 1 << 20
+    info = _info(rows, distinct, 20)
+    info.max_children[0] = 100000
+    q = hc.Query(n, atoms)
+    infos = [info] * len(atoms)
+    order, shares = hc.compute_shares_from_info(q, infos, K, flags=hc.HC_CACHE_SHARES)
+    assert sum(shares) == K
+
+    def slice_bytes(sh):
+        return max(4.0 * rows / 2 ** sum(sh[v] for v in a) for a in atoms)
+
+    def domain_ok(sh):
+        return all(not s or distinct >= 3 * 2 ** s * math.log(2 ** s) for s in sh)
+
+    cands = []
+    for comp in itertools.product(range(K + 1), repeat=n):
+        if sum(comp) != K:
+            continue
+        sh = [0] * n
+        for i in range(n):
+            sh[order[i]] = comp[i]
+        if domain_ok(sh):
+            cands.append((sh, slice_bytes(sh), hc.plan_cost_from_info(q, infos, order, sh)[0]))
+    fits = [c for c in cands if c[1] <= 4 * 2 ** 20]
+    cost = hc.plan_cost_from_info(q, infos, order, shares)[0]
+    if fits:
+        assert slice_bytes(shares) <= 4 * 2 ** 20
+        assert cost <= min(c[2] for c in fits) * (1 + 1e-9)
+    else:
+        assert slice_bytes(shares) <= min(c[1] for c in cands) * (1 + 1e-9)
