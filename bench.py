@@ -331,7 +331,9 @@ def bench_tensor(args):
                 for key, t in uniq.items():
                     cs[key] = hc.build_coco(ctx, t, [0, 1, 2])
                 cocos = [cs[id(r)] for r in rels]
-                o2, shares = hc.compute_shares(ctx, q, cocos, args.log2_cells, flags=hc.HC_KEEP_ORDER, order=order)
+                rule = hc.HC_CACHE_SHARES if args.share_rule == "cache" else 0
+                o2, shares = hc.compute_shares(ctx, q, cocos, args.log2_cells, flags=hc.HC_KEEP_ORDER | rule,
+                                               order=order)
                 cnt = hc.join_count(ctx, q, cocos, order, shares, flags=flags)
                 for c in cs.values():
                     c.free()
