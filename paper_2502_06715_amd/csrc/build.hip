@@ -158,7 +158,10 @@ __global__ void k_max_children(const int32_t* __restrict__ O, int64_t l, unsigne
 __global__ void k_bitmap_mark(const uint32_t* __restrict__ V, int64_t l, uint32_t* bitmap) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < l; e += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t v = V[e];
-        atomicOr(&bitmap[v >> 5], 1u << (v & 31u));
+        const uint32_t bit = 1u << (v & 31u);
+        // most values repeat: test first, so that only the first few setters of a bit
+        // contend for its word (a stale read only costs one redundant atomic)
+        if (!(__atomic_load_n(&bitmap[v >> 5], __ATOMIC_RELAXED) & bit)) atomicOr(&bitmap[v >> 5], bit);
     }
 }
 
@@ -304,6 +307,12 @@ void build_coco(hc_ctx* ctx, const void* tuples, int64_t n, int arity, hc_dtype 
         }
         if (b > 30) {   // bitmap too large to be worth it: upper bound
             out->distinct[c] = out->level_len[r];
+            continue;
+        }
+        if ((flags & HC_BUILD_SYMMETRIC) && arity == 2) {
+            // a symmetric binary relation holds the same values in both columns (the
+            // symmetry itself is verified below, failing the build otherwise)
+            out->distinct[c] = out->level_len[0];
             continue;
         }
         const int64_t words = ((int64_t)1 << b) / 32 + 1;
