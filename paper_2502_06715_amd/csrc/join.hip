@@ -716,7 +716,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         const uint64_t base = item_begin + r_begin;
         const uint32_t n_c = (uint32_t)(r_begin + kChunk < n_items ? kChunk : n_items - r_begin);
         // current entry and its wave-uniform description
-        int64_t e = (int64_t)uni64((uint64_t)chunk_entry[c]);
+        int64_t e = sload(chunk_entry + c);
         int32_t lo_rel;
         uint32_t hi_rel;
         int it;
