@@ -195,6 +195,12 @@ def test_config2_triangle_count(ctx):
     log("config2 order=%s shares=%s" % (order, shares))
     assert hc.join_count(ctx, q, [c] * 3, order, shares) == GOLD["2"]["count"]
     assert hc.join_count(ctx, q, [c] * 3, [0, 1, 2], [0, 0, 0]) == GOLD["2"]["count"]
+    # the cache share rule (the bench's default): count and output digest
+    order, shares = hc.compute_shares(ctx, q, [c] * 3, 12, flags=hc.HC_CACHE_SHARES)
+    log("config2 cache rule order=%s shares=%s" % (order, shares))
+    cnt, dg = hc.join_count(ctx, q, [c] * 3, order, shares, digest=True)
+    assert cnt == GOLD["2"]["count"]
+    assert dg == (int(GOLD["2"]["digest"][0]), int(GOLD["2"]["digest"][1]))
 
 
 def _config3(ctx):
@@ -216,6 +222,9 @@ def test_config3_clique4_count_and_digest(ctx):
     assert cnt == g["count"]
     assert dg == (int(g["digest"][0]), int(g["digest"][1]))
     assert hc.join_count(ctx, q, [c] * 6, order, shares, flags=hc.HC_NO_REWRITE) == g["count"]
+    order, shares = hc.compute_shares(ctx, q, [c] * 6, 12, flags=hc.HC_CACHE_SHARES)
+    log("config3 cache rule order=%s shares=%s" % (order, shares))
+    assert hc.join_count(ctx, q, [c] * 6, order, shares) == g["count"]
 
 
 def test_config3_chunked_emit(ctx):
