@@ -449,7 +449,7 @@ __device__ inline T sload(const T* p) {
 // costs about log64 of its length in dependent loads (wave-uniform result).  Lanes
 // past the end reload the last element instead of branching around their load.
 __device__ inline bool probe_lt(const uint32_t* __restrict__ Bc, int32_t n, uint32_t v, uint32_t lane4) {
-    const uint32_t n4 = (uint32_t)(n - 1) * 4u;   // n >= 1
+    const uint32_t n4 = (uint32_t)((n < 64 ? n : 64) - 1) * 4u;   // n >= 1; only 64 lanes
     const uint32_t x = *(const uint32_t*)((const char*)Bc + (lane4 < n4 ? lane4 : n4));
     return lane4 <= n4 && x < v;
 }
