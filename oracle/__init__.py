@@ -13,5 +13,6 @@ Contents
   brute.py           brute-force enumeration of tiny instances (pins)
   coco.py            the CoCo levels and partition histograms by definition
   rewrite.py         the lifted-intersection rewriting, executed literally
-  plan.py            the cost model and share/order decision, written plainly
+  cells.py           HyperCube cells: Generic Join per cell, with the partition
+                     checks (disjoint cell outputs whose union is Q(D))
 """

@@ -37,7 +37,7 @@
 #endif
 
 #define OQ_MAX_VARS 8
-#define OQ_MAX_ATOMS 12
+#define OQ_MAX_ATOMS 16
 #define OQ_MAX_ARITY 4
 
 typedef struct {
@@ -46,6 +46,8 @@ typedef struct {
     int k;
     int var_of_col[OQ_MAX_ARITY];
     int64_t distinct0;  /* number of distinct first-column values */
+    int perm[OQ_MAX_ARITY];  /* input column of each sorted column */
+    int shared;         /* t is another atom's sorted copy (same input, same column permutation) */
 } oq_rel;
 
 typedef struct {
@@ -230,7 +232,10 @@ static void gj_level(const oq_state* s, oq_frame* f, int i) {
  * Returns the count, or -1 on an invalid query.
  */
 static void free_state(oq_state* s) {
-    for (int j = 0; j < OQ_MAX_ATOMS; ++j) { free(s->rel[j].t); s->rel[j].t = NULL; }
+    for (int j = 0; j < OQ_MAX_ATOMS; ++j) {
+        if (!s->rel[j].shared) free(s->rel[j].t);
+        s->rel[j].t = NULL;
+    }
 }
 
 /* Sort and deduplicate every atom in variable-order column order; returns 0 or -1. */
@@ -263,6 +268,24 @@ static int prepare(oq_state* s, int n_vars, int n_atoms, const int* arity, const
                 int tmp = perm[y]; perm[y] = perm[y - 1]; perm[y - 1] = tmp;
             }
         for (int c = 0; c < k; ++c) r->var_of_col[c] = av[perm[c]];
+        /* an atom over the same input array with the same column permutation as an
+           earlier atom reuses that atom's sorted, deduplicated copy */
+        int same = -1;
+        for (int j2 = 0; j2 < j && same < 0; ++j2) {
+            if (rel[j2] != rel[j] || rows[j2] != rows[j] || s->rel[j2].k != k) continue;
+            int eq = 1;
+            for (int c = 0; c < k; ++c) eq = eq && s->rel[j2].perm[c] == perm[c];
+            if (eq) same = j2;
+        }
+        for (int c = 0; c < k; ++c) r->perm[c] = perm[c];
+        if (same >= 0) {
+            r->t = s->rel[same].t;
+            r->rows = s->rel[same].rows;
+            r->distinct0 = s->rel[same].distinct0;
+            r->shared = 1;
+            av += k;
+            continue;
+        }
         r->t = (int64_t*)malloc(sizeof(int64_t) * (size_t)(rows[j] > 0 ? rows[j] : 1) * k);
         for (int64_t row = 0; row < rows[j]; ++row)
             for (int c = 0; c < k; ++c) r->t[row * k + c] = rel[j][row * k + perm[c]];

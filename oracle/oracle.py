@@ -58,6 +58,19 @@ def lib():
     return _lib
 
 
+def _as_int64(relations, atoms):
+    """int64 row-major copies of the relations; an object given for several atoms of
+    the same arity is converted once (the C side then sorts it once per column order)."""
+    seen = {}
+    out = []
+    for r, a in zip(relations, atoms):
+        key = (id(r), len(a))
+        if key not in seen:
+            seen[key] = np.ascontiguousarray(np.asarray(r, dtype=np.int64).reshape(-1, len(a)))
+        out.append(seen[key])
+    return out
+
+
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
@@ -71,20 +84,21 @@ class Result:
 
 
 def gj(n_vars: int, atoms, relations, order=None, lo=None, hi=None, emit=False,
-       digest=False, work=False, threads: int = 0) -> Result:
+       digest=False, work=False, threads: int = 0, capacity: int = None) -> Result:
     """Generic Join.
 
     atoms: list of variable tuples, one per atom (head-order variable ids).
     relations: list of int arrays [rows, arity], one per atom (may repeat objects).
     order: variable order (default 0..n-1).  lo/hi: optional per-variable range
-    predicate lo[v] <= x_v < hi[v] on raw ids.
+    predicate lo[v] <= x_v < hi[v] on raw ids.  capacity: with emit, the expected
+    number of rows if known (one pass instead of a counting pass first; a larger
+    result falls back to the two passes).
     """
     L = lib()
     order = list(range(n_vars)) if order is None else list(order)
     arity = np.array([len(a) for a in atoms], dtype=np.int32)
     avars = np.array([v for a in atoms for v in a], dtype=np.int32)
-    rels = [np.ascontiguousarray(np.asarray(r, dtype=np.int64).reshape(-1, len(a)))
-            for r, a in zip(relations, atoms)]
+    rels = _as_int64(relations, atoms)
     rows = np.array([r.shape[0] for r in rels], dtype=np.int64)
     ptrs = (ctypes.c_void_p * len(rels))(*[r.ctypes.data for r in rels])
     ordr = np.array(order, dtype=np.int32)
@@ -94,7 +108,10 @@ def gj(n_vars: int, atoms, relations, order=None, lo=None, hi=None, emit=False,
         hi_a = np.array(hi, dtype=np.int64)
     out = None
     cap = 0
-    if emit:
+    if emit and capacity is not None:
+        cap = max(int(capacity), 1)
+        out = np.zeros((cap, n_vars), dtype=np.int64)
+    elif emit:
         # first pass: count, to size the buffer exactly
         c0 = L.oracle_gj(n_vars, len(atoms), _ptr(arity), _ptr(avars), ptrs, _ptr(rows), _ptr(ordr),
                          _ptr(lo_a) if lo_a is not None else None,
@@ -114,6 +131,8 @@ def gj(n_vars: int, atoms, relations, order=None, lo=None, hi=None, emit=False,
                     _ptr(wk) if wk is not None else None, threads)
     if c < 0:
         raise ValueError("invalid query")
+    if emit and c > cap:
+        return gj(n_vars, atoms, relations, order, lo, hi, emit, digest, work, threads)
     res_rows = None
     if emit:
         res_rows = out[:c]
@@ -132,8 +151,7 @@ def gj_sample(n_vars: int, atoms, relations, ranges, budget_s: float, order=None
     order = list(range(n_vars)) if order is None else list(order)
     arity = np.array([len(a) for a in atoms], dtype=np.int32)
     avars = np.array([v for a in atoms for v in a], dtype=np.int32)
-    rels = [np.ascontiguousarray(np.asarray(r, dtype=np.int64).reshape(-1, len(a)))
-            for r, a in zip(relations, atoms)]
+    rels = _as_int64(relations, atoms)
     rows = np.array([r.shape[0] for r in rels], dtype=np.int64)
     ptrs = (ctypes.c_void_p * len(rels))(*[r.ctypes.data for r in rels])
     ordr = np.array(order, dtype=np.int32)

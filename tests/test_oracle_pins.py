@@ -16,7 +16,7 @@ import pytest
 import scipy.sparse as sp
 
 from paper_2502_06715_amd import inputs
-from oracle import brute, coco, oracle, rewrite
+from oracle import brute, cells, coco, oracle, rewrite
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 Q = inputs.QUERIES
@@ -331,3 +331,50 @@ def test_ternary_closed_forms():
     n, atoms = Q["ct"]
     gu = g[g[:, 0] < U]
     assert oracle.gj(n, atoms, [gu] * 3).count == U * N ** 3
+
+
+@pytest.mark.parametrize("name,shares", [("triangle", [1, 2, 1]), ("cycle4", [1, 0, 1, 1]),
+                                         ("clique4", [1, 1, 1, 0]), ("lw", [1, 1, 0, 1])])
+def test_cells_mode_equals_brute_force_partition(name, shares):
+    """Cells mode against the definition of Section 5: every brute-force result tuple
+    t belongs to the one cell (h(t_1), .., h(t_n)); the per-cell counts must be the
+    histogram of those cells, in the library's cell packing, for every order."""
+    n, atoms = Q[name]
+    b, seed = 4, 0x51
+    ternary = any(len(a) > 2 for a in atoms)
+    rels = [inputs.random_relation(40 if ternary else 30, 4 if ternary else 10, 900 + j, arity=len(a))
+            for j, a in enumerate(atoms)]
+    exp = np.asarray(brute.brute(n, atoms, rels), dtype=np.int64).reshape(-1, n)
+    assert exp.shape[0] > 0
+    for order in itertools.islice(itertools.permutations(range(n)), 0, None, 7):
+        got, rows = cells.cells(n, atoms, rels, shares, b, seed, order=order)
+        want = np.zeros(got.size, dtype=np.uint64)
+        for t in exp:
+            c = [int(coco.mix_scalar(int(t[v]), b, seed)) >> (b - shares[v]) for v in range(n)]
+            cid, shift = 0, 0   # the library's packing: first variable of the order lowest
+            for v in order:
+                cid |= c[v] << shift
+                shift += shares[v]
+            want[cid] += 1
+        assert np.array_equal(got, want)
+        assert int(got.sum()) == exp.shape[0]
+
+
+def test_gj_sample_blocks_sum_to_the_count():
+    """The CPU-baseline sampler: the counts of first-variable id blocks that cover the
+    domain add up to the Generic Join count, and each block's count equals Generic
+    Join under the same range predicate."""
+    n, atoms = Q["triangle"]
+    E = inputs.rmat(10, 6000, 44)
+    full = oracle.gj(n, atoms, [E] * 3).count
+    nid = int(E.max()) + 1
+    w = 37
+    ranges = [(a, a + w) for a in range(0, nid, w)]
+    perm = np.random.default_rng(1).permutation(len(ranges))
+    ranges = [ranges[i] for i in perm]
+    _, done = oracle.gj_sample(n, atoms, [E] * 3, ranges, budget_s=1e9, threads=2)
+    assert len(done) == len(ranges)
+    assert sum(d[2] for d in done) == full
+    for lo, hi, cnt, _ in done[:12]:
+        big = 1 << 40
+        assert cnt == oracle.gj(n, atoms, [E] * 3, lo=[lo, 0, 0], hi=[hi, big, big]).count
