@@ -238,12 +238,19 @@ def bench_serve(args):
         run(eng, args.slots, True, probe[:500], True)
         run(base_eng, 1, False, probe[:200], True)
     sat_base, c_base = run(base_eng, 1, False, probe, True)
-    sat_srv, c_srv = run(eng, args.slots, True, probe, True)
     print("# saturation, one query per launch: %s" % json.dumps(sat_base), file=sys.stderr, flush=True)
+    sat_srv, c_srv = run(eng, args.slots, True, probe, True)
     print("# saturation, serving loop: %s" % json.dumps(sat_srv), file=sys.stderr, flush=True)
     if c_base != c_srv or any(c is None for c in c_srv):
-        print("served counts differ from one-query-per-launch counts", file=sys.stderr)
+        bad = [i for i, (a, b) in enumerate(zip(c_base, c_srv)) if a != b]
+        print("served counts differ from one-query-per-launch counts at %d requests (first %s); errors: %s"
+              % (len(bad), bad[:8], json.dumps(sat_srv["errors"])), file=sys.stderr)
         sys.exit(1)
+    if args.saturation_only:
+        print(json.dumps({"saturation": {"serving_loop": sat_srv, "one_query_per_launch": sat_base}}), flush=True)
+        eng.close()
+        base_eng.close()
+        return
     qps_sat = sat_base["queries_per_s"]
     open_runs = {}
     for frac in (0.8, 0.5):
@@ -525,6 +532,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=200.0, help="served workload: HBM admission budget")
     ap.add_argument("--max-weight", type=float, default=2e6,
                     help="served workload: work proxy a fused pass may carry (0: unlimited)")
+    ap.add_argument("--saturation-only", action="store_true",
+                    help="served workload: only the closed-loop saturation runs")
     ap.add_argument("--tensor-scale", type=int, default=1,
                     help="tensor workloads: divide ST-Sparse's domain sizes by 2^s (densities kept)")
     ap.add_argument("--copy-calibration", action="store_true",

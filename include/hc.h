@@ -77,10 +77,22 @@ typedef void (*hc_free_fn)(void* ptr, void* user);
 #define HC_BUILD_SYMMETRIC 0x1u   /* binary relation claimed symmetric: verified on the
                                      device; the CoCo then serves both column orders */
 
-/* Flags of hc_compute_shares / hc_join_count / hc_join_emit */
+/* Flags of hc_compute_shares / hc_join_count / hc_join_emit.  Every call rejects
+ * (HC_ERR_INVALID) a bit it does not take: the joins take HC_NO_REWRITE,
+ * HC_FORCE_MERGE, HC_FORCE_GALLOP, an HC_SEARCH_* method and (hc_join_emit only)
+ * HC_EMIT_SORTED; hc_compute_shares takes HC_NO_REWRITE, HC_KEEP_ORDER,
+ * HC_JOINT_SEARCH, HC_PESSIMISTIC and HC_CACHE_SHARES. */
 #define HC_NO_REWRITE     0x1u    /* disable the Section 6.1 lift */
-#define HC_FORCE_MERGE    0x2u    /* reserved */
-#define HC_FORCE_GALLOP   0x4u    /* reserved */
+/* The two forced intersection methods of Section 5: every operand a level does
+ * not iterate is searched from its cursor by a linear scan (the multiway merge,
+ * HC_FORCE_MERGE, the same as HC_SEARCH_LINEAR) or by galloping (exponential
+ * search, HC_FORCE_GALLOP, the same as HC_SEARCH_EXPONENTIAL).  Setting both,
+ * or one with an HC_SEARCH_* method other than its own, is HC_ERR_INVALID. */
+#define HC_FORCE_MERGE    0x2u
+#define HC_FORCE_GALLOP   0x4u
+/* hc_join_emit: the rows come out in lexicographic order of the head-order tuple
+ * (raw ids compared as unsigned integers), sorted on the device. */
+#define HC_EMIT_SORTED    0x80u
 /* hc_join_*: how the operands a level does not iterate are searched (Section 5).
  * HC_SEARCH_WINDOW (0, default): wave-cooperative -- the step's candidate range
  * is staged in LDS and searched there.  The others are the paper's per-element
@@ -327,7 +339,8 @@ hc_status hc_join_workspace_bound(hc_ctx* ctx, const hc_query* q, const hc_coco*
  * raw ids, same dtype as the CoCos' input.  n_out (host) always receives the
  * exact number of result rows; if it exceeds capacity the call returns
  * HC_ERR_OVERFLOW and the contents of out are unspecified.  Row order is
- * deterministic for given inputs, order and shares, but otherwise unspecified.
+ * deterministic for given inputs, order and shares, but otherwise unspecified,
+ * unless flags has HC_EMIT_SORTED: then the rows are in lexicographic order.
  * Other arguments and errors as hc_join_count.
  */
 hc_status hc_join_emit(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,

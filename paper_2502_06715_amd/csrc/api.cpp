@@ -1,4 +1,6 @@
 // C-ABI entry points: argument validation, error capture, allocation.
+#include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <exception>
 #include <new>
@@ -56,6 +58,19 @@ hc_status guarded(hc_ctx* ctx, F&& f) {
         if (ctx) ctx->err = "unknown error";
         return HC_ERR_DEVICE;
     }
+}
+
+// Flags each entry point takes; any other bit is rejected.
+constexpr uint32_t kJoinFlags = HC_NO_REWRITE | HC_FORCE_MERGE | HC_FORCE_GALLOP | HC_SEARCH_MASK;
+constexpr uint32_t kShareFlags = HC_NO_REWRITE | HC_KEEP_ORDER | HC_JOINT_SEARCH | HC_PESSIMISTIC | HC_CACHE_SHARES;
+
+void check_flags(uint32_t flags, uint32_t allowed, const char* call) {
+    HC_REQUIRE((flags & ~allowed) == 0, HC_ERR_INVALID,
+               std::string(call) + ": unknown flag bits 0x" + [&] {
+                   char b[16];
+                   std::snprintf(b, sizeof(b), "%x", flags & ~allowed);
+                   return std::string(b);
+               }());
 }
 
 void check_query_ptrs(const hc_query* q) {
@@ -269,6 +284,7 @@ hc_status hc_compute_shares(hc_ctx* ctx, const hc_query* q, const hc_coco* const
         check_query_ptrs(q);
         HC_REQUIRE(atom_index && var_order_inout && log2_shares_out, HC_ERR_INVALID, "NULL argument");
         HC_REQUIRE(log2_total_P >= 0 && log2_total_P <= 24, HC_ERR_INVALID, "log2_total_P must be 0..24");
+        check_flags(flags, kShareFlags, "hc_compute_shares");
         hc::validate_query(q, 4);
         auto st = stats_of(q, atom_index);
         hc::choose_shares(q, st, log2_total_P, flags, var_order_inout, log2_shares_out);
@@ -281,6 +297,7 @@ hc_status hc_compute_shares_from_info(const hc_query* q, const hc_coco_info* inf
         check_query_ptrs(q);
         HC_REQUIRE(infos && var_order_inout && log2_shares_out, HC_ERR_INVALID, "NULL argument");
         HC_REQUIRE(log2_total_P >= 0 && log2_total_P <= 24, HC_ERR_INVALID, "log2_total_P must be 0..24");
+        check_flags(flags, kShareFlags, "hc_compute_shares_from_info");
         hc::validate_query(q, 4);
         hc::choose_shares(q, stats_of_info(q, infos), log2_total_P, flags, var_order_inout, log2_shares_out);
         return HC_OK;
@@ -297,6 +314,7 @@ hc_status hc_plan_cost_from_info(const hc_query* q, const hc_coco_info* infos, c
     try {
         check_query_ptrs(q);
         HC_REQUIRE(infos && var_order && total_out, HC_ERR_INVALID, "NULL argument");
+        check_flags(flags, HC_NO_REWRITE | HC_PESSIMISTIC, "hc_plan_cost_from_info");
         *total_out = hc::plan_cost(q, stats_of_info(q, infos), var_order, log2_shares, flags, per_level_out);
         return HC_OK;
     } catch (const hc::Error& e) {
@@ -313,6 +331,28 @@ hc_status hc_join_count(hc_ctx* ctx, const hc_query* q, const hc_coco* const* at
     return guarded(ctx, [&] {
         check_query_ptrs(q);
         HC_REQUIRE(atom_index && var_order && count_out, HC_ERR_INVALID, "NULL argument");
+        check_flags(flags, kJoinFlags, "hc_join_count");
+        // A count without shares whose first variable is restricted to a narrow id
+        // range is a batch of one request: its first level then searches the
+        // range's mixed ids instead of walking the whole top level.
+        if (!digest_out && q->var_lo && q->n_vars > 1 && atom_index[0]) {
+            bool no_shares = true;
+            for (int v = 0; v < q->n_vars && log2_shares; ++v) no_shares = no_shares && log2_shares[v] == 0;
+            const int v0 = var_order[0];
+            const hc_coco* c0 = atom_index[0];
+            const bool v0_ok = v0 >= 0 && v0 < q->n_vars;
+            const int64_t lo = v0_ok ? std::max<int64_t>(q->var_lo[v0], 0) : 0, hi = v0_ok ? q->var_hi[v0] : 0;
+            const bool one_segment = c0->key_bits == c0->mix_bits || hi <= lo ||
+                                     (lo >> c0->mix_bits) == ((hi - 1) >> c0->mix_bits);
+            if (no_shares && v0_ok && hi - lo <= ((int64_t)1 << 16) && one_segment) {
+                const int64_t rng[2] = {lo, hi};
+                uint64_t per = 0, total = 0;
+                hc::join_run(ctx, q, atom_index, var_order, nullptr, flags, false, &total, nullptr, nullptr, 0,
+                             nullptr, &per, 1, rng);
+                *count_out = per;
+                return;
+            }
+        }
         hc::join_run(ctx, q, atom_index, var_order, log2_shares, flags, false, count_out, digest_out, nullptr, 0,
                      nullptr);
     });
@@ -325,6 +365,7 @@ hc_status hc_join_count_cells(hc_ctx* ctx, const hc_query* q, const hc_coco* con
     return guarded(ctx, [&] {
         check_query_ptrs(q);
         HC_REQUIRE(atom_index && var_order && cell_counts && count_out, HC_ERR_INVALID, "NULL argument");
+        check_flags(flags, kJoinFlags, "hc_join_count_cells");
         hc::join_run(ctx, q, atom_index, var_order, log2_shares, flags, false, count_out, nullptr, nullptr, 0,
                      nullptr, cell_counts);
     });
@@ -338,6 +379,7 @@ hc_status hc_join_workspace_bound(hc_ctx* ctx, const hc_query* q, const hc_coco*
         check_query_ptrs(q);
         HC_REQUIRE(atom_index && var_order && bytes_out, HC_ERR_INVALID, "NULL argument");
         HC_REQUIRE(n_queries >= 0 && first_width >= 0, HC_ERR_INVALID, "negative n_queries or first_width");
+        check_flags(flags, kJoinFlags, "hc_join_workspace_bound");
         for (int j = 0; j < q->n_atoms; ++j) HC_REQUIRE(atom_index[j] != nullptr, HC_ERR_INVALID, "atom CoCo handle is NULL");
         *bytes_out = hc::join_workspace_bound(q, atom_index, var_order, log2_shares, flags, n_queries, first_width);
     });
@@ -351,6 +393,7 @@ hc_status hc_join_count_multi(hc_ctx* ctx, const hc_query* q, const hc_coco* con
         check_query_ptrs(q);
         HC_REQUIRE(atom_index && var_order && first_var_ranges && counts_out, HC_ERR_INVALID, "NULL argument");
         HC_REQUIRE(n_queries >= 0, HC_ERR_INVALID, "negative n_queries");
+        check_flags(flags, kJoinFlags, "hc_join_count_multi");
         if (n_queries == 0) return;
         uint64_t total = 0;
         hc::join_run(ctx, q, atom_index, var_order, nullptr, flags, false, &total, nullptr, nullptr, 0, nullptr,
@@ -367,13 +410,21 @@ hc_status hc_join_emit(hc_ctx* ctx, const hc_query* q, const hc_coco* const* ato
         HC_REQUIRE(atom_index && var_order && n_out, HC_ERR_INVALID, "NULL argument");
         HC_REQUIRE(capacity >= 0, HC_ERR_INVALID, "capacity must be >= 0");
         HC_REQUIRE(capacity == 0 || out != nullptr, HC_ERR_INVALID, "out is NULL");
+        check_flags(flags, kJoinFlags | HC_EMIT_SORTED, "hc_join_emit");
         uint64_t count = 0;
-        hc::join_run(ctx, q, atom_index, var_order, log2_shares, flags, true, &count, nullptr, out, capacity,
-                     n_out);
+        hc::join_run(ctx, q, atom_index, var_order, log2_shares, flags & ~HC_EMIT_SORTED, true, &count, nullptr,
+                     out, capacity, n_out);
         *n_out = (int64_t)count;
         if ((int64_t)count > capacity)
             hc::fail(HC_ERR_OVERFLOW, "hc_join_emit: " + std::to_string(count) + " rows exceed capacity " +
                                           std::to_string(capacity));
+        if ((flags & HC_EMIT_SORTED) && count > 1) {
+            // rows of raw ids below 2^key_bits (the build rejects larger ids)
+            const hc_coco* c0 = atom_index[0];
+            hc::sort_rows(ctx->alloc, out, (int64_t)count, q->n_vars, c0->key_bits, c0->dtype == HC_I64,
+                          ctx->stream);
+            HC_HIP(hipStreamSynchronize(ctx->stream));
+        }
     });
 }
 
@@ -381,6 +432,7 @@ hc_status hc_plan_describe(const hc_query* q, const int32_t* var_order, uint32_t
     try {
         check_query_ptrs(q);
         HC_REQUIRE(var_order && buf, HC_ERR_INVALID, "NULL argument");
+        check_flags(flags, HC_NO_REWRITE, "hc_plan_describe");
         hc::Plan p = hc::compile_plan(q, var_order, !(flags & HC_NO_REWRITE));
         std::string s = hc::describe_plan(p);
         if (s.size() + 1 > cap) return HC_ERR_OVERFLOW;

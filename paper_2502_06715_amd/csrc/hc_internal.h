@@ -150,6 +150,10 @@ void scan_popc(const Alloc& a, const uint64_t* words, uint64_t* out, int64_t n, 
 void radix_sort_u64(const Alloc& a, DevBuf<uint64_t>& keys, DevBuf<uint64_t>& tmp, int64_t n, int bits,
                     hipStream_t s);
 
+// Sort n emitted head-order rows (nv columns of raw ids below 2^b, int32 or int64)
+// lexicographically, in place (rows.hip).
+void sort_rows(const Alloc& a, void* rows, int64_t n, int nv, int b, bool i64, hipStream_t s);
+
 // ---------------------------------------------------------------- build (build.hip)
 void build_coco(hc_ctx* ctx, const void* tuples, int64_t n, int arity, hc_dtype dtype,
                 const int32_t* col_order, int key_bits, int mix_bits, uint64_t seed, uint32_t flags,
@@ -223,11 +227,18 @@ double plan_cost(const hc_query* q, const std::vector<AtomStats>& st, const int3
                  uint32_t flags, double* per_level);
 
 // ---------------------------------------------------------------- join (join.hip)
+// Chunking cap: frontier entries, lifted-pool elements and elements per expand /
+// emit chunk below F_0 (a single entry larger than the cap still goes whole).
+constexpr int64_t kDefaultCap = (int64_t)1 << 27;
+// alloc: where the call's device buffers come from (null: the context's allocator);
+// cap_entries: the chunking cap (0: kDefaultCap).
 void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
               const int32_t* shares, uint32_t flags, bool emit, uint64_t* count, uint64_t* digest,
               void* out, int64_t capacity, int64_t* n_out, uint64_t* cell_counts = nullptr,
-              int64_t n_multi = 0, const int64_t* multi_ranges = nullptr);
+              int64_t n_multi = 0, const int64_t* multi_ranges = nullptr, const Alloc* alloc = nullptr,
+              int64_t cap_entries = 0);
 uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
-                              const int32_t* shares, uint32_t flags, int64_t n_queries, int64_t first_width);
+                              const int32_t* shares, uint32_t flags, int64_t n_queries, int64_t first_width,
+                              int64_t cap_entries = kDefaultCap);
 
 }  // namespace hc

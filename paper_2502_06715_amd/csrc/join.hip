@@ -190,6 +190,21 @@ __global__ void k_child_ranges(const int32_t* __restrict__ O0, const uint32_t* _
     }
 }
 
+// Range of a top-level operand for one entry: the whole level, or the key range of
+// the coordinate (of a share, or of the segment) that the cell or an entry word names.
+__device__ inline void v0_bounds(const KData& D, const KOp& op, const int32_t* ent, uint32_t cell, int64_t& beg,
+                                 int64_t& end) {
+    if (op.v0_range) {
+        const uint32_t src = op.rng_word >= 0 ? (uint32_t)ent[op.rng_word] : cell;
+        const int2 r = op.v0_range[(src >> op.rng_shift) & ((1u << op.rng_k) - 1u)];
+        beg = r.x;
+        end = r.y;
+    } else {
+        beg = 0;
+        end = D.atoms[op.atom].len[0];
+    }
+}
+
 // Resolve every operand of every entry to a [begin, end) range, restricted to the cell.
 __global__ __launch_bounds__(kBlock) void k_prep(KData D, KStep S, const int32_t* __restrict__ F, int64_t e0,
                                                  int64_t n, Seg G) {
@@ -208,15 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(KData D, KStep S, const int32_t
             const KOp& op = S.ops[o];
             int64_t beg, end;
             if (op.kind == OP_V0) {
-                if (op.v0_range) {
-                    const uint32_t src = op.rng_word >= 0 ? (uint32_t)ent[op.rng_word] : cell;
-                    const int2 r = op.v0_range[(src >> op.rng_shift) & ((1u << op.rng_k) - 1u)];
-                    beg = r.x;
-                    end = r.y;
-                } else {
-                    beg = 0;
-                    end = D.atoms[op.atom].len[0];
-                }
+                v0_bounds(D, op, ent, cell, beg, end);
             } else if (op.kind == OP_CHILD) {
                 const int32_t node = ent[op.word];
                 const int32_t* O = D.atoms[op.atom].O[op.lvl - 1];
@@ -1131,6 +1138,48 @@ __global__ __launch_bounds__(kBlock) void k_materialize(KData D, KStep S, const 
     }
 }
 
+// Request batches (F_0 = one entry per request, each with its first-variable id
+// range lo..hi, inclusive, in words pred_word and pred_word + 1).  The mixer is a
+// bijection, so the keys a request can bind at the first level are the mixed ids of
+// its block: slot g of request t (slot_prefix[t] <= g < slot_prefix[t+1]) mixes id
+// lo + (g - slot_prefix[t]) and binary-searches it in every top-level operand.  A
+// block of w ids then costs w searches instead of a pass over the top level.
+__global__ void k_first_ids(KData D, KStep S, const int32_t* __restrict__ F, const uint64_t* __restrict__ slot_prefix,
+                            int64_t n_req, uint64_t n_slots, uint32_t* __restrict__ found, uint32_t* __restrict__ keys,
+                            int32_t* __restrict__ pos) {
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_slots;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const int64_t t = find_entry(slot_prefix, 0, n_req, g);
+        const int32_t* ent = F + t * S.W_in;
+        const uint32_t raw = (uint32_t)ent[S.pred_word] + (uint32_t)(g - slot_prefix[t]);
+        const uint32_t key = mix_key(raw, D.mix);
+        bool ok = pred_ok(S, ent, key, D.mix);
+        for (int o = 0; o < S.n_ops; ++o) {
+            int64_t beg, end;
+            v0_bounds(D, S.ops[o], ent, (uint32_t)ent[0], beg, end);
+            const uint32_t* arr = D.atoms[S.ops[o].atom].V[0];
+            const int64_t p = lower_bound_u32(arr, beg, end, key);
+            ok = ok && p < end && arr[p] == key;
+            pos[(uint64_t)o * n_slots + g] = (int32_t)p;
+        }
+        found[g] = ok ? 1u : 0u;
+        keys[g] = key;
+    }
+}
+
+__global__ void k_first_write(KData D, KStep S, const int32_t* __restrict__ F, const uint64_t* __restrict__ slot_prefix,
+                              int64_t n_req, uint64_t n_slots, const uint32_t* __restrict__ keys,
+                              const int32_t* __restrict__ pos, const uint64_t* __restrict__ rank, MatOut out) {
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_slots;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        if (rank[g + 1] == rank[g]) continue;
+        const int64_t t = find_entry(slot_prefix, 0, n_req, g);
+        int64_t pp[kMaxOps];
+        for (int o = 0; o < S.n_ops; ++o) pp[o] = pos[(uint64_t)o * n_slots + g];
+        write_item(M_EXPAND, D, S, F + t * S.W_in, keys[g], pp, (int64_t)rank[g], out);
+    }
+}
+
 __global__ void k_chunk_entries(const uint64_t* __restrict__ prefix, int64_t e_begin, int64_t e_end,
                                 uint64_t item_begin, uint64_t n_chunks, int64_t* __restrict__ out) {
     for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_chunks;
@@ -1291,6 +1340,7 @@ struct Runner {
     bool emit, digest;
     int seg_bits = 0;                        // key bits above the mixed bits (batched queries)
     int range_word = -1;                     // F_0 word of a query batch's id ranges
+    std::vector<uint64_t> id_slots;          // query batch: exclusive prefix of the id-block widths
     int search_mode = SEARCH_WINDOW;
     unsigned long long* cell_out = nullptr;  // per-cell counts (device), or null
     int64_t cap_entries;
@@ -1312,7 +1362,7 @@ struct Runner {
     int64_t leaf_launches = 0;
     uint64_t leaf_items = 0;
 
-    Runner(hc_ctx* c) : ctx(c), A(c->alloc), s(c->stream) {}
+    Runner(hc_ctx* c, const Alloc& a) : ctx(c), A(a), s(c->stream) {}
     ~Runner() {
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
@@ -1388,7 +1438,7 @@ struct Runner {
             const DAtom& a = D.atoms[po.atom];
             const int64_t stride = ((int64_t)1 << k) + 1;
             const int64_t nodes = a.len[po.lvl - 1];
-            if (nodes * stride <= ((int64_t)1 << 27)) {
+            if (nodes * stride <= cap_entries) {
                 const uint64_t key = ((uint64_t)po.atom << 16) | ((uint64_t)po.lvl << 8) | (uint64_t)k;
                 int found = -1;
                 for (size_t t = 0; t < child_key.size(); ++t)
@@ -1571,11 +1621,42 @@ struct Runner {
     }
 
     void run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n);
+    void first_ids(const int32_t* F, int64_t n);
 };
+
+// F_0 -> F_1 of a request batch by searching each request's mixed ids (k_first_ids).
+void Runner::first_ids(const int32_t* F, int64_t n) {
+    const KStep& S = level_step[0];
+    const uint64_t n_slots = id_slots[(size_t)n];
+    DevBuf<uint64_t> sp(A, (size_t)n + 1);
+    HC_HIP(hipMemcpyAsync(sp.p, id_slots.data(), sizeof(uint64_t) * ((size_t)n + 1), hipMemcpyHostToDevice, s));
+    DevBuf<uint32_t> found(A, (size_t)n_slots), keys(A, (size_t)n_slots);
+    DevBuf<int32_t> pos(A, (size_t)S.n_ops * (size_t)n_slots);
+    DevBuf<uint64_t> rank(A, (size_t)n_slots + 1);
+    k_first_ids<<<grid_for((int64_t)n_slots), kBlock, 0, s>>>(D, S, F, sp.p, n, n_slots, found.p, keys.p, pos.p);
+    HC_HIP(hipGetLastError());
+    scan_exclusive(A, LoadU32{found.p}, rank.p, (int64_t)n_slots, s);
+    const uint64_t got = read_u64(rank.p + n_slots);
+    if (got == 0) return;
+    DevBuf<int32_t> Fn(A, (size_t)got * (size_t)lay[1].W);
+    MatOut mo{};
+    mo.F = Fn.p;
+    k_first_write<<<grid_for((int64_t)n_slots), kBlock, 0, s>>>(D, S, F, sp.p, n, n_slots, keys.p, pos.p, rank.p, mo);
+    HC_HIP(hipGetLastError());
+    found.reset();
+    keys.reset();
+    pos.reset();
+    rank.reset();
+    run_level(1, Fn.p, Fn.p, (int64_t)got);
+}
 
 void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
     if (n <= 0) return;
     const int nv = P.n_vars;
+    if (i == 0 && !id_slots.empty()) {
+        first_ids(F, n);
+        return;
+    }
     // 1. lifted intersections whose lift level is i, chunked by the tmp pool
     std::vector<int> groups;
     for (int g = 0; g < P.n_groups; ++g)
@@ -1724,8 +1805,9 @@ void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
 
 void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order, const int32_t* shares,
               uint32_t flags, bool emit, uint64_t* count, uint64_t* digest, void* out, int64_t capacity,
-              int64_t* n_out, uint64_t* cell_counts, int64_t n_multi, const int64_t* multi_ranges) {
-    Runner R(ctx);
+              int64_t* n_out, uint64_t* cell_counts, int64_t n_multi, const int64_t* multi_ranges,
+              const Alloc* alloc, int64_t cap_entries) {
+    Runner R(ctx, alloc ? *alloc : ctx->alloc);
     // A batch of queries has one F_0 entry per query: an intersection of whole top
     // levels lifted to F_0 would be recomputed for every query, so it is not lifted.
     R.P = compile_plan(q, order, !(flags & HC_NO_REWRITE), n_multi > 0 ? 1 : 0);
@@ -1822,13 +1904,23 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
     R.digest = digest != nullptr;
     R.out_rows = out;
     R.out_cap = capacity;
-    R.cap_entries = (int64_t)1 << 27;
-    R.tmp_max = (int64_t)1 << 27;
+    R.cap_entries = cap_entries > 0 ? cap_entries : kDefaultCap;
+    R.tmp_max = R.cap_entries;
     R.acc = DevBuf<unsigned long long>(R.A, 4);
     R.split = DevBuf<int64_t>(R.A, 2);
     HC_HIP(hipMemsetAsync(R.acc.p, 0, sizeof(unsigned long long) * 4, R.s));
     R.search_mode = (int)((flags & HC_SEARCH_MASK) >> HC_SEARCH_SHIFT);
     HC_REQUIRE(R.search_mode <= SEARCH_BY_SIZE, HC_ERR_INVALID, "unknown search method in flags");
+    // the forced methods of Section 5: the merge is the cursor's linear scan,
+    // galloping the exponential search
+    if (flags & (HC_FORCE_MERGE | HC_FORCE_GALLOP)) {
+        HC_REQUIRE((flags & (HC_FORCE_MERGE | HC_FORCE_GALLOP)) != (HC_FORCE_MERGE | HC_FORCE_GALLOP),
+                   HC_ERR_INVALID, "HC_FORCE_MERGE and HC_FORCE_GALLOP exclude each other");
+        const int forced = (flags & HC_FORCE_MERGE) ? SEARCH_LINEAR : SEARCH_EXPONENTIAL;
+        HC_REQUIRE(R.search_mode == SEARCH_WINDOW || R.search_mode == forced, HC_ERR_INVALID,
+                   "a forced intersection method contradicts the HC_SEARCH_* method");
+        R.search_mode = forced;
+    }
     R.setup_layouts();
     // query batches: F_0 entries end with the query's id range (lo, hi inclusive) on
     // the first variable; word 0 (the cell) is the query index
@@ -1881,6 +1973,26 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
         k_init_cells<<<grid_for(ncell), kBlock, 0, R.s>>>(F0.p, ncell, R.lay[0].W);
         HC_HIP(hipGetLastError());
     }
+    if (n_multi > 0 && P.n_vars > 1) {
+        // small id blocks: search the blocks' mixed ids in the top levels instead of
+        // walking them (taken when the blocks hold fewer ids than a quarter of the
+        // smallest top-level operand)
+        bool all_v0 = true;
+        int64_t len0 = INT64_MAX;
+        for (int t = 0; t < P.levels[0].n_ops; ++t) {
+            const PlanOp& o = P.levels[0].ops[t];
+            all_v0 = all_v0 && o.kind == OP_V0;
+            if (o.kind == OP_V0) len0 = std::min<int64_t>(len0, atoms[o.atom]->level_len[0]);
+        }
+        std::vector<uint64_t> slots((size_t)ncell + 1, 0);
+        for (int64_t t = 0; t < ncell; ++t) {
+            const int64_t lo = std::max<int64_t>(multi_ranges[2 * t], 0);
+            const int64_t hi = std::min<int64_t>(multi_ranges[2 * t + 1], (int64_t)1 << b);
+            slots[(size_t)t + 1] = slots[(size_t)t] + (uint64_t)(hi > lo ? hi - lo : 0);
+        }
+        const uint64_t total = slots[(size_t)ncell];
+        if (all_v0 && total <= ((uint64_t)1 << 27) && (int64_t)total * 4 <= len0) R.id_slots = std::move(slots);
+    }
     R.run_level(0, F0.p, F0.p, ncell);
     unsigned long long a[3] = {0, 0, 0};
     HC_HIP(hipMemcpyAsync(a, R.acc.p, sizeof(a), hipMemcpyDeviceToHost, R.s));
@@ -1919,13 +2031,15 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
 // step buffers, match words, lifted-intersection pools, work-queue tables), from
 // host-side CoCo statistics only.  Entries of F_{i+1} are bounded by those of F_i
 // times the longest list of level i's shortest operand (a predicate bounds it by
-// its id range), and every frontier chunk by the chunking cap.
+// its id range); below F_0 every frontier chunk, pool and match-word array holds at
+// most max(cap, one entry's elements) items, cap being the chunking cap of the call.
 uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
-                              const int32_t* shares, uint32_t flags, int64_t n_queries, int64_t first_width) {
+                              const int32_t* shares, uint32_t flags, int64_t n_queries, int64_t first_width,
+                              int64_t cap_entries) {
     const Plan P = compile_plan(q, order, !(flags & HC_NO_REWRITE), n_queries > 0 ? 1 : 0);
-    constexpr double kCap = (double)((int64_t)1 << 27);   // frontier entries / pool elements per chunk
+    const double kCap = (double)cap_entries;   // frontier entries / pool elements per chunk
     int K = 0;
-    for (int v = 0; v < P.n_vars; ++v) K += shares ? shares[v] : 0;
+    for (int v = 0; v < P.n_vars; ++v) K += (shares && n_queries == 0) ? shares[v] : 0;
     auto op_max = [&](const PlanOp& o) -> double {
         const hc_coco* c = atoms[o.atom];
         return o.kind == OP_CHILD ? (double)c->max_children[o.lvl - 1] : (double)c->level_len[0];
@@ -1939,6 +2053,34 @@ uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, co
     double E = n_queries > 0 ? (double)n_queries : std::ldexp(1.0, K);
     double bytes = (double)(1 << 20);   // allocation granularity of the many small buffers
     bytes += 8.0 * E + (n_queries > 0 ? 12.0 * E : 0.0);   // per-cell (per-query) counts, query ranges
+    // Tables the operands take at set-up (Runner::make_op): the key range of a top
+    // level per coordinate (8 bytes per coordinate of a share, or of the segment
+    // bits) and, per (atom, CoCo level, share), the child sub-range table of
+    // nodes * (2^k + 1) + 1 int32 when it has at most cap entries.
+    {
+        const int seg_bits = atoms[0]->key_bits - atoms[0]->mix_bits;
+        std::vector<uint64_t> tab_keys;
+        auto op_tables = [&](const PlanOp& o, int var) {
+            const int k = (shares && n_queries == 0) ? shares[var] : 0;
+            if (o.kind == OP_V0) {
+                const int vk = k > 0 ? k : seg_bits;
+                if (vk > 0) bytes += 8.0 * std::ldexp(1.0, vk);
+            } else if (o.kind == OP_CHILD && k > 0) {
+                const double nodes = (double)atoms[o.atom]->level_len[o.lvl - 1];
+                const double entries = nodes * (std::ldexp(1.0, k) + 1.0);
+                const uint64_t key = ((uint64_t)o.atom << 16) | ((uint64_t)o.lvl << 8) | (uint64_t)k;
+                if (entries <= kCap && std::find(tab_keys.begin(), tab_keys.end(), key) == tab_keys.end()) {
+                    tab_keys.push_back(key);
+                    bytes += 4.0 * (entries + 1.0);
+                }
+            }
+        };
+        for (int i = 0; i < P.n_vars; ++i)
+            for (int t = 0; t < P.levels[i].n_ops; ++t) op_tables(P.levels[i].ops[t], P.levels[i].var);
+        for (int g = 0; g < P.n_groups; ++g)
+            for (int t = 0; t < P.groups[g].n_ops; ++t) op_tables(P.groups[g].ops[t], P.groups[g].var);
+    }
+    double chunk = 1e30;   // entries of one frontier chunk: F_0 is never split
     for (int i = 0; i < P.n_vars; ++i) {
         const PlanLevel& L = P.levels[i];
         double m = 1e30;
@@ -1947,24 +2089,29 @@ uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, co
         if (q->var_lo && q->var_hi && q->var_hi[L.var] > q->var_lo[L.var])
             m = std::min(m, (double)q->var_hi[L.var] - (double)q->var_lo[L.var]);
         if (i == 0 && n_queries > 0 && first_width > 0) m = std::min(m, (double)first_width);
-        const double n = std::min(E, kCap);
+        const double n = std::min(E, chunk);
         const Layout Li = make_layout(P, i);
         bytes += n * 4.0 * (Li.W + (i == 0 && n_queries > 0 ? 2 : 0));   // F_i
         bytes += n * (8.0 * L.n_ops + 16.0) + 8.0;             // ranges, iterated operand, length, prefix
         for (int g = 0; g < P.n_groups; ++g) {
             if (P.groups[g].lift != i) continue;
-            const double pool = std::min(n * gmax[g], kCap);
+            // a pool holds at most the cap, or one entry's elements when that is larger
+            const double pool = std::min(n * gmax[g], std::max(kCap, gmax[g]));
             bytes += n * (8.0 * P.groups[g].n_ops + 16.0) + 8.0;
             bytes += pool * 4.0 * (1 + P.groups[g].n_ops) + (pool / 64 + 1) * 16.0;
             bytes += pool * 4.0 * P.groups[g].n_ops;                       // positions of the bitmap pass
         }
         const double items = std::min(n * m, 1e18);
+        const double citems = std::min(items, std::max(kCap, m));   // elements of one expand / emit chunk
+        if (i == 0 && n_queries > 0)   // id-block search of a request batch: found flag, key, rank
+            bytes += std::min(items, kCap) * 24.0 + 8.0 * (n + 1);
         if (i + 1 < P.n_vars) {
-            bytes += (std::min(items, kCap) / 64 + 1) * 16.0;   // match words of a chunk
-            bytes += std::min(items, kCap) * 4.0 * L.n_ops;     // positions of the bitmap pass
+            bytes += (citems / 64 + 1) * 16.0;   // match words of a chunk
+            bytes += citems * 4.0 * L.n_ops;     // positions of the bitmap pass
         }
         bytes += (items / 2048 + 1) * 8.0 + 64.0;                                  // work-queue chunk table
         E = std::min(E * m, 1e18);
+        chunk = std::max(kCap, m);
     }
     return (uint64_t)std::min(bytes, 1.8e19);
 }

@@ -29,6 +29,7 @@ HC_KEEP_ORDER = 0x8
 HC_JOINT_SEARCH = 0x10
 HC_PESSIMISTIC = 0x20
 HC_CACHE_SHARES = 0x40
+HC_EMIT_SORTED = 0x80
 HC_SEARCH_WINDOW = 0x000
 HC_SEARCH_EXPONENTIAL = 0x100
 HC_SEARCH_QUADRATIC = 0x200
@@ -156,13 +157,18 @@ class Context:
         self._sptr = sptr
         self.max_bytes = int(max_bytes)
         self.live = {}
+        self.alloc_error = None   # why the allocator last refused a request
+        self.n_allocs = 0         # requests the library made through this context's allocator
         if use_torch_allocator:
             def _alloc(nbytes, user):
+                self.n_allocs += 1
                 if self.max_bytes and sum(self.live.values()) + int(nbytes) > self.max_bytes:
+                    self.alloc_error = "context cap of %d bytes" % self.max_bytes
                     return None
                 try:
                     p = torch.cuda.caching_allocator_alloc(int(nbytes), device, sptr)
-                except Exception:
+                except Exception as e:
+                    self.alloc_error = "%s: %s" % (type(e).__name__, str(e).splitlines()[0] if str(e) else "")
                     return None
                 if self.max_bytes:
                     self.live[p] = int(nbytes)
@@ -183,7 +189,11 @@ class Context:
 
     def check(self, st: int):
         if st != HC_OK:
-            raise HCError(st, lib().hc_last_error(self.h).decode())
+            msg = lib().hc_last_error(self.h).decode()
+            if st == HC_ERR_OOM and self.alloc_error:
+                msg += " (%s)" % self.alloc_error
+                self.alloc_error = None
+            raise HCError(st, msg)
 
     def cancel(self, on: bool = True):
         """Raise (or withdraw) the context's cancel request; safe from another thread."""

@@ -286,7 +286,12 @@ def replay(server: Server, requests: List[Request], time_scale: float = 1.0):
 def summarize(requests: List[Request], wall_s: float) -> Dict:
     lat = np.array([(r.t_done - r.t_arrival) * 1e3 for r in requests if r.error is None])
     ok = int(lat.size)
+    errors: Dict[str, int] = {}
+    for r in requests:
+        if r.error is not None:
+            errors[r.error] = errors.get(r.error, 0) + 1
     return {
+        "errors": errors,
         "requests": len(requests),
         "answered": ok,
         "failed": len(requests) - ok,

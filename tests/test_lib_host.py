@@ -234,3 +234,28 @@ def test_cache_shares_is_the_cheapest_vector_that_fits(name, rows, K):
         assert cost <= min(c[2] for c in fits) * (1 + 1e-9)
     else:
         assert slice_bytes(shares) <= min(c[1] for c in cands) * (1 + 1e-9)
+
+
+def test_unknown_flags_are_rejected_by_host_calls():
+    """Every call rejects flag bits it does not take (HC_ERR_INVALID): the share
+    decision takes only its own flags, the plan cost and description only theirs."""
+    n, atoms = inputs.QUERIES["triangle"]
+    q = hc.Query(n, atoms)
+    info = hc.CocoInfo()
+    info.n_input = info.n_unique = 1 << 16
+    info.arity = 2
+    info.key_bits = info.mix_bits = 12
+    info.level_len[0], info.level_len[1] = 1 << 12, 1 << 16
+    info.max_children[0] = 64
+    info.distinct[0] = info.distinct[1] = 1 << 12
+    infos = [info] * 3
+    assert hc.compute_shares_from_info(q, infos, 6, flags=hc.HC_CACHE_SHARES | hc.HC_PESSIMISTIC)
+    for bad in [hc.HC_EMIT_SORTED, hc.HC_FORCE_MERGE, hc.HC_SEARCH_LINEAR, 0x10000]:
+        with pytest.raises(hc.HCError) as ei:
+            hc.compute_shares_from_info(q, infos, 6, flags=bad)
+        assert ei.value.status == hc.HC_ERR_INVALID
+    with pytest.raises(hc.HCError):
+        hc.plan_cost_from_info(q, infos, [0, 1, 2], flags=hc.HC_CACHE_SHARES)
+    with pytest.raises(hc.HCError):
+        hc.plan_describe(q, [0, 1, 2], flags=hc.HC_FORCE_GALLOP)
+    assert hc.plan_describe(q, [0, 1, 2], flags=hc.HC_NO_REWRITE)["levels"]
