@@ -283,6 +283,27 @@ hc_status hc_join_count(hc_ctx* ctx, const hc_query* q, const hc_coco* const* at
                         uint64_t* count_out, uint64_t* digest_out);
 
 /*
+ * hc_join_count for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same count and digest, with every device buffer of the call carved out of a
+ * fixed scratch array of 256 MiB that the library holds on each GPU it runs on
+ * (set up when the first context on that GPU is created, kept until the process
+ * ends).  The call makes no hipMalloc or hipFree and never calls the context's
+ * allocator; profiling events are not recorded.  The call's inputs (the CoCos)
+ * and outputs are the caller's as for hc_join_count.
+ *   scratch_used  host, nullable: receives the bytes of the array the call used
+ * Every call on one GPU shares that GPU's array and leaves its contents behind
+ * (the call clears what it needs): calls that overlap on one GPU -- from two
+ * contexts or threads -- race and must not be issued.
+ * Errors: HC_ERR_UNSUPPORTED when hc_join_workspace_bound of the call exceeds
+ * the array (use hc_join_count then); HC_ERR_OOM if the array's free ranges
+ * cannot hold a buffer; otherwise as hc_join_count.
+ */
+hc_status hc_join_count_noalloc(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
+                                const int32_t* var_order, const int32_t* log2_shares, uint32_t flags,
+                                uint64_t* count_out, uint64_t* digest_out, uint64_t* scratch_used);
+
+/*
  * Count per HyperCube cell (the output of each of the paper's threads, Section
  * 5): cell_counts (host, 2^(sum of log2_shares) entries) receives the number of
  * result tuples of every cell; the cell id packs the coordinates of the

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhc.so")
-SOURCES = ["api.cpp", "plan.cpp", "prim.hip", "build.hip", "join.hip", "rows.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "prim.hip", "build.hip", "join.hip", "rows.hip", "noalloc.hip"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # packed-fp32 instructions stay off on this target

@@ -116,6 +116,13 @@ hc_status hc_ctx_create(int device, void* hip_stream, hc_alloc_fn alloc, hc_free
         return HC_ERR_DEVICE;
     }
     __atomic_store_n(c->h_cancel, 0, __ATOMIC_SEQ_CST);
+    // the device address of this device's scratch array (hc_join_count_noalloc)
+    try {
+        hc::scratch_setup(device);
+    } catch (const hc::Error& e) {
+        hc_ctx_destroy(c);
+        return e.st;
+    }
     *out = c;
     return HC_OK;
 }
@@ -355,6 +362,52 @@ hc_status hc_join_count(hc_ctx* ctx, const hc_query* q, const hc_coco* const* at
         }
         hc::join_run(ctx, q, atom_index, var_order, log2_shares, flags, false, count_out, digest_out, nullptr, 0,
                      nullptr);
+    });
+}
+
+hc_status hc_join_count_noalloc(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
+                                const int32_t* var_order, const int32_t* log2_shares, uint32_t flags,
+                                uint64_t* count_out, uint64_t* digest_out, uint64_t* scratch_used) {
+    if (!ctx) return HC_ERR_INVALID;
+    return guarded(ctx, [&] {
+        check_query_ptrs(q);
+        HC_REQUIRE(atom_index && var_order && count_out, HC_ERR_INVALID, "NULL argument");
+        check_flags(flags, kJoinFlags, "hc_join_count_noalloc");
+        for (int j = 0; j < q->n_atoms; ++j) HC_REQUIRE(atom_index[j] != nullptr, HC_ERR_INVALID, "atom CoCo handle is NULL");
+        // the largest chunking cap whose workspace bound fits the array (smaller caps
+        // split the frontiers into more, smaller chunks)
+        int64_t cap = hc::kDefaultCap;
+        uint64_t need = 0;
+        for (;; cap >>= 2) {
+            need = hc::join_workspace_bound(q, atom_index, var_order, log2_shares, flags, 0, 0, cap);
+            if (need <= hc::scratch_bytes() || cap <= ((int64_t)1 << 12)) break;
+        }
+        HC_REQUIRE(need <= hc::scratch_bytes(), HC_ERR_UNSUPPORTED,
+                   "hc_join_count_noalloc: the call may need " + std::to_string(need) +
+                       " bytes of device scratch even in chunks of " + std::to_string(cap) +
+                       " entries, more than the fixed " + std::to_string(hc::scratch_bytes()) +
+                       " bytes it has; use hc_join_count");
+        void* base = hc::scratch_ptr(ctx->device);
+        HC_REQUIRE(base != nullptr, HC_ERR_DEVICE, "scratch array of this device was not set up");
+        hc::ScratchArena arena(base, hc::scratch_bytes());
+        hc::Alloc a;
+        a.alloc = hc::ScratchArena::alloc_cb;
+        a.free_ = hc::ScratchArena::free_cb;
+        a.user = &arena;
+        a.stream = ctx->stream;
+        // no timing events either: profiling is off for this call
+        const int prof = ctx->profiling;
+        ctx->profiling = 0;
+        try {
+            hc::join_run(ctx, q, atom_index, var_order, log2_shares, flags, false, count_out, digest_out, nullptr, 0,
+                         nullptr, nullptr, 0, nullptr, &a, cap);
+        } catch (...) {
+            ctx->profiling = prof;
+            HC_HIP(hipStreamSynchronize(ctx->stream));   // nothing may still use the arena's ranges
+            throw;
+        }
+        ctx->profiling = prof;
+        if (scratch_used) *scratch_used = arena.high_water();
     });
 }
 

@@ -104,6 +104,32 @@ struct DevBuf {
     ~DevBuf() { reset(); }
 };
 
+// First-fit arena over the per-device scratch array (noalloc.hip): hands out
+// 256-byte aligned ranges, host-side bookkeeping only.
+class ScratchArena {
+public:
+    ScratchArena(void* base, size_t size);
+    void* get(size_t bytes);
+    void put(void* p);
+    size_t high_water() const { return high_; }
+    static void* alloc_cb(size_t bytes, void* user);
+    static void free_cb(void* p, void* user);
+
+private:
+    struct Range {
+        size_t off, len;
+    };
+    char* base_;
+    size_t size_;
+    size_t high_ = 0;
+    std::vector<Range> free_, used_;
+};
+// Look up the device address of this device's scratch array (the device must be
+// current); idempotent.  scratch_ptr returns it (null before set-up).
+void scratch_setup(int device);
+void* scratch_ptr(int device);
+size_t scratch_bytes();
+
 }  // namespace hc
 
 // ---------------------------------------------------------------- handles

@@ -87,6 +87,7 @@ SIGNATURES = {
     "hc_join_count": (ctypes.c_int, [P, P, P, P, P, U32, P, P]),
     "hc_join_emit": (ctypes.c_int, [P, P, P, P, P, U32, P, I64, P]),
     "hc_join_count_cells": (ctypes.c_int, [P, P, P, P, P, U32, P, P]),
+    "hc_join_count_noalloc": (ctypes.c_int, [P, P, P, P, P, U32, P, P, P]),
     "hc_join_workspace_bound": (ctypes.c_int, [P, P, P, P, P, U32, I64, I64, P]),
     "hc_join_count_multi": (ctypes.c_int, [P, P, P, P, U32, I64, P, P]),
     "hc_plan_describe": (ctypes.c_int, [P, P, U32, P, ctypes.c_size_t]),
@@ -326,6 +327,23 @@ def join_count(ctx: Context, q: Query, cocos, order, log2_shares=None, flags: in
     if digest:
         return int(cnt.value), (int(dg[0]), int(dg[1]))
     return int(cnt.value)
+
+
+def join_count_noalloc(ctx: Context, q: Query, cocos, order, log2_shares=None, flags: int = 0,
+                       digest: bool = False):
+    """hc_join_count_noalloc: the count (and digest) with every device buffer taken from
+    the library's fixed per-GPU scratch array.  Returns (count, digest or None, bytes of
+    scratch used)."""
+    order_a = _i32(order)
+    sh = _i32(log2_shares) if log2_shares is not None else None
+    cnt = ctypes.c_uint64(0)
+    used = ctypes.c_uint64(0)
+    dg = (ctypes.c_uint64 * 2)()
+    qc = q.c()
+    ctx.check(lib().hc_join_count_noalloc(ctx.h, ctypes.byref(qc), _handles(cocos), order_a.ctypes.data,
+                                          sh.ctypes.data if sh is not None else None, flags, ctypes.byref(cnt),
+                                          dg if digest else None, ctypes.byref(used)))
+    return int(cnt.value), ((int(dg[0]), int(dg[1])) if digest else None), int(used.value)
 
 
 def join_count_cells(ctx: Context, q: Query, cocos, order, log2_shares, flags: int = 0):
