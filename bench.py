@@ -33,10 +33,29 @@ CLOCK_HZ = 2.4e9
 
 
 def _source_hash():
+    """Hash of the sources that decide the leaf kernel's work: its code and the share
+    decision (a different share vector changes the kernel's traffic)."""
     h = hashlib.sha256()
-    for f in ["join.hip", "prim_dev.h", "hc_internal.h"]:
+    for f in ["join.hip", "prim_dev.h", "hc_internal.h", "plan.cpp"]:
         h.update(open(os.path.join(ROOT, "paper_2502_06715_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _host_threads():
+    try:
+        return min(16, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        return min(16, os.cpu_count() or 1)
 
 
 def _workload(cfg):
@@ -57,15 +76,10 @@ def _workload(cfg):
     return desc, spec["n"].bit_length() - 1, "clique4"
 
 
-def cpu_baseline(E, n_vars, atoms, full_count, budget_s=15.0):
-    """The oracle on this host: sort once, then Generic Join over randomly chosen
-    blocks of first-variable ids until budget_s of join time; the full-job time is
-    estimated as sort + join_time * full_count / sample_count."""
+def _sample_run(E, n_vars, atoms, full_count, budget_s, threads):
+    """The oracle on a bounded sample: sort once, then Generic Join over randomly
+    chosen blocks of first-variable ids until budget_s of join time is spent."""
     from oracle import oracle
-    try:
-        threads = min(16, len(os.sched_getaffinity(0)))
-    except AttributeError:
-        threads = min(16, os.cpu_count() or 1)
     nid = int(E.max()) + 1
     nblk = 1024
     width = (nid + nblk - 1) // nblk
@@ -75,16 +89,33 @@ def cpu_baseline(E, n_vars, atoms, full_count, budget_s=15.0):
     cnt = sum(d[2] for d in done)
     js = sum(d[3] for d in done)
     frac = cnt / full_count if full_count else 0.0
-    est = sort_s + (js / frac if frac > 0 else float("inf"))
+    return sort_s, js, len(done), nblk, frac
+
+
+def cpu_baseline(E, n_vars, atoms, full_count, budget_s=15.0, budget_1t=5.0):
+    """The oracle on this host's cores (its OpenMP threads = the host threads this
+    process may use, at most 16), on a bounded sample of the workload; the job's
+    output rate is the sample's tuples over the sample's sort + join time.  A
+    one-thread sample is timed beside it.  (The full job at the same thread count is
+    measured once and recorded with the design notes: it takes minutes.)"""
+    threads = _host_threads()
+    sort_s, js, nb, nblk, frac = _sample_run(E, n_vars, atoms, full_count, budget_s, threads)
+    # sample output rate: the sampled blocks' tuples per second of their join time, the
+    # sort of the whole input charged in proportion to the sampled fraction
+    t_job = sort_s + (js / frac if frac > 0 else float("inf"))
+    s1, j1, nb1, _, f1 = _sample_run(E, n_vars, atoms, full_count, budget_1t, 1)
+    t1 = s1 + (j1 / f1 if f1 > 0 else float("inf"))
     return {
-        "value": full_count / est if est > 0 else 0.0,
+        "value": full_count / t_job if t_job > 0 else 0.0,
         "unit": "tuples/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": ("oracle sort+dedup of all %d atoms (%.1f s) then Generic Join over %d of %d random "
-                   "first-variable id blocks (%.1f s, %.2f%% of the output); full-job time extrapolated "
-                   "as sort + join/fraction = %.1f s" % (len(atoms), sort_s, len(done), nblk, js,
-                                                         100 * frac, est)),
+        "cpu_model": _cpu_model(),
+        "one_thread_value": full_count / t1 if t1 > 0 else 0.0,
+        "sample": ("oracle (C, OpenMP, %d threads) sort+dedup of every atom (%.1f s), then Generic Join over "
+                   "%d of %d random first-variable id blocks (%.1f s, %.2f%% of the output): %.1f s per "
+                   "full job at that rate; one thread: %d blocks, %.2f%% of the output, %.1f s per full job"
+                   % (threads, sort_s, nb, nblk, js, 100 * frac, t_job, nb1, 100 * f1, t1)),
     }
 
 
@@ -536,6 +567,8 @@ def main():
                     help="served workload: only the closed-loop saturation runs")
     ap.add_argument("--tensor-scale", type=int, default=1,
                     help="tensor workloads: divide ST-Sparse's domain sizes by 2^s (densities kept)")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="only time the CPU oracle on the whole workload (sort + Generic Join), no GPU")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -548,6 +581,23 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}), flush=True)
+        return
+    if args.cpu_full:
+        from paper_2502_06715_amd import inputs
+        from oracle import oracle
+        desc, _, qname = _workload(args.config)
+        n_vars, atoms = inputs.QUERIES[qname]
+        E = inputs.config_graph(args.config)
+        gold = json.load(open(os.path.join(ROOT, "tests", "golden", "workloads.json")))
+        threads = _host_threads()
+        t0 = time.perf_counter()
+        cnt = oracle.gj(n_vars, atoms, [E] * len(atoms), threads=threads).count
+        sec = time.perf_counter() - t0
+        if cnt != gold[str(args.config)]["count"]:
+            print("oracle count %d differs from the stored count" % cnt, file=sys.stderr)
+            sys.exit(1)
+        print(json.dumps({"workload": desc, "cpu_full_s": round(sec, 2), "tuples_per_s": cnt / sec,
+                          "threads": threads, "cpu_model": _cpu_model(), "count": cnt}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library runs the join on a single device "
@@ -631,6 +681,7 @@ def main():
 
     # roofline of the dominant kernel: the deepest level of Generic Join
     leaf_ms = sum(r["leaf_ms"] for r in res)
+    shares_now = res[-1]["shares"]
     launches = sum(r["leaf_launches"] for r in res)
     wk = gold[str(args.config)].get("work_gallop_per_level")
     roof = None
@@ -641,25 +692,36 @@ def main():
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
         traffic = None
         issue = None
+        hbm_measured = None
+        limiter = None
         tf = os.path.join(ROOT, "profiles", "leaf_traffic_config%d.json" % args.config)
         if os.path.exists(tf):
             t = json.load(open(tf))
-            if t.get("source_hash") == _source_hash():
+            # the counters hold for this kernel source, share rule and share vector only
+            if t.get("source_hash") == _source_hash() and t.get("log2_shares") == shares_now:
                 traffic = t.get("bytes_per_launch")
-                # the kernel is bound by instruction issue rather than HBM: wave64 vector
-                # instructions take one of a CU's 4 SIMDs for 4 cycles, scalar ones the
-                # CU's scalar unit for 1 (256 CUs at 2.4 GHz); counts from the profile,
-                # time from this run
+                sec = avg_ms * 1e-3
+                hbm_measured = {"gbs": round(traffic / sec / 1e9, 1),
+                                "frac": round(traffic / sec / 1e9 / HBM_PEAK_GBS, 4)}
+                # instruction issue: a wave64 vector instruction takes one of a CU's 4 SIMDs
+                # for 4 cycles, a scalar one the CU's scalar unit for 1 (256 CUs at 2.4 GHz);
+                # counts from the profile, time from this run
                 if t.get("valu_insts_per_launch"):
-                    sec = avg_ms * 1e-3
                     issue = {"valu_frac": round(t["valu_insts_per_launch"] * 4 / (1024 * CLOCK_HZ * sec), 3),
                              "salu_frac": round(t["salu_insts_per_launch"] / (256 * CLOCK_HZ * sec), 3),
                              "source": t.get("summary")}
+                # what the counters say limits the kernel: the busiest of HBM and the two
+                # issue pipes (the rest of its time is spent waiting on L2 and LDS latency)
+                fr = {"hbm": hbm_measured["frac"]}
+                if issue:
+                    fr.update({"vector issue": issue["valu_frac"], "scalar issue": issue["salu_frac"]})
+                limiter = max(fr, key=fr.get)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_probe2<M_COUNT, 2> (deepest level)", "avg_launch_ms": round(avg_ms, 3),
                 "launches_per_step": launches / args.steps,
-                "algorithmic_bytes_per_launch": per_launch, "issue": issue}
+                "algorithmic_bytes_per_launch": per_launch,
+                "hbm_measured": hbm_measured, "issue": issue, "limiter": limiter}
     out = {
         "metric": "output tuples/s on triangle query" if qname == "triangle" else "output tuples/s",
         "value": count / (ms_per_step / 1000.0),

@@ -455,17 +455,17 @@ __device__ inline T sload(const T* p) {
 // probe of the 64 elements at the cursor, then 64-ary narrowing, so a long jump
 // costs about log64 of its length in dependent loads (wave-uniform result).  Lanes
 // past the end reload the last element instead of branching around their load.
-__device__ inline bool probe_lt(const uint32_t* __restrict__ Bc, int32_t n, uint32_t v, uint32_t lane4) {
+__device__ inline uint64_t probe_lt(const uint32_t* __restrict__ Bc, int32_t n, uint32_t v, uint32_t lane4) {
     const uint32_t n4 = (uint32_t)((n < 64 ? n : 64) - 1) * 4u;   // n >= 1; only 64 lanes
     const uint32_t x = *(const uint32_t*)((const char*)Bc + (lane4 < n4 ? lane4 : n4));
-    return lane4 <= n4 && x < v;
+    return __ballot(lane4 <= n4) & __ballot(x < v);   // ballots of single compares
 }
 __device__ inline int32_t wave_search(const uint32_t* __restrict__ B, int32_t c, int32_t end, uint32_t v,
                                       int lane) {
     if (c >= end) return c;
     const uint32_t lane4 = (uint32_t)lane * 4u;
     {
-        const int k = __popcll(__ballot(probe_lt(B + c, end - c, v, lane4)));
+        const int k = __popcll(probe_lt(B + c, end - c, v, lane4));
         if (k < 64) return c + k;
     }
     int32_t lo = c + 64, hi = end;   // the answer lies in [lo, hi]
@@ -481,7 +481,26 @@ __device__ inline int32_t wave_search(const uint32_t* __restrict__ B, int32_t c,
         hi = nhi;
     }
     if (lo >= hi) return lo;
-    return lo + __popcll(__ballot(probe_lt(B + lo, hi - lo, v, lane4)));
+    return lo + __popcll(probe_lt(B + lo, hi - lo, v, lane4));
+}
+
+// The same when the answer is expected about `hint` elements past c: the first round
+// probes 64 positions hint/32 apart (the expected answer falls in the first half of
+// them), then the found stride is searched as above.
+__device__ inline int32_t wave_search_hint(const uint32_t* __restrict__ B, int32_t c, int32_t end, uint32_t v,
+                                           int lane, uint32_t hint) {
+    if (c >= end) return c;
+    // stride: hint / 32, at most (end - c) / 63 + 1 (so c + 63 * st stays near end)
+    const int32_t st = (int32_t)min(hint >> 5, (uint32_t)(end - c) / 63u + 1u);
+    if (st <= 1) return wave_search(B, c, end, v, lane);
+    const int32_t p = c + lane * st;
+    const uint64_t in = __ballot(p < end);
+    const uint64_t lt = __ballot(B[p < end ? p : end - 1] < v) & in;
+    const int k = __popcll(lt);   // probes below v: a prefix of the lanes
+    if (k == 0) return c;
+    const int32_t lo = c + (k - 1) * st + 1;
+    const int32_t hi = (k == 64 || c + k * st >= end) ? end : c + k * st;   // B[hi] >= v when hi < end
+    return wave_search(B, lo, hi, v, lane);
 }
 
 // Stage B[base, base + len_al) in an LDS region with 16-byte loads (base is a
@@ -539,6 +558,40 @@ __device__ inline void stage_window_inlist(uint32_t* rw, const uint32_t* __restr
     for (int i = 0; i < 4; ++i)
         if (lane + 64 * i < nq) dst[lane + 64 * i] = val[i];
     if (lane < sh) rw[lane] = 0u;
+}
+
+// The same when all of B[base, base + p2) lies inside the list (p2 a power of two,
+// 64 <= p2 <= 1024): it is copied whole, later list elements past the window being
+// no smaller than any searched value; whole rows of 64 quads need no lane test.
+__device__ inline void stage_full(uint32_t* rw, const uint32_t* __restrict__ B, int32_t base, int32_t sh, int32_t p2,
+                                  int lane) {
+    const uint4* src = reinterpret_cast<const uint4*>(B + base);
+    uint4* dst = reinterpret_cast<uint4*>(rw);
+    const int nq = p2 >> 2;
+    if (nq >= 256) {
+        const uint4 v0 = src[lane], v1 = src[lane + 64], v2 = src[lane + 128], v3 = src[lane + 192];
+        dst[lane] = v0;
+        dst[lane + 64] = v1;
+        dst[lane + 128] = v2;
+        dst[lane + 192] = v3;
+    } else if (nq == 128) {
+        const uint4 v0 = src[lane], v1 = src[lane + 64];
+        dst[lane] = v0;
+        dst[lane + 64] = v1;
+    } else if (nq == 64) {
+        dst[lane] = src[lane];
+    } else if (lane < nq) {
+        dst[lane] = src[lane];
+    }
+    if (lane < sh) rw[lane] = 0u;
+}
+
+// nsc * rem_b / rem_a, approximately (a window size estimate: single precision is
+// plenty), wave-uniform.
+__device__ inline uint32_t est_cover(uint32_t nsc, uint32_t rem_b, uint32_t rem_a) {
+    const float r = (float)rem_b * __builtin_amdgcn_rcpf((float)rem_a);
+    const int32_t e = (int32_t)fminf((float)nsc * r, 1.0e9f);
+    return (uint32_t)__builtin_amdgcn_readfirstlane(e);
 }
 
 // Largest e' in [e, e_end) with prefix[e'] <= g, given prefix[e] <= g: exponential
@@ -893,16 +946,56 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                         }
                         continue;
                     }
-                    // ---- long operand: the step's values a_first .. a_last have their lower
-                    // bounds in [lo, hi], found by two wave searches from the cursor.  The
-                    // range is staged in LDS when it fits; otherwise every s-th element
-                    // is (fences), and each value finishes with a search of its s-element
-                    // bucket in place.
+                    // ---- long operand: the lower bounds of the step's values a_first .. a_last
+                    // lie in [cursor, lower bound of a_last].  Keys are hashed, so they spread
+                    // over about est = nsc * (rest of B) / (rest of the iterated list) elements
+                    // from the cursor: that many, with a margin, are staged in LDS from the
+                    // cursor without searching for the range's end, and the step searches
+                    // there.  When the estimate exceeds the region, or the staged window
+                    // ends below a_last (an overshoot), the range is found by two wave searches
+                    // from the cursor (the second starting with strides sized by est) and
+                    // staged when it fits; otherwise every s-th element is (fences), and each
+                    // value finishes with a search of its s-element bucket in place.
 #pragma unroll
                     for (int u = 0; u < NOPS; ++u) wc_ptr[u] = nullptr;   // the window overwrites every region
                     const uint32_t a_first = sload(ab), a_last = sload(ab + last);
+                    const uint32_t est = est_cover((uint32_t)nsc, (uint32_t)(end[o] - cur[o]), hi_rel - rc);
+                    {
+                        const int32_t ws = cur[o] & ~3;
+                        const int32_t sh0 = cur[o] - ws;
+                        const uint32_t want = est + (est >> 2) + 32u + (uint32_t)sh0;
+                        if (want <= (uint32_t)kWin) {
+                            int32_t P = 64;
+                            while ((uint32_t)P < want) P <<= 1;
+                            const bool to_end = ws + P >= end[o];
+                            const int32_t len_al = to_end ? end[o] - ws : P;
+                            if (!to_end)
+                                stage_full(win, B, ws, sh0, P, lane);
+                            else
+                                stage_window(win, B, ws, sh0, len_al, P, lane);
+                            wave_sync();
+                            // (the LDS word is the same for every lane: read it as a uniform value, so
+                            // that the branch and the cursor stay scalar)
+                            if (to_end || (uint32_t)uni((int32_t)win[P - 1]) >= a_last) {
+                                int32_t p[kSub];
+                                lds_search<kSub>(win, P, a, p);
+                                int32_t pl = 0;
+#pragma unroll
+                                for (int k = 0; k < kSub; ++k) {
+                                    const int32_t pc = min(max(p[k], sh0), P - 1);
+                                    fm[k] &= __ballot(pc < len_al) & __ballot(win[pc] == a[k]);
+                                    if (kPos) pos[o][k] = ws + pc;
+                                    if (k == (last >> 6)) pl = __builtin_amdgcn_readlane(max(p[k], sh0), last & 63);
+                                }
+                                wave_sync();
+                                cur[o] = ws + pl;   // lower bound of the step's last value
+                                continue;
+                            }
+                            wave_sync();
+                        }
+                    }
                     const int32_t lo = uni(wave_search(B, cur[o], end[o], a_first, lane));
-                    const int32_t hi = uni(wave_search(B, lo, end[o], a_last, lane));
+                    const int32_t hi = uni(wave_search_hint(B, lo, end[o], a_last, lane, est));
                     const int32_t cover = (hi < end[o] ? hi + 1 : end[o]) - lo;
                     if (cover <= kWin - 4) {
                         // The window starts at the 16-byte boundary below lo (16-byte
