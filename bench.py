@@ -297,6 +297,32 @@ def bench_serve(args):
             if cb != cs:
                 print("served counts differ from one-query-per-launch counts", file=sys.stderr)
                 sys.exit(1)
+    # full queries: the whole query on a resident graph (triangles on every graph,
+    # 4-cycles and 4-cliques on the graphs of at most inputs.FULL_MAX_EDGES edges)
+    full = {}
+    if args.full_requests > 0:
+        fprobe = inputs.serve_full_stream(specs, args.full_requests, qps=1.0)
+        fsat_base, fc_base = run(base_eng, 1, False, fprobe, True)
+        print("# full queries, saturation, one query per launch: %s" % json.dumps(fsat_base), file=sys.stderr,
+              flush=True)
+        fsat_srv, fc_srv = run(eng, args.slots, True, fprobe, True)
+        print("# full queries, saturation, serving loop: %s" % json.dumps(fsat_srv), file=sys.stderr, flush=True)
+        if fc_base != fc_srv or any(c is None for c in fc_srv):
+            print("full-query counts differ between the serving loop and one query per launch", file=sys.stderr)
+            sys.exit(1)
+        fqps = 0.8 * fsat_base["queries_per_s"]
+        fstream = inputs.serve_full_stream(specs, args.full_requests, qps=fqps)
+        fo_srv, fcs = run(eng, args.slots, True, fstream, False)
+        fo_base, fcb = run(base_eng, 1, False, fstream, False)
+        print("# full queries, open loop %.1f/s: serving loop %s; one query per launch %s"
+              % (fqps, json.dumps(fo_srv), json.dumps(fo_base)), file=sys.stderr, flush=True)
+        if fcs != fcb or any(c is None for c in fcs):
+            print("full-query counts differ between the serving loop and one query per launch", file=sys.stderr)
+            sys.exit(1)
+        full = {"requests": args.full_requests, "max_edges_4var": inputs.FULL_MAX_EDGES,
+                "saturation": {"serving_loop": fsat_srv, "one_query_per_launch": fsat_base,
+                               "speedup": round(fsat_srv["queries_per_s"] / max(fsat_base["queries_per_s"], 1e-9), 3)},
+                "open_loop_at_0.8x": {"serving_loop": fo_srv, "one_query_per_launch": fo_base}}
     main_run = open_runs["serving_loop_at_0.8x"]
     out = {
         "metric": "served queries/s (saturation) with p50/p99 latency at 0.8x the one-query-per-launch "
@@ -323,6 +349,7 @@ def bench_serve(args):
         "saturation": {"serving_loop": sat_srv, "one_query_per_launch": sat_base,
                        "speedup": round(sat_srv["queries_per_s"] / max(qps_sat, 1e-9), 3)},
         "open_loop": open_runs,
+        "full_queries": full,
         "roofline": None,
     }
     eng.close()
@@ -563,6 +590,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=200.0, help="served workload: HBM admission budget")
     ap.add_argument("--max-weight", type=float, default=2e6,
                     help="served workload: work proxy a fused pass may carry (0: unlimited)")
+    ap.add_argument("--full-requests", type=int, default=400,
+                    help="served workload: requests of the full-query stream (0: none)")
     ap.add_argument("--saturation-only", action="store_true",
                     help="served workload: only the closed-loop saturation runs")
     ap.add_argument("--tensor-scale", type=int, default=1,

@@ -434,6 +434,7 @@ constexpr int kWin = 1024;      // LDS window per wave (elements)
 constexpr int kSub = 4;         // 64-element chunks per cursor step
 constexpr int kTiny = 48;       // counting modes: entries shorter than this take the per-lane path
 constexpr uint64_t kChunk = 4096;       // elements per work-queue chunk (one queue atomic each)
+constexpr uint64_t kMinChunk = 256;     // smallest chunk, for launches with few elements
 constexpr int kXcd = 8;                 // XCDs of an MI355X
 constexpr uint64_t kPersistBlocks = 2048;   // 8 workgroups of 4 waves per CU: 8 waves per SIMD
 
@@ -720,7 +721,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                                                    const uint64_t* __restrict__ prefix, int64_t e_begin,
                                                    int64_t e_end, uint64_t item_begin, uint64_t n_items,
                                                    const int64_t* __restrict__ chunk_entry,
-                                                   unsigned long long* queue, uint64_t n_chunks,
+                                                   unsigned long long* queue, uint64_t n_chunks, uint32_t chunk_sz,
                                                    uint64_t* __restrict__ words, unsigned long long* acc,
                                                    const uint64_t* __restrict__ wprefix, MatOut out) {
     constexpr bool kMat = mat_mode(MODE);
@@ -769,12 +770,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         if (uni(stop)) break;
         const uint64_t c = c_lo + uni64(t);
         if (c >= c_hi) break;
-        const uint64_t r_begin = c * kChunk;
+        const uint64_t r_begin = c * chunk_sz;
         // Positions inside the chunk are 32-bit offsets from its first item (uniform
         // 64-bit compares would cost vector instructions); so are the bounds of the
         // current entry, [lo_rel, hi_rel), the upper one clamped far beyond the chunk.
         const uint64_t base = item_begin + r_begin;
-        const uint32_t n_c = (uint32_t)(r_begin + kChunk < n_items ? kChunk : n_items - r_begin);
+        const uint32_t n_c = (uint32_t)(r_begin + chunk_sz < n_items ? chunk_sz : n_items - r_begin);
         // current entry and its wave-uniform description
         int64_t e = sload(chunk_entry + c);
         int32_t lo_rel;
@@ -1274,10 +1275,10 @@ __global__ void k_first_write(KData D, KStep S, const int32_t* __restrict__ F, c
 }
 
 __global__ void k_chunk_entries(const uint64_t* __restrict__ prefix, int64_t e_begin, int64_t e_end,
-                                uint64_t item_begin, uint64_t n_chunks, int64_t* __restrict__ out) {
+                                uint64_t item_begin, uint64_t n_chunks, uint64_t chunk_sz, int64_t* __restrict__ out) {
     for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_chunks;
          t += (uint64_t)gridDim.x * blockDim.x)
-        out[t] = find_entry(prefix, e_begin, e_end, item_begin + t * kChunk);
+        out[t] = find_entry(prefix, e_begin, e_end, item_begin + t * chunk_sz);
 }
 
 template <int MODE>
@@ -1309,7 +1310,12 @@ static void launch_probe(const Alloc& A, const KData& D, const KStep& S, const i
         HC_HIP(hipGetLastError());
         return;
     }
-    const uint64_t n_chunks = (n_items + kChunk - 1) / kChunk;
+    // Chunks of kChunk elements; a launch with fewer elements than the persistent grid
+    // has waves takes smaller chunks (down to kMinChunk), so that its waves all get
+    // work instead of a few walking long chunks one after another.
+    uint64_t chunk_sz = kChunk;
+    while (chunk_sz > kMinChunk && n_items / chunk_sz < kPersistBlocks * kWaves) chunk_sz >>= 1;
+    const uint64_t n_chunks = (n_items + chunk_sz - 1) / chunk_sz;
     DevBuf<int64_t> ce(A, (size_t)n_chunks + 1);
     DevBuf<unsigned long long> q(A, kXcd);
     HC_HIP(hipMemsetAsync(q.p, 0, sizeof(unsigned long long) * kXcd, s));
@@ -1317,7 +1323,7 @@ static void launch_probe(const Alloc& A, const KData& D, const KStep& S, const i
         int64_t g = (int64_t)((n_chunks + kBlock - 1) / kBlock);
         if (g < 1) g = 1;
         if (g > 16384) g = 16384;
-        k_chunk_entries<<<(unsigned)g, kBlock, 0, s>>>(prefix, e_begin, e_end, item_begin, n_chunks, ce.p);
+        k_chunk_entries<<<(unsigned)g, kBlock, 0, s>>>(prefix, e_begin, e_end, item_begin, n_chunks, chunk_sz, ce.p);
         HC_HIP(hipGetLastError());
     }
     // persistent grid: a multiple of 8 workgroups (every XCD queue has consumers)
@@ -1328,10 +1334,12 @@ static void launch_probe(const Alloc& A, const KData& D, const KStep& S, const i
     if (S.search == SEARCH_WINDOW)                                                                            \
         k_probe2<MODE, N, 0><<<(unsigned)blocks, kBlock, 0, s>>>(D, S, F, G, prefix, e_begin, e_end,         \
                                                                  item_begin, n_items, ce.p, q.p, n_chunks,    \
+                                                                 (uint32_t)chunk_sz,                          \
                                                                  words, acc, wprefix, out);                   \
     else                                                                                                      \
         k_probe2<MODE, N, 1><<<(unsigned)blocks, kBlock, 0, s>>>(D, S, F, G, prefix, e_begin, e_end,         \
                                                                  item_begin, n_items, ce.p, q.p, n_chunks,    \
+                                                                 (uint32_t)chunk_sz,                          \
                                                                  words, acc, wprefix, out)
     switch (S.n_ops) {
         case 1: HC_PROBE2(1); break;
@@ -2202,7 +2210,8 @@ uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, co
             bytes += (citems / 64 + 1) * 16.0;   // match words of a chunk
             bytes += citems * 4.0 * L.n_ops;     // positions of the bitmap pass
         }
-        bytes += (items / 2048 + 1) * 8.0 + 64.0;                                  // work-queue chunk table
+        // work-queue chunk table: chunks of 4096 elements, or at most 16384 smaller ones
+        bytes += (std::max(items / 2048.0, 16384.0) + 1) * 8.0 + 64.0;
         E = std::min(E * m, 1e18);
         chunk = std::max(kCap, m);
     }

@@ -328,6 +328,34 @@ def serve_stream(graph_specs, n_requests: int = 20000, qps: float = 2000.0, seed
     return out
 
 
+FULL_SALT = 0x4655_4C4C_5155_4552   # separates the full-query stream from the id-block stream
+FULL_MAX_EDGES = 150000             # 4-cycle and 4-clique full counts only on graphs this small
+
+
+def serve_full_stream(graph_specs, n_requests: int = 400, qps: float = 50.0, seed: int = SEED_SERVE,
+                      max_edges: int = FULL_MAX_EDGES):
+    """Full-query requests over the resident graphs, in arrival order: request i draws
+    3 numbers from stream seed ^ FULL_SALT (draws 3i .. 3i+2): the Poisson gap, the
+    shape (50% triangle, 30% 4-cycle, 20% 4-clique) and the graph -- uniform over all
+    graphs for triangles, over the graphs of at most max_edges undirected edges for
+    the 4-variable shapes (their full outputs reach 10^9 and more tuples on the larger
+    graphs).  Each request counts the query's whole output on its graph."""
+    r = splitmix64(seed ^ FULL_SALT, 0, 3 * n_requests).reshape(n_requests, 3)
+    u = _unit_double(r.reshape(-1)).reshape(n_requests, 3)
+    t = np.cumsum(-np.log1p(-u[:, 0]) / qps)
+    cum = np.cumsum([p for _, p in SERVE_MIX])
+    small = [s["g"] for s in graph_specs if s["m"] <= max_edges]
+    out = []
+    for i in range(n_requests):
+        k = int(np.searchsorted(cum, u[i, 1], side="right"))
+        shape = SERVE_MIX[min(k, len(SERVE_MIX) - 1)][0]
+        pool = list(range(len(graph_specs))) if shape == "triangle" else small
+        g = pool[min(int(u[i, 2] * len(pool)), len(pool) - 1)]
+        out.append({"id": i, "t": float(t[i]), "query": shape, "graph": g, "lo": 0,
+                    "hi": graph_specs[g]["n"], "full": True})
+    return out
+
+
 # ---------------------------------------------------------------- tensor workloads
 SEED_TENSOR = 0x4843_3000_0000
 TENSOR_U = (0, 1)   # first-attribute domain of the clover-triangle relations (reading of a garbled passage)

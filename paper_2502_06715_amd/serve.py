@@ -1,8 +1,9 @@
 """Serving join queries over resident CoCo indexes, with continuous batching.
 
 A request asks for the count of one query shape (triangle, 4-cycle, 4-clique)
-over one resident graph, restricted to a block of ids of the query's first
-variable.  The server:
+over one resident graph, either restricted to a block of ids of the query's
+first variable or whole (a full query: the id block is the graph's whole id
+range).  The server:
 
 * keeps one symmetric CoCo per graph resident in HBM (built once, reused by
   every request and every atom of every shape);
@@ -55,6 +56,7 @@ class Request:
     count: Optional[int] = None
     error: Optional[str] = None
     batch: int = 0                # size of the pass that answered it
+    full: bool = False            # the whole query on its graph (not an id block)
     done: threading.Event = field(default_factory=threading.Event, repr=False)
 
 
@@ -304,5 +306,6 @@ def summarize(requests: List[Request], wall_s: float) -> Dict:
 
 
 def requests_from_stream(stream) -> List[Request]:
-    return [Request(id=s["id"], graph=s["graph"], query=s["query"], lo=s["lo"], hi=s["hi"], t_arrival=s["t"])
+    return [Request(id=s["id"], graph=s["graph"], query=s["query"], lo=s["lo"], hi=s["hi"], t_arrival=s["t"],
+                    full=bool(s.get("full", False)))
             for s in stream]

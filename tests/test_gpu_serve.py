@@ -136,3 +136,35 @@ def test_batch_ranges_must_stay_in_one_segment(ctx):
     got = hc.join_count_multi(ctx, q, [c] * 3, [0, 1, 2], [(0, 1 << mb), (1 << mb, 2 << mb)])
     assert [int(x) for x in got] == [6 * oracle.textbook_triangles(g) for g in gs]
     c.free()
+
+
+def test_full_queries_in_the_mix_equal_alone(ctx):
+    """Full-query requests (the whole query on a resident graph) served together with
+    id-block requests of the same shapes, concurrently and fused: each answer equals
+    the same request alone and the oracle's full count."""
+    specs = inputs.serve_graph_specs(n_graphs=3, log2_lo=11.0, log2_hi=13.0)
+    graphs = [inputs.serve_graph(s) for s in specs]
+    blocks = inputs.serve_stream(specs, 200, qps=20000.0, seed=inputs.SEED_SERVE + 98)
+    fulls = inputs.serve_full_stream(specs, 30, qps=20000.0, seed=inputs.SEED_SERVE + 97, max_edges=6000)
+    assert {f["query"] for f in fulls} == {"triangle", "cycle4", "clique4"}
+    stream = sorted(blocks + [dict(f, id=1000 + f["id"]) for f in fulls], key=lambda r: r["t"])
+    eng = serve.GpuEngine(graphs, n_slots=3, shared_index=True)
+    ref = serve.GpuEngine(graphs, n_slots=1)
+    srv = serve.Server(eng, budget_bytes=16 << 30, n_slots=3, max_batch=64)
+    reqs = serve.requests_from_stream(stream)
+    wall = serve.replay(srv, reqs)
+    summ = serve.summarize(reqs, wall)
+    log("served with full queries: %s" % summ)
+    assert summ["answered"] == len(reqs)
+    full_exp = {}
+    for r in reqs:
+        assert r.count == ref.run(0, ref.group_key(r), [r], fused=False)[0], r
+        if r.full:
+            key = (r.graph, r.query)
+            if key not in full_exp:
+                n, atoms = inputs.QUERIES[r.query]
+                full_exp[key] = oracle.gj(n, atoms, [graphs[r.graph]] * len(atoms)).count
+            assert r.count == full_exp[key], r
+    assert sum(r.full for r in reqs) == 30
+    ref.close()
+    eng.close()

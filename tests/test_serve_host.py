@@ -7,7 +7,7 @@ import time
 import numpy as np
 import pytest
 
-from paper_2502_06715_amd import serve
+from paper_2502_06715_amd import inputs, serve
 
 
 class FakeEngine:
@@ -136,3 +136,24 @@ def test_weight_budget_keeps_heavy_requests_apart():
         assert w <= 10.0 or len(ranges) == 1
     assert any(ranges == [(0, 100)] for _, _, ranges, _ in eng.passes)
     assert all(r.count == r.lo * 7 + r.hi for r in reqs)
+
+
+def test_full_query_stream_shapes_and_graphs():
+    """Full-query requests cover the whole id range of their graph; triangles go to
+    any graph, 4-cycles and 4-cliques only to graphs of at most max_edges edges; the
+    stream is a pure function of its seed."""
+    specs = inputs.serve_graph_specs()
+    a = inputs.serve_full_stream(specs, 300, qps=40.0)
+    assert a == inputs.serve_full_stream(specs, 300, qps=40.0)
+    small = {s["g"] for s in specs if s["m"] <= inputs.FULL_MAX_EDGES}
+    assert small and len(small) < len(specs)
+    shapes = set()
+    for r in a:
+        assert r["full"] and r["lo"] == 0 and r["hi"] == specs[r["graph"]]["n"]
+        shapes.add(r["query"])
+        if r["query"] != "triangle":
+            assert r["graph"] in small
+    assert shapes == {"triangle", "cycle4", "clique4"}
+    assert {r["graph"] for r in a if r["query"] == "triangle"} - small
+    t = [r["t"] for r in a]
+    assert all(x < y for x, y in zip(t, t[1:]))
