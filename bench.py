@@ -121,11 +121,13 @@ def cpu_baseline(E, n_vars, atoms, full_count, budget_s=15.0, budget_1t=5.0):
 
 def bench_batch(args):
     """Batched workload: 4096 independent triangle / 4-cycle queries, each on its own
-    ER or R-MAT graph with log-uniform 2^10..2^18 edges.  A step builds one segmented
-    CoCo per query shape over the union of that shape's graphs and runs one fused
-    count per shape; the per-query counts are checked against the oracle's.  The
-    one-query-per-launch baseline (build, shares, count per query) runs on the same
-    queries and device."""
+    ER or R-MAT graph with log-uniform 2^10..2^18 edges.  The queries are grouped by
+    shape and size class (batch.size_class: the log2 of their edge count); a step
+    builds one segmented CoCo per group over the union of its graphs and runs one
+    fused count per group, with the extra split and the search method the autotuner
+    picked for that group; the per-query counts are checked against the oracle's.
+    The one-query-per-launch baseline (build, shares, count per query) runs on the
+    same queries and device."""
     import torch
     from paper_2502_06715_amd import batch, hc, inputs
 
@@ -140,32 +142,37 @@ def bench_batch(args):
     shapes = ["triangle", "cycle4"]
     groups = {}
     for shape in shapes:
-        idx = np.array([i for i, s in enumerate(specs) if s["query"] == shape], dtype=np.int64)
-        gs = [graphs[i] for i in idx]
-        mb = batch.id_bits(gs)
-        rel, seg = batch.union_relation(gs, mb)
-        groups[shape] = dict(idx=idx, mb=mb, seg=seg, rel=torch.from_numpy(rel).to(dev), n=len(gs))
+        for cls in range(len(batch.SIZE_CLASSES) + 1):
+            idx = np.array([i for i, s in enumerate(specs)
+                            if s["query"] == shape and batch.size_class(s["m"]) == cls], dtype=np.int64)
+            if idx.size == 0:
+                continue
+            gs = [graphs[i] for i in idx]
+            mb = batch.id_bits(gs)
+            rel, seg = batch.union_relation(gs, mb)
+            groups[(shape, cls)] = dict(idx=idx, mb=mb, seg=seg, rel=torch.from_numpy(rel).to(dev), n=len(gs))
     torch.cuda.synchronize()
-    # the autotuner times candidates on every 8th query of each shape
+    # the autotuner times its candidates on every 8th query of each group
     tune = batch.Autotune()
-    for shape, g in groups.items():
+    for key, g in groups.items():
+        shape = key[0]
         sub = [graphs[i] for i in g["idx"][::8]]
         srel, sseg = batch.union_relation(sub, g["mb"])
         sdev = torch.from_numpy(srel).to(dev)
         c = hc.build_coco(ctx, sdev, [0, 1], key_bits=g["mb"], segment_bits=sseg, symmetric=True)
-        tune.pick(shape, lambda x, m: batch.count_batched(ctx, shape, sdev, len(sub), g["mb"], sseg,
-                                                          extra_bits=x, coco=c, method=m))
+        tune.pick(key, lambda x, m: batch.count_batched(ctx, shape, sdev, len(sub), g["mb"], sseg,
+                                                        extra_bits=x, coco=c, method=m))
         c.free()
         del sdev
-        g["extra"], g["method"] = tune.choice[shape]
-        print("# autotune %s: extra split bits %d, search %s (timings %s)"
-              % (shape, g["extra"], g["method"],
-                 {"%d/%s" % k[1]: round(v, 3) for k, v in tune.timings.items() if k[0] == shape}),
+        g["extra"], g["method"] = tune.choice[key]
+        print("# autotune %s class %d (%d queries): extra split bits %d, search %s (timings %s)"
+              % (shape, key[1], g["n"], g["extra"], g["method"],
+                 {"%d/%s" % k[1]: round(v, 4) for k, v in tune.timings.items() if k[0] == key}),
               file=sys.stderr, flush=True)
 
     def step():
         got = np.zeros(len(specs), dtype=np.uint64)
-        for shape, g in groups.items():
+        for (shape, _), g in groups.items():
             got[g["idx"]] = batch.count_batched(ctx, shape, g["rel"], g["n"], g["mb"], g["seg"],
                                                 extra_bits=g["extra"], method=g["method"])
         return got
@@ -188,7 +195,7 @@ def bench_batch(args):
     torch.cuda.synchronize()
     seq = np.zeros(len(specs), dtype=np.uint64)
     t2 = time.perf_counter()
-    for shape, g in groups.items():
+    for (shape, _), g in groups.items():
         seq[g["idx"]] = batch.count_sequential(ctx, shape, [per_dev[i] for i in g["idx"]])
     torch.cuda.synchronize()
     ms_seq = 1000.0 * (time.perf_counter() - t2)
@@ -211,10 +218,11 @@ def bench_batch(args):
         "data": "synthetic",
         "config": {"workload": "4096 independent triangle / 4-cycle queries, each on its own Erdos-Renyi or "
                                "R-MAT graph, undirected edges log-uniform in [2^10, 2^18], int32 ids",
-                   "queries": {s: int(g["n"]) for s, g in groups.items()},
+                   "size_classes_log2_edges": list(batch.SIZE_CLASSES),
+                   "queries": {"%s/%d" % k: int(g["n"]) for k, g in groups.items()},
                    "tuples": int(sum(g["rel"].shape[0] for g in groups.values())),
-                   "extra_split_bits": {s: int(g["extra"]) for s, g in groups.items()},
-                   "search": {s: g["method"] for s, g in groups.items()}},
+                   "extra_split_bits": {"%s/%d" % k: int(g["extra"]) for k, g in groups.items()},
+                   "search": {"%s/%d" % k: g["method"] for k, g in groups.items()}},
         "one_query_per_launch": {"value": nq / (ms_seq / 1000.0), "unit": "queries/s",
                                  "ms_total": round(ms_seq, 3)},
         "speedup_vs_one_query_per_launch": round(ms_seq / ms_batched, 3),

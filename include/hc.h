@@ -317,6 +317,22 @@ hc_status hc_join_count_cells(hc_ctx* ctx, const hc_query* q, const hc_coco* con
                               uint64_t* cell_counts, uint64_t* count_out);
 
 /*
+ * Count per segment of segmented CoCos (the batched workload: one independent
+ * query per segment, all fused into one join; Section 5's cells partition the
+ * output, so a segment's cells add up to its query's count).  The first variable
+ * of the order takes the share segment_bits + log2_extra (every segment split into
+ * 2^log2_extra cells, the per-query split the batch autotuner chooses), the others
+ * none; the per-cell counts are summed per segment on the device.
+ *   segment_counts  host, 2^segment_bits entries: the count of each segment
+ *   count_out       host: the total
+ * Errors: HC_ERR_INVALID (CoCos not segmented, segment_bits + log2_extra > 24, bad
+ * query or order); otherwise as hc_join_count.
+ */
+hc_status hc_join_count_segments(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
+                                 const int32_t* var_order, int32_t log2_extra, uint32_t flags,
+                                 uint64_t* segment_counts, uint64_t* count_out);
+
+/*
  * Many instances of one query in one pass (the served workload fuses the
  * queued requests of one shape over one resident CoCo set): instance t is q
  * with its first variable (var_order[0]) restricted to raw ids in
@@ -395,9 +411,10 @@ hc_status hc_ctx_set_profiling(hc_ctx* ctx, int on);
  * Cancel request (for callers that bound a request's time, e.g. a serving loop):
  * on != 0 raises it, on = 0 withdraws it.  While it is raised, every join call on
  * this context returns HC_ERR_CANCELLED: a call already running notices it
- * between its launches and inside the intersection kernels, whose waves read
- * the request (a word of pinned host memory the context owns) every 64 work
- * chunks and leave; the call's outputs are then unspecified.  Safe to call from
+ * between its launches and inside the intersection kernels, where the wave that
+ * takes every 64th work chunk reads the request (a word of pinned host memory the
+ * context owns) and, finding it raised, empties the work queues so that every
+ * wave leaves at its next chunk; the call's outputs are then unspecified.  Safe to call from
  * another thread while a join runs on ctx: it is a plain store, no stream
  * operation.  Errors: HC_ERR_INVALID (NULL ctx).
  */

@@ -1,7 +1,7 @@
 """Batched execution of many small join queries.
 
-All queries of one shape (triangle or 4-cycle) are fused into a single Generic
-Join: their graphs become one relation whose ids carry the query number above
+The queries of one shape (triangle or 4-cycle) and size class are fused into a
+single Generic Join: their graphs become one relation whose ids carry the query number above
 the vertex bits (a segmented CoCo, see hc_build_coco_segmented), the first
 variable's share is the query number, so every query is one HyperCube cell (or
 2^extra cells), and the per-cell counts of hc_join_count_cells are the per-query
@@ -34,17 +34,31 @@ def union_relation(graphs, mix_bits: int):
     return rel, seg_bits
 
 
+# Size classes of the batched queries: class c holds the queries whose edge count is
+# below 2^SIZE_CLASSES[c] (and at least the previous bound); the last class the rest.
+SIZE_CLASSES = (12, 14, 16)
+
+
+def size_class(m: int) -> int:
+    """Size class of a query with m undirected edges."""
+    for c, lg in enumerate(SIZE_CLASSES):
+        if m < (1 << lg):
+            return c
+    return len(SIZE_CLASSES)
+
+
 def id_bits(graphs) -> int:
     mx = max((int(g.max()) for g in graphs if g.shape[0]), default=1)
     return max(1, mx.bit_length())
 
 
 class Autotune:
-    """Measured choice of a batch's launch parameters, cached per batch signature:
-    the extra split of every query's first variable (2^extra cells per query) and
-    the search method of the intersections (the LDS windows or one of Section 5's
-    per-element methods).  Coordinate descent: the split is timed with the
-    default method, then the methods with the chosen split."""
+    """Measured choice of a batch's launch parameters, cached per batch signature
+    (a shape and size class of queries): the extra split of every query's first
+    variable (its share: 2^extra cells per query) and the search method of the
+    intersections (the LDS windows or one of Section 5's per-element methods).
+    Coordinate descent: the split is timed with the default method, then the
+    methods with the chosen split."""
 
     def __init__(self, splits=(0, 1, 2, 3), methods=("window", "exponential", "by_size")):
         self.splits = tuple(splits)
@@ -80,14 +94,11 @@ def count_batched(ctx: hc.Context, shape: str, rel_dev, n_queries: int, mix_bits
     own = coco is None
     if own:
         coco = hc.build_coco(ctx, rel_dev, [0, 1], key_bits=mix_bits, segment_bits=seg_bits, symmetric=True)
-    order = list(range(n))
-    shares = [0] * n
-    shares[order[0]] = seg_bits + extra_bits
-    cells, _ = hc.join_count_cells(ctx, hc.Query(n, atoms), [coco] * len(atoms), order, shares,
-                                   flags=hc.SEARCH_METHODS[method])
+    # one segment per query: the library sums each query's 2^extra_bits cells
+    per_query, _ = hc.join_count_segments(ctx, hc.Query(n, atoms), [coco] * len(atoms), list(range(n)),
+                                          extra_bits, flags=hc.SEARCH_METHODS[method])
     if own:
         coco.free()
-    per_query = cells.reshape(-1, 1 << extra_bits).sum(axis=1)
     return per_query[:n_queries]
 
 

@@ -424,6 +424,27 @@ hc_status hc_join_count_cells(hc_ctx* ctx, const hc_query* q, const hc_coco* con
     });
 }
 
+hc_status hc_join_count_segments(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
+                                 const int32_t* var_order, int32_t log2_extra, uint32_t flags,
+                                 uint64_t* segment_counts, uint64_t* count_out) {
+    if (!ctx) return HC_ERR_INVALID;
+    return guarded(ctx, [&] {
+        check_query_ptrs(q);
+        HC_REQUIRE(atom_index && var_order && segment_counts && count_out, HC_ERR_INVALID, "NULL argument");
+        check_flags(flags, kJoinFlags, "hc_join_count_segments");
+        HC_REQUIRE(atom_index[0] != nullptr, HC_ERR_INVALID, "atom CoCo handle is NULL");
+        const int seg = atom_index[0]->key_bits - atom_index[0]->mix_bits;
+        HC_REQUIRE(seg >= 1, HC_ERR_INVALID, "hc_join_count_segments needs segmented CoCos");
+        HC_REQUIRE(log2_extra >= 0 && seg + log2_extra <= 24, HC_ERR_INVALID, "log2_extra out of range");
+        HC_REQUIRE(var_order[0] >= 0 && var_order[0] < q->n_vars, HC_ERR_INVALID, "bad var_order");
+        std::vector<int32_t> shares((size_t)q->n_vars, 0);
+        shares[(size_t)var_order[0]] = seg + log2_extra;
+        // the cell id is the first variable's coordinate (segment above the extra split)
+        hc::join_run(ctx, q, atom_index, var_order, shares.data(), flags, false, count_out, nullptr, nullptr, 0,
+                     nullptr, segment_counts, 0, nullptr, nullptr, 0, log2_extra);
+    });
+}
+
 hc_status hc_join_workspace_bound(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
                                   const int32_t* var_order, const int32_t* log2_shares, uint32_t flags,
                                   int64_t n_queries, int64_t first_width, uint64_t* bytes_out) {

@@ -257,12 +257,13 @@ double plan_cost(const hc_query* q, const std::vector<AtomStats>& st, const int3
 // emit chunk below F_0 (a single entry larger than the cap still goes whole).
 constexpr int64_t kDefaultCap = (int64_t)1 << 27;
 // alloc: where the call's device buffers come from (null: the context's allocator);
-// cap_entries: the chunking cap (0: kDefaultCap).
+// cap_entries: the chunking cap (0: kDefaultCap); cell_group: cell_counts holds one
+// count per group of 2^cell_group consecutive cells.
 void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
               const int32_t* shares, uint32_t flags, bool emit, uint64_t* count, uint64_t* digest,
               void* out, int64_t capacity, int64_t* n_out, uint64_t* cell_counts = nullptr,
               int64_t n_multi = 0, const int64_t* multi_ranges = nullptr, const Alloc* alloc = nullptr,
-              int64_t cap_entries = 0);
+              int64_t cap_entries = 0, int cell_group = 0);
 uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
                               const int32_t* shares, uint32_t flags, int64_t n_queries, int64_t first_width,
                               int64_t cap_entries = kDefaultCap);

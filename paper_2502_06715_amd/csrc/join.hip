@@ -52,6 +52,7 @@ struct KData {
     int32_t b;
     int32_t dtype64;
     const int* cancel;   // nonzero: the caller cancelled the call (polled between work chunks)
+    int32_t cell_group;  // per-cell counts are accumulated per group of 2^cell_group consecutive cells
 };
 
 struct KOp {
@@ -339,7 +340,8 @@ __global__ __launch_bounds__(kBlock) void k_probe(KData D, KStep S, const int32_
             if (lane == 0) words[w] = bal;
         } else {
             cnt += (uint64_t)__popcll(bal);
-            if (MODE == M_CELLS) cell_add_lanes(cells, ca, P.found, P.found ? (uint32_t)F[P.e * S.W_in] : 0u, lane);
+            if (MODE == M_CELLS)
+                cell_add_lanes(cells, ca, P.found, P.found ? (uint32_t)F[P.e * S.W_in] >> D.cell_group : 0u, lane);
             if (MODE == M_DIGEST && P.found) {
                 const int32_t* ent = F + P.e * S.W_in;
                 uint64_t h = 0x6A09E667F3BCC909ull;
@@ -758,14 +760,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
     }
     const int xcd = (int)(blockIdx.x % kXcd);
     const uint64_t c_lo = n_chunks * (uint64_t)xcd / kXcd, c_hi = n_chunks * (uint64_t)(xcd + 1) / kXcd;
-    int polls = 0;
     for (;;) {
         unsigned long long t = 0;
         int stop = 0;
         if (lane == 0) {
             t = atomicAdd(&queue[xcd], 1ull);
-            // the cancel word is host memory: read it every 64th chunk
-            if ((polls++ & 63) == 0) stop = __atomic_load_n(D.cancel, __ATOMIC_RELAXED);
+            // The cancel word is host memory: the wave that takes every 64th chunk of an
+            // XCD's queue reads it (a small launch reads it a few times, not once per
+            // wave).  A wave that finds it raised pushes every queue 2^40 chunks on, so
+            // that all waves leave at their next claim.
+            if ((t & 63) == 0 && __atomic_load_n(D.cancel, __ATOMIC_RELAXED)) {
+                stop = 1;
+                for (int x = 0; x < kXcd; ++x) atomicAdd(&queue[x], 1ull << 40);
+            }
         }
         if (uni(stop)) break;
         const uint64_t c = c_lo + uni64(t);
@@ -1085,7 +1092,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                         cnt += (uint64_t)__popcll(bal);
                         if (MODE == M_DIGEST && hit) digest_add<MODE>(D, S, F + e * S.W_in, a[k], dsum, dxor);
                         if (MODE == M_CELLS)
-                            cell_add(out.cells, ca, (uint32_t)uni(F[e * S.W_in]), (uint64_t)__popcll(bal), lane);
+                            cell_add(out.cells, ca, (uint32_t)uni(F[e * S.W_in]) >> D.cell_group,
+                                     (uint64_t)__popcll(bal), lane);
                     }
                 }
                 rc += n_sc;
@@ -1180,7 +1188,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                     cnt += (uint64_t)__popcll(bal);
                     if (MODE == M_DIGEST && found) digest_add<MODE>(D, S, F + my_e * S.W_in, av, dsum, dxor);
                     if (MODE == M_CELLS)
-                        cell_add_lanes(out.cells, ca, found, found ? (uint32_t)F[my_e * S.W_in] : 0u, lane);
+                        cell_add_lanes(out.cells, ca, found, found ? (uint32_t)F[my_e * S.W_in] >> D.cell_group : 0u,
+                                       lane);
                 }
                 // continue inside the last entry touched (its cursors restart)
                 e = e_hi;
@@ -1311,8 +1320,9 @@ static void launch_probe(const Alloc& A, const KData& D, const KStep& S, const i
         return;
     }
     // Chunks of kChunk elements; a launch with fewer elements than the persistent grid
-    // has waves takes smaller chunks (down to kMinChunk), so that its waves all get
-    // work instead of a few walking long chunks one after another.
+    // has waves takes smaller chunks (down to kMinChunk; chunk starts stay on
+    // match-word boundaries), so that its waves all get work instead of a few walking
+    // long chunks one after another.
     uint64_t chunk_sz = kChunk;
     while (chunk_sz > kMinChunk && n_items / chunk_sz < kPersistBlocks * kWaves) chunk_sz >>= 1;
     const uint64_t n_chunks = (n_items + chunk_sz - 1) / chunk_sz;
@@ -1907,7 +1917,7 @@ void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
 void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order, const int32_t* shares,
               uint32_t flags, bool emit, uint64_t* count, uint64_t* digest, void* out, int64_t capacity,
               int64_t* n_out, uint64_t* cell_counts, int64_t n_multi, const int64_t* multi_ranges,
-              const Alloc* alloc, int64_t cap_entries) {
+              const Alloc* alloc, int64_t cap_entries, int cell_group) {
     Runner R(ctx, alloc ? *alloc : ctx->alloc);
     // A batch of queries has one F_0 entry per query: an intersection of whole top
     // levels lifted to F_0 would be recomputed for every query, so it is not lifted.
@@ -2049,11 +2059,16 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
     }
     // F_0: one entry per cell (per query of a batch)
     const int64_t ncell = n_multi > 0 ? n_multi : (int64_t)1 << K;
+    // per-cell counters, one per group of 2^cell_group consecutive cells
+    HC_REQUIRE(cell_group >= 0 && (n_multi > 0 ? cell_group == 0 : cell_group <= K), HC_ERR_INVALID,
+               "cell groups larger than the cells");
+    R.D.cell_group = cell_group;
+    const int64_t ngroup = ncell >> cell_group;
     DevBuf<unsigned long long> cells;
     if (cell_counts) {
         HC_REQUIRE(!emit, HC_ERR_INVALID, "per-cell counts are a counting mode");
-        cells = DevBuf<unsigned long long>(R.A, (size_t)ncell);
-        HC_HIP(hipMemsetAsync(cells.p, 0, sizeof(unsigned long long) * ncell, R.s));
+        cells = DevBuf<unsigned long long>(R.A, (size_t)ngroup);
+        HC_HIP(hipMemsetAsync(cells.p, 0, sizeof(unsigned long long) * ngroup, R.s));
         R.cell_out = cells.p;
     }
     DevBuf<int32_t> F0(R.A, (size_t)ncell * (size_t)R.lay[0].W);
@@ -2098,7 +2113,7 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
     unsigned long long a[3] = {0, 0, 0};
     HC_HIP(hipMemcpyAsync(a, R.acc.p, sizeof(a), hipMemcpyDeviceToHost, R.s));
     if (cell_counts)
-        HC_HIP(hipMemcpyAsync(cell_counts, cells.p, sizeof(unsigned long long) * ncell, hipMemcpyDeviceToHost, R.s));
+        HC_HIP(hipMemcpyAsync(cell_counts, cells.p, sizeof(unsigned long long) * ngroup, hipMemcpyDeviceToHost, R.s));
     HC_HIP(hipStreamSynchronize(R.s));
     R.check_cancel();   // a kernel may have left early
     if (emit) {
@@ -2210,7 +2225,7 @@ uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, co
             bytes += (citems / 64 + 1) * 16.0;   // match words of a chunk
             bytes += citems * 4.0 * L.n_ops;     // positions of the bitmap pass
         }
-        // work-queue chunk table: chunks of 4096 elements, or at most 16384 smaller ones
+        // work-queue chunk table: chunks of 4096 elements, or fewer than 16384 smaller ones
         bytes += (std::max(items / 2048.0, 16384.0) + 1) * 8.0 + 64.0;
         E = std::min(E * m, 1e18);
         chunk = std::max(kCap, m);

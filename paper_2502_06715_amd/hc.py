@@ -88,6 +88,7 @@ SIGNATURES = {
     "hc_join_emit": (ctypes.c_int, [P, P, P, P, P, U32, P, I64, P]),
     "hc_join_count_cells": (ctypes.c_int, [P, P, P, P, P, U32, P, P]),
     "hc_join_count_noalloc": (ctypes.c_int, [P, P, P, P, P, U32, P, P, P]),
+    "hc_join_count_segments": (ctypes.c_int, [P, P, P, P, I32, U32, P, P]),
     "hc_join_workspace_bound": (ctypes.c_int, [P, P, P, P, P, U32, I64, I64, P]),
     "hc_join_count_multi": (ctypes.c_int, [P, P, P, P, U32, I64, P, P]),
     "hc_plan_describe": (ctypes.c_int, [P, P, U32, P, ctypes.c_size_t]),
@@ -356,6 +357,20 @@ def join_count_cells(ctx: Context, q: Query, cocos, order, log2_shares, flags: i
     ctx.check(lib().hc_join_count_cells(ctx.h, ctypes.byref(qc), _handles(cocos), order_a.ctypes.data,
                                         sh.ctypes.data, flags, cells.ctypes.data, ctypes.byref(cnt)))
     return cells, int(cnt.value)
+
+
+def join_count_segments(ctx: Context, q: Query, cocos, order, log2_extra: int = 0, flags: int = 0):
+    """Per-segment counts (numpy uint64, 2^segment_bits entries) of segmented CoCos, and
+    the total; the first variable of the order is split into 2^log2_extra cells per
+    segment."""
+    order_a = _i32(order)
+    seg = int(cocos[0].info.key_bits - cocos[0].info.mix_bits)
+    counts = np.zeros(1 << seg, dtype=np.uint64)
+    cnt = ctypes.c_uint64(0)
+    qc = q.c()
+    ctx.check(lib().hc_join_count_segments(ctx.h, ctypes.byref(qc), _handles(cocos), order_a.ctypes.data,
+                                           int(log2_extra), flags, counts.ctypes.data, ctypes.byref(cnt)))
+    return counts, int(cnt.value)
 
 
 def join_workspace_bound(ctx: Context, q: Query, cocos, order, log2_shares=None, flags: int = 0,

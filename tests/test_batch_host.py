@@ -27,3 +27,14 @@ def test_autotune_picks_fastest_and_caches():
     n = len(calls)
     assert t.pick("cycle4", run) == (2, "by_size") and len(calls) == n   # cached
     assert n == 4 + 3
+
+
+def test_size_classes_cover_the_batch():
+    from paper_2502_06715_amd import batch, inputs
+    specs = inputs.batch_spec(512)
+    cls = [batch.size_class(s["m"]) for s in specs]
+    assert set(cls) == set(range(len(batch.SIZE_CLASSES) + 1))
+    for s, c in zip(specs, cls):
+        lo = 0 if c == 0 else 1 << batch.SIZE_CLASSES[c - 1]
+        hi = 1 << batch.SIZE_CLASSES[c] if c < len(batch.SIZE_CLASSES) else 1 << 62
+        assert lo <= s["m"] < hi
