@@ -76,34 +76,31 @@ def _workload(cfg):
     return desc, spec["n"].bit_length() - 1, "clique4"
 
 
-def _sample_run(E, n_vars, atoms, full_count, budget_s, threads):
-    """The oracle on a bounded sample: sort once, then Generic Join over randomly
-    chosen blocks of first-variable ids until budget_s of join time is spent."""
+def _sample_run(E, n_vars, atoms, full_count, budget_s, threads, stride):
+    """The oracle on a bounded sample: sort once, then Generic Join over the first
+    variable's values of every stride-th rank (phase after phase, each one parallel
+    loop with the whole job's mix of light and heavy values) until budget_s of join
+    time is spent."""
     from oracle import oracle
-    nid = int(E.max()) + 1
-    nblk = 1024
-    width = (nid + nblk - 1) // nblk
-    perm = np.random.default_rng(0x4843).permutation(nblk)
-    ranges = [(int(b) * width, int(b + 1) * width) for b in perm]
-    sort_s, done = oracle.gj_sample(n_vars, atoms, [E] * len(atoms), ranges, budget_s, threads=threads)
-    cnt = sum(d[2] for d in done)
-    js = sum(d[3] for d in done)
+    sort_s, done = oracle.gj_strided(n_vars, atoms, [E] * len(atoms), stride, budget_s, threads=threads)
+    cnt = sum(d[1] for d in done)
+    js = sum(d[2] for d in done)
     frac = cnt / full_count if full_count else 0.0
-    return sort_s, js, len(done), nblk, frac
+    return sort_s, js, len(done), frac
 
 
 def cpu_baseline(E, n_vars, atoms, full_count, budget_s=15.0, budget_1t=5.0):
     """The oracle on this host's cores (its OpenMP threads = the host threads this
-    process may use, at most 16), on a bounded sample of the workload; the job's
-    output rate is the sample's tuples over the sample's sort + join time.  A
-    one-thread sample is timed beside it.  (The full job at the same thread count is
-    measured once and recorded with the design notes: it takes minutes.)"""
+    process may use, at most 16), on a bounded sample of the workload: the job's
+    rate is the full count over the sort plus the sample's join time scaled by its
+    share of the output.  A one-thread sample is timed beside it.  (The whole job
+    at the same thread count is timed by `bench.py --cpu-full`: about a minute.)"""
     threads = _host_threads()
-    sort_s, js, nb, nblk, frac = _sample_run(E, n_vars, atoms, full_count, budget_s, threads)
-    # sample output rate: the sampled blocks' tuples per second of their join time, the
-    # sort of the whole input charged in proportion to the sampled fraction
+    stride = 32
+    sort_s, js, nph, frac = _sample_run(E, n_vars, atoms, full_count, budget_s, threads, stride)
     t_job = sort_s + (js / frac if frac > 0 else float("inf"))
-    s1, j1, nb1, _, f1 = _sample_run(E, n_vars, atoms, full_count, budget_1t, 1)
+    stride1 = 256
+    s1, j1, nph1, f1 = _sample_run(E, n_vars, atoms, full_count, budget_1t, 1, stride1)
     t1 = s1 + (j1 / f1 if f1 > 0 else float("inf"))
     return {
         "value": full_count / t_job if t_job > 0 else 0.0,
@@ -113,9 +110,10 @@ def cpu_baseline(E, n_vars, atoms, full_count, budget_s=15.0, budget_1t=5.0):
         "cpu_model": _cpu_model(),
         "one_thread_value": full_count / t1 if t1 > 0 else 0.0,
         "sample": ("oracle (C, OpenMP, %d threads) sort+dedup of every atom (%.1f s), then Generic Join over "
-                   "%d of %d random first-variable id blocks (%.1f s, %.2f%% of the output): %.1f s per "
-                   "full job at that rate; one thread: %d blocks, %.2f%% of the output, %.1f s per full job"
-                   % (threads, sort_s, nb, nblk, js, 100 * frac, t_job, nb1, 100 * f1, t1)),
+                   "%d of %d strided phases of the first variable's values (%.1f s, %.2f%% of the output): "
+                   "%.1f s per full job at that rate; one thread: %d of %d phases, %.2f%% of the output, %.1f s "
+                   "per full job" % (threads, sort_s, nph, stride, js, 100 * frac, t_job, nph1, stride1,
+                                     100 * f1, t1)),
     }
 
 
@@ -252,7 +250,7 @@ def bench_serve(args):
     print("# generated %d graphs (%d tuples) in %.1f s" % (len(graphs), sum(g.shape[0] for g in graphs),
                                                         time.time() - t0), file=sys.stderr, flush=True)
     base_eng = serve.GpuEngine(graphs, n_slots=1)
-    eng = serve.GpuEngine(graphs, n_slots=args.slots, shared_index=True)
+    eng = serve.GpuEngine(graphs, n_slots=args.slots, shared_index=True, grid_share=args.grid_share)
     torch.cuda.synchronize()
     print("# resident CoCos: %.2f GB per graph, %.2f GB shared" % (base_eng.index_bytes / 1e9, eng.index_bytes / 1e9),
           file=sys.stderr, flush=True)
@@ -351,7 +349,8 @@ def bench_serve(args):
         "config": {"workload": "Poisson stream of %d requests, 50%% triangle / 30%% 4-cycle / 20%% 4-clique, over "
                                "16 resident R-MAT graphs with 2^16..2^24 undirected edges (int32), first-variable "
                                "blocks of 1..16 ids, HBM admission budget %.0f GB" % (args.requests, args.budget_gb),
-                   "slots": args.slots, "resident_index_gb": round(eng.index_bytes / 1e9, 3),
+                   "slots": args.slots, "grid_share": args.grid_share,
+                   "resident_index_gb": round(eng.index_bytes / 1e9, 3),
                    "max_weight": args.max_weight,
                    "saturation_requests": n_sat},
         "saturation": {"serving_loop": sat_srv, "one_query_per_launch": sat_base,
@@ -598,6 +597,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=200.0, help="served workload: HBM admission budget")
     ap.add_argument("--max-weight", type=float, default=2e6,
                     help="served workload: work proxy a fused pass may carry (0: unlimited)")
+    ap.add_argument("--grid-share", type=float, default=0.5,
+                    help="served workload: share of the default persistent grid each slot may use (0: all)")
     ap.add_argument("--full-requests", type=int, default=400,
                     help="served workload: requests of the full-query stream (0: none)")
     ap.add_argument("--saturation-only", action="store_true",

@@ -408,6 +408,16 @@ typedef struct {
 hc_status hc_ctx_set_profiling(hc_ctx* ctx, int on);
 
 /*
+ * Device share of the context's calls (for callers that run several calls at once
+ * on one GPU, e.g. the slots of a serving loop): the persistent intersection
+ * kernels launch at most max_workgroups workgroups (rounded down to a multiple of
+ * 8, at least 8) instead of 8 per compute unit, so that a long call does not hold
+ * every compute unit while others wait.  0 restores the default.  Results do not
+ * depend on it.  Errors: HC_ERR_INVALID (NULL ctx, negative limit).
+ */
+hc_status hc_ctx_set_grid_limit(hc_ctx* ctx, int32_t max_workgroups);
+
+/*
  * Cancel request (for callers that bound a request's time, e.g. a serving loop):
  * on != 0 raises it, on = 0 withdraws it.  While it is raised, every join call on
  * this context returns HC_ERR_CANCELLED: a call already running notices it

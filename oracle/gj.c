@@ -485,6 +485,86 @@ int64_t oracle_gj_sample(int n_vars, int n_atoms, const int* arity, const int* a
     return k;
 }
 
+/*
+ * Timed strided sample for the CPU baseline: sort once, then for phase = 0, 1, ...
+ * run Generic Join on the level-0 runs whose index is congruent to the phase modulo
+ * `stride` (one parallel loop over them, so every phase has the whole job's mix of
+ * light and heavy values and its parallelism), until the join time reaches
+ * budget_s or all phases are done.  Writes per-phase counts and seconds; returns
+ * the number of phases run (or -1).  *sort_s receives the sort + dedup time.
+ */
+int64_t oracle_gj_strided(int n_vars, int n_atoms, const int* arity, const int* atom_vars,
+                          const int64_t* const* rel, const int64_t* rows, const int* order,
+                          int64_t stride, double budget_s, uint64_t* counts, double* secs, double* sort_s,
+                          int nthreads) {
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    if (stride < 1) return -1;
+    double t0 = now_s();
+    oq_state s;
+    if (prepare(&s, n_vars, n_atoms, arity, atom_vars, rel, rows, order) != 0) return -1;
+    oq_level0 L;
+    level0_runs(&s, &L);
+    *sort_s = now_s() - t0;
+    /* the runs of one phase, as a run-start table of their own */
+    oq_level0 P;
+    P.best = L.best;
+    P.starts = (int64_t*)malloc(sizeof(int64_t) * (size_t)(2 * (L.nruns / stride + 2)));
+    double spent = 0;
+    int64_t k = 0;
+    for (; k < stride && spent < budget_s; ++k) {
+        double t1 = now_s();
+        uint64_t tc = 0, ts = 0, tx = 0, tw[OQ_MAX_VARS] = {0};
+        int64_t out_pos = 0;
+        /* run_runs walks consecutive runs [i, i+1) of a start table: build one whose
+           run j is the original run phase + j * stride */
+        int64_t nr = 0;
+        for (int64_t r = k; r < L.nruns; r += stride) {
+            P.starts[2 * nr] = L.starts[r];
+            P.starts[2 * nr + 1] = L.starts[r + 1];
+            ++nr;
+        }
+        tc = 0;
+#pragma omp parallel
+        {
+            oq_frame f;
+            memset(&f, 0, sizeof(f));
+            for (int j = 0; j < s.n_atoms; ++j) { f.lo[j] = 0; f.hi[j] = s.rel[j].rows; f.depth[j] = 0; }
+            f.out_pos = &out_pos;
+            const int na = s.n_ops[0];
+            const oq_rel* rb = &s.rel[s.ops[0][P.best]];
+#pragma omp for schedule(dynamic, 16)
+            for (int64_t j = 0; j < nr; ++j) {
+                int64_t r = P.starts[2 * j], r1 = P.starts[2 * j + 1];
+                int64_t v = rb->t[r * rb->k];
+                int64_t nlo[OQ_MAX_ATOMS], nhi[OQ_MAX_ATOMS];
+                int ok = 1;
+                for (int q = 0; q < na && ok; ++q) {
+                    int a = s.ops[0][q];
+                    if (q == P.best) { nlo[q] = r; nhi[q] = r1; continue; }
+                    const oq_rel* ra = &s.rel[a];
+                    int64_t e0 = lower_row(ra, 0, 0, ra->rows, v);
+                    int64_t e1 = upper_row(ra, 0, e0, ra->rows, v);
+                    if (e0 == e1) ok = 0;
+                    nlo[q] = e0; nhi[q] = e1;
+                }
+                if (ok) bind_and_recurse(&s, &f, 0, v, nlo, nhi);
+            }
+#pragma omp critical
+            { tc += f.count; ts += f.dsum; tx ^= f.dxor; }
+        }
+        (void)tw;
+        counts[k] = tc;
+        secs[k] = now_s() - t1;
+        spent += secs[k];
+    }
+    free(P.starts);
+    free(L.starts);
+    free_state(&s);
+    return k;
+}
+
 /* Digest of an explicit list of head-order tuples (so tests can digest brute-force
  * or chunked outputs with the same definition). */
 void oracle_digest_rows(const int64_t* t, int64_t rows, int n, uint64_t* digest) {

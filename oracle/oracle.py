@@ -44,6 +44,9 @@ def lib():
         L.oracle_gj_sample.restype = ctypes.c_int64
         L.oracle_gj_sample.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, ctypes.c_int64, P, P,
                                        ctypes.c_double, P, P, P, ctypes.c_int]
+        L.oracle_gj_strided.restype = ctypes.c_int64
+        L.oracle_gj_strided.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, ctypes.c_int64,
+                                        ctypes.c_double, P, P, P, ctypes.c_int]
         L.oracle_digest_rows.restype = None
         L.oracle_digest_rows.argtypes = [P, ctypes.c_int64, ctypes.c_int, P]
         L.textbook_triangles.restype = ctypes.c_int64
@@ -166,6 +169,28 @@ def gj_sample(n_vars: int, atoms, relations, ranges, budget_s: float, order=None
     if k < 0:
         raise ValueError("invalid query")
     return float(sort_s[0]), [(int(lo[i]), int(hi[i]), int(counts[i]), float(secs[i])) for i in range(k)]
+
+
+def gj_strided(n_vars: int, atoms, relations, stride: int, budget_s: float, order=None, threads: int = 0):
+    """Sort once, then count the first variable's values of every stride-th rank
+    (phase 0, then 1, ...) until budget_s seconds of join time; each phase runs as
+    one parallel loop.  Returns (sort_seconds, [(phase, count, seconds), ...])."""
+    L = lib()
+    order = list(range(n_vars)) if order is None else list(order)
+    arity = np.array([len(a) for a in atoms], dtype=np.int32)
+    avars = np.array([v for a in atoms for v in a], dtype=np.int32)
+    rels = _as_int64(relations, atoms)
+    rows = np.array([r.shape[0] for r in rels], dtype=np.int64)
+    ptrs = (ctypes.c_void_p * len(rels))(*[r.ctypes.data for r in rels])
+    ordr = np.array(order, dtype=np.int32)
+    counts = np.zeros(stride, dtype=np.uint64)
+    secs = np.zeros(stride, dtype=np.float64)
+    sort_s = np.zeros(1, dtype=np.float64)
+    k = L.oracle_gj_strided(n_vars, len(atoms), _ptr(arity), _ptr(avars), ptrs, _ptr(rows), _ptr(ordr), stride,
+                            budget_s, _ptr(counts), _ptr(secs), _ptr(sort_s), threads)
+    if k < 0:
+        raise ValueError("invalid query")
+    return float(sort_s[0]), [(i, int(counts[i]), float(secs[i])) for i in range(k)]
 
 
 def digest_rows(rows: np.ndarray) -> tuple:

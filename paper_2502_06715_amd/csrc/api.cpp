@@ -519,6 +519,12 @@ hc_status hc_plan_describe(const hc_query* q, const int32_t* var_order, uint32_t
     }
 }
 
+hc_status hc_ctx_set_grid_limit(hc_ctx* ctx, int32_t max_workgroups) {
+    if (!ctx || max_workgroups < 0) return HC_ERR_INVALID;
+    ctx->grid_limit = max_workgroups;
+    return HC_OK;
+}
+
 hc_status hc_ctx_set_profiling(hc_ctx* ctx, int on) {
     if (!ctx) return HC_ERR_INVALID;
     ctx->profiling = on ? 1 : 0;

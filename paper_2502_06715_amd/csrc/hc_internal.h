@@ -141,6 +141,7 @@ struct hc_ctx {
     int profiling = 0;
     hc_timing timing{};
     int num_cus = 256;
+    int grid_limit = 0;                    // workgroups of a persistent launch at most (0: default)
     std::atomic<int> cancel{0};            // cancel request (host view)
     int* h_cancel = nullptr;               // the same request in coherent pinned host memory,
     int* d_cancel = nullptr;               // read by kernels through this device address

@@ -53,6 +53,7 @@ struct KData {
     int32_t dtype64;
     const int* cancel;   // nonzero: the caller cancelled the call (polled between work chunks)
     int32_t cell_group;  // per-cell counts are accumulated per group of 2^cell_group consecutive cells
+    int32_t grid_limit;  // host only: workgroups of a persistent launch at most (0: kPersistBlocks)
 };
 
 struct KOp {
@@ -1323,8 +1324,12 @@ static void launch_probe(const Alloc& A, const KData& D, const KStep& S, const i
     // has waves takes smaller chunks (down to kMinChunk; chunk starts stay on
     // match-word boundaries), so that its waves all get work instead of a few walking
     // long chunks one after another.
+    // the persistent grid: 8 workgroups per CU, or the context's limit (a multiple of
+    // the 8 XCDs, so that every XCD queue has consumers)
+    const uint64_t max_blocks = D.grid_limit > 0 ? std::max<uint64_t>(kXcd, (uint64_t)D.grid_limit / kXcd * kXcd)
+                                                 : kPersistBlocks;
     uint64_t chunk_sz = kChunk;
-    while (chunk_sz > kMinChunk && n_items / chunk_sz < kPersistBlocks * kWaves) chunk_sz >>= 1;
+    while (chunk_sz > kMinChunk && n_items / chunk_sz < max_blocks * kWaves) chunk_sz >>= 1;
     const uint64_t n_chunks = (n_items + chunk_sz - 1) / chunk_sz;
     DevBuf<int64_t> ce(A, (size_t)n_chunks + 1);
     DevBuf<unsigned long long> q(A, kXcd);
@@ -1338,7 +1343,7 @@ static void launch_probe(const Alloc& A, const KData& D, const KStep& S, const i
     }
     // persistent grid: a multiple of 8 workgroups (every XCD queue has consumers)
     uint64_t blocks = (n_chunks + kWaves - 1) / kWaves;
-    if (blocks > kPersistBlocks) blocks = kPersistBlocks;
+    if (blocks > max_blocks) blocks = max_blocks;
     blocks = ((blocks + kXcd - 1) / kXcd) * kXcd;
 #define HC_PROBE2(N)                                                                                          \
     if (S.search == SEARCH_WINDOW)                                                                            \
@@ -2010,6 +2015,7 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
     R.D.mix = make_mixer(mb, seed, b);
     R.D.b = b;
     R.D.cancel = ctx->d_cancel;
+    R.D.grid_limit = ctx->grid_limit;
     R.D.dtype64 = dtype64;
     R.emit = emit;
     R.digest = digest != nullptr;

@@ -94,6 +94,7 @@ SIGNATURES = {
     "hc_plan_describe": (ctypes.c_int, [P, P, U32, P, ctypes.c_size_t]),
     "hc_plan_cost_from_info": (ctypes.c_int, [P, P, P, P, U32, P, P]),
     "hc_ctx_set_profiling": (ctypes.c_int, [P, ctypes.c_int]),
+    "hc_ctx_set_grid_limit": (ctypes.c_int, [P, I32]),
     "hc_ctx_cancel": (ctypes.c_int, [P, I32]),
     "hc_ctx_get_timing": (ctypes.c_int, [P, P]),
 }
@@ -202,6 +203,11 @@ class Context:
         st = lib().hc_ctx_cancel(self.h, 1 if on else 0)
         if st != HC_OK:
             raise HCError(st, "hc_ctx_cancel failed")
+
+    def set_grid_limit(self, max_workgroups: int):
+        """Persistent kernels of this context launch at most max_workgroups workgroups
+        (0: the default, 8 per compute unit)."""
+        self.check(lib().hc_ctx_set_grid_limit(self.h, int(max_workgroups)))
 
     def set_profiling(self, on: bool):
         lib().hc_ctx_set_profiling(self.h, 1 if on else 0)

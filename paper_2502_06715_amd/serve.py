@@ -69,7 +69,10 @@ class GpuEngine:
     fuse into one pass; otherwise each graph has its own CoCo and a pass covers one
     (graph, shape)."""
 
-    def __init__(self, graphs: List[np.ndarray], n_slots: int, device: int = 0, shared_index: bool = False):
+    def __init__(self, graphs: List[np.ndarray], n_slots: int, device: int = 0, shared_index: bool = False,
+                 grid_share: float = 0.0):
+        """grid_share in (0, 1]: each slot's persistent kernels use at most that share of
+        the default grid, leaving compute units free for the passes of other slots."""
         import torch
         from . import batch, hc
         self.hc = hc
@@ -78,6 +81,10 @@ class GpuEngine:
         # default-priority streams, one per slot
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(max(1, n_slots))]
         self.ctxs = [hc.Context(device, stream=s) for s in self.streams]
+        if grid_share > 0:
+            n_cu = torch.cuda.get_device_properties(self.dev).multi_processor_count
+            for c in self.ctxs:
+                c.set_grid_limit(max(8, int(8 * n_cu * grid_share)))
         self.est_ctx = hc.Context(device, stream=self.streams[0])   # estimates run under the scheduler lock
         self.cocos = []
         self.index_bytes = 0

@@ -168,3 +168,22 @@ def test_full_queries_in_the_mix_equal_alone(ctx):
     assert sum(r.full for r in reqs) == 30
     ref.close()
     eng.close()
+
+
+def test_grid_limit_keeps_results(ctx, graph):
+    """A context whose persistent kernels use at most a few workgroups (a serving
+    slot's device share) gets the same counts as the default grid."""
+    import torch
+    c = hc.build_coco(ctx, torch.from_numpy(graph).to("cuda:0"), [0, 1], symmetric=True)
+    small = hc.Context(0)
+    for name in ["triangle", "clique4"]:
+        n, atoms = inputs.QUERIES[name]
+        q = hc.Query(n, atoms)
+        exp = hc.join_count(ctx, q, [c] * len(atoms), list(range(n)), [1] * n)
+        for lim in [8, 64, 1000]:
+            small.set_grid_limit(lim)
+            assert hc.join_count(small, q, [c] * len(atoms), list(range(n)), [1] * n) == exp
+        small.set_grid_limit(0)
+    with pytest.raises(hc.HCError):
+        small.set_grid_limit(-1)
+    c.free()

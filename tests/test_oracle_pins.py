@@ -378,3 +378,15 @@ def test_gj_sample_blocks_sum_to_the_count():
     for lo, hi, cnt, _ in done[:12]:
         big = 1 << 40
         assert cnt == oracle.gj(n, atoms, [E] * 3, lo=[lo, 0, 0], hi=[hi, big, big]).count
+
+
+def test_gj_strided_phases_sum_to_the_count():
+    """The strided CPU-baseline sampler: the phases of a stride partition the first
+    variable's values, so their counts add up to the Generic Join count."""
+    n, atoms = Q["clique4"]
+    E = inputs.chung_lu(1024, 6000, 45)
+    full = oracle.gj(n, atoms, [E] * 6).count
+    _, done = oracle.gj_strided(n, atoms, [E] * 6, stride=7, budget_s=1e9, threads=2)
+    assert len(done) == 7 and sum(d[1] for d in done) == full
+    _, one = oracle.gj_strided(n, atoms, [E] * 6, stride=1, budget_s=1e9, threads=2)
+    assert one[0][1] == full
