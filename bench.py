@@ -76,32 +76,26 @@ def _workload(cfg):
     return desc, spec["n"].bit_length() - 1, "clique4"
 
 
-def _sample_run(E, n_vars, atoms, full_count, budget_s, threads, stride):
-    """The oracle on a bounded sample: sort once, then Generic Join over the first
-    variable's values of every stride-th rank (phase after phase, each one parallel
-    loop with the whole job's mix of light and heavy values) until budget_s of join
-    time is spent."""
-    from oracle import oracle
-    sort_s, done = oracle.gj_strided(n_vars, atoms, [E] * len(atoms), stride, budget_s, threads=threads)
-    cnt = sum(d[1] for d in done)
-    js = sum(d[2] for d in done)
-    frac = cnt / full_count if full_count else 0.0
-    return sort_s, js, len(done), frac
-
-
-def cpu_baseline(E, n_vars, atoms, full_count, budget_s=15.0, budget_1t=5.0):
+def cpu_baseline(E, n_vars, atoms, full_count, budget_s=15.0, budget_1t=5.0, seed=1):
     """The oracle on this host's cores (its OpenMP threads = the host threads this
-    process may use, at most 16), on a bounded sample of the workload: the job's
-    rate is the full count over the sort plus the sample's join time scaled by its
-    share of the output.  A one-thread sample is timed beside it.  (The whole job
-    at the same thread count is timed by `bench.py --cpu-full`: about a minute.)"""
+    process may use, at most 16), on a bounded sample of the workload: sort once, then
+    Generic Join over the first variable's values in a seeded random order (so the
+    sample is a uniform one of the values, with the whole job's mix of light and heavy
+    ones) as one parallel loop that takes no new value after budget_s seconds.  The
+    job's time is the sort plus the loop's busy thread-seconds over the thread count,
+    scaled by the sample's share of the output (a thread still in a heavy value at the
+    deadline finishes it alone; its busy time counts that value, the wall time would
+    count it for every thread).  A one-thread sample is timed beside it.
+    (`bench.py --cpu-full` times the whole job at the same thread count: about a
+    minute.)"""
+    from oracle import oracle
     threads = _host_threads()
-    stride = 32
-    sort_s, js, nph, frac = _sample_run(E, n_vars, atoms, full_count, budget_s, threads, stride)
-    t_job = sort_s + (js / frac if frac > 0 else float("inf"))
-    stride1 = 256
-    s1, j1, nph1, f1 = _sample_run(E, n_vars, atoms, full_count, budget_1t, 1, stride1)
-    t1 = s1 + (j1 / f1 if f1 > 0 else float("inf"))
+    r = oracle.gj_timed(n_vars, atoms, [E] * len(atoms), budget_s, seed=seed, threads=threads)
+    frac = r["count"] / full_count if full_count else 0.0
+    t_job = r["sort_s"] + (r["busy"] / threads / frac if frac > 0 else float("inf"))
+    r1 = oracle.gj_timed(n_vars, atoms, [E] * len(atoms), budget_1t, seed=seed, threads=1)
+    f1 = r1["count"] / full_count if full_count else 0.0
+    t1 = r1["sort_s"] + (r1["busy"] / f1 if f1 > 0 else float("inf"))
     return {
         "value": full_count / t_job if t_job > 0 else 0.0,
         "unit": "tuples/s",
@@ -110,10 +104,10 @@ def cpu_baseline(E, n_vars, atoms, full_count, budget_s=15.0, budget_1t=5.0):
         "cpu_model": _cpu_model(),
         "one_thread_value": full_count / t1 if t1 > 0 else 0.0,
         "sample": ("oracle (C, OpenMP, %d threads) sort+dedup of every atom (%.1f s), then Generic Join over "
-                   "%d of %d strided phases of the first variable's values (%.1f s, %.2f%% of the output): "
-                   "%.1f s per full job at that rate; one thread: %d of %d phases, %.2f%% of the output, %.1f s "
-                   "per full job" % (threads, sort_s, nph, stride, js, 100 * frac, t_job, nph1, stride1,
-                                     100 * f1, t1)),
+                   "%d of %d first-variable values in seeded random order (%.1f s wall, %.1f busy thread-seconds, "
+                   "%.2f%% of the output): %.1f s per full job; one thread: %d values, %.2f%% of the output, "
+                   "%.1f s per full job" % (threads, r["sort_s"], r["runs_done"], r["runs"], r["wall"],
+                                            r["busy"], 100 * frac, t_job, r1["runs_done"], 100 * f1, t1)),
     }
 
 

@@ -445,15 +445,22 @@ static double now_s(void) {
 #endif
 
 /*
- * Timed sample for the CPU baseline: sort once, then run Generic Join on the
- * level-0 value ranges [lo[k], hi[k]) in the given order until the join time
- * reaches budget_s.  Writes per-range counts and seconds; returns the number of
- * ranges run (or -1).  *sort_s receives the preparation (sort + dedup) time.
+ * Timed sample for the CPU baseline: sort once, then run Generic Join on the level-0
+ * runs in a seeded random order (a Fisher-Yates shuffle driven by splitmix64, so any
+ * prefix is a uniform sample of the first variable's values; an order by value would
+ * follow the generator's id structure, e.g. R-MAT's heavy low-bit-zero ids) as ONE
+ * parallel loop, like the whole job, in which a thread takes no new run once budget_s
+ * seconds of join time have passed.  Heavy runs thus overlap with the others as they
+ * do in the whole job, and only the runs in flight at the deadline finish alone.
+ * Writes the count of the runs done, the loop's wall time, the busy thread-seconds
+ * (the sum over threads of the time from the loop's start to the end of their last
+ * run) and the number of runs done; returns the number of level-0 runs (or -1).
+ * *sort_s receives the sort + dedup time.
  */
-int64_t oracle_gj_sample(int n_vars, int n_atoms, const int* arity, const int* atom_vars,
-                         const int64_t* const* rel, const int64_t* rows, const int* order,
-                         int64_t n_ranges, const int64_t* lo, const int64_t* hi, double budget_s,
-                         uint64_t* counts, double* secs, double* sort_s, int nthreads) {
+int64_t oracle_gj_timed(int n_vars, int n_atoms, const int* arity, const int* atom_vars,
+                        const int64_t* const* rel, const int64_t* rows, const int* order,
+                        uint64_t seed, double budget_s, uint64_t* count, double* wall, double* busy,
+                        int64_t* runs_done, double* sort_s, int nthreads) {
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
@@ -463,106 +470,66 @@ int64_t oracle_gj_sample(int n_vars, int n_atoms, const int* arity, const int* a
     oq_level0 L;
     level0_runs(&s, &L);
     *sort_s = now_s() - t0;
-    const oq_rel* rb = &s.rel[s.ops[0][L.best]];
-    double spent = 0;
-    int64_t k = 0;
-    for (; k < n_ranges && spent < budget_s; ++k) {
-        double t1 = now_s();
-        /* runs whose value lies in [lo, hi) */
-        int64_t a = 0, z = L.nruns;
-        while (a < z) { int64_t m = (a + z) / 2; if (rb->t[L.starts[m] * rb->k] < lo[k]) a = m + 1; else z = m; }
-        int64_t b = a; z = L.nruns;
-        while (b < z) { int64_t m = (b + z) / 2; if (rb->t[L.starts[m] * rb->k] < hi[k]) b = m + 1; else z = m; }
-        uint64_t tc = 0, ts = 0, tx = 0, tw[OQ_MAX_VARS] = {0};
-        int64_t out_pos = 0;
-        run_runs(&s, &L, a, b, &tc, &ts, &tx, tw, &out_pos);
-        counts[k] = tc;
-        secs[k] = now_s() - t1;
-        spent += secs[k];
+    const int64_t nruns = L.nruns;
+    /* position j of the loop runs level-0 run perm[j] */
+    int64_t* perm = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nruns + 1));
+    for (int64_t j = 0; j < nruns; ++j) perm[j] = j;
+    uint64_t st = seed;
+    for (int64_t j = nruns - 1; j > 0; --j) {
+        st += 0x9E3779B97F4A7C15ull;                 /* splitmix64 step */
+        uint64_t k = (uint64_t)(((unsigned __int128)fmix64(st) * (uint64_t)(j + 1)) >> 64);
+        int64_t tmp = perm[j]; perm[j] = perm[k]; perm[k] = tmp;
     }
-    free(L.starts);
-    free_state(&s);
-    return k;
-}
-
-/*
- * Timed strided sample for the CPU baseline: sort once, then for phase = 0, 1, ...
- * run Generic Join on the level-0 runs whose index is congruent to the phase modulo
- * `stride` (one parallel loop over them, so every phase has the whole job's mix of
- * light and heavy values and its parallelism), until the join time reaches
- * budget_s or all phases are done.  Writes per-phase counts and seconds; returns
- * the number of phases run (or -1).  *sort_s receives the sort + dedup time.
- */
-int64_t oracle_gj_strided(int n_vars, int n_atoms, const int* arity, const int* atom_vars,
-                          const int64_t* const* rel, const int64_t* rows, const int* order,
-                          int64_t stride, double budget_s, uint64_t* counts, double* secs, double* sort_s,
-                          int nthreads) {
-#ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-#endif
-    if (stride < 1) return -1;
-    double t0 = now_s();
-    oq_state s;
-    if (prepare(&s, n_vars, n_atoms, arity, atom_vars, rel, rows, order) != 0) return -1;
-    oq_level0 L;
-    level0_runs(&s, &L);
-    *sort_s = now_s() - t0;
-    /* the runs of one phase, as a run-start table of their own */
-    oq_level0 P;
-    P.best = L.best;
-    P.starts = (int64_t*)malloc(sizeof(int64_t) * (size_t)(2 * (L.nruns / stride + 2)));
-    double spent = 0;
-    int64_t k = 0;
-    for (; k < stride && spent < budget_s; ++k) {
-        double t1 = now_s();
-        uint64_t tc = 0, ts = 0, tx = 0, tw[OQ_MAX_VARS] = {0};
-        int64_t out_pos = 0;
-        /* run_runs walks consecutive runs [i, i+1) of a start table: build one whose
-           run j is the original run phase + j * stride */
-        int64_t nr = 0;
-        for (int64_t r = k; r < L.nruns; r += stride) {
-            P.starts[2 * nr] = L.starts[r];
-            P.starts[2 * nr + 1] = L.starts[r + 1];
-            ++nr;
-        }
-        tc = 0;
+    uint64_t tc = 0;
+    double bsum = 0;
+    int64_t done = 0;
+    volatile int stop = 0;
+    double t1 = now_s();
+    const double deadline = t1 + budget_s;
 #pragma omp parallel
-        {
-            oq_frame f;
-            memset(&f, 0, sizeof(f));
-            for (int j = 0; j < s.n_atoms; ++j) { f.lo[j] = 0; f.hi[j] = s.rel[j].rows; f.depth[j] = 0; }
-            f.out_pos = &out_pos;
-            const int na = s.n_ops[0];
-            const oq_rel* rb = &s.rel[s.ops[0][P.best]];
-#pragma omp for schedule(dynamic, 16)
-            for (int64_t j = 0; j < nr; ++j) {
-                int64_t r = P.starts[2 * j], r1 = P.starts[2 * j + 1];
-                int64_t v = rb->t[r * rb->k];
-                int64_t nlo[OQ_MAX_ATOMS], nhi[OQ_MAX_ATOMS];
-                int ok = 1;
-                for (int q = 0; q < na && ok; ++q) {
-                    int a = s.ops[0][q];
-                    if (q == P.best) { nlo[q] = r; nhi[q] = r1; continue; }
-                    const oq_rel* ra = &s.rel[a];
-                    int64_t e0 = lower_row(ra, 0, 0, ra->rows, v);
-                    int64_t e1 = upper_row(ra, 0, e0, ra->rows, v);
-                    if (e0 == e1) ok = 0;
-                    nlo[q] = e0; nhi[q] = e1;
-                }
-                if (ok) bind_and_recurse(&s, &f, 0, v, nlo, nhi);
+    {
+        oq_frame f;
+        memset(&f, 0, sizeof(f));
+        for (int j = 0; j < s.n_atoms; ++j) { f.lo[j] = 0; f.hi[j] = s.rel[j].rows; f.depth[j] = 0; }
+        int64_t out_pos = 0;
+        f.out_pos = &out_pos;
+        const int na = s.n_ops[0];
+        const oq_rel* rb = &s.rel[s.ops[0][L.best]];
+        double t_last = t1;
+        int64_t my_done = 0;
+#pragma omp for schedule(dynamic, 16) nowait
+        for (int64_t j = 0; j < nruns; ++j) {
+            if (stop) continue;
+            int64_t run = perm[j];
+            int64_t r = L.starts[run], r1 = L.starts[run + 1];
+            int64_t v = rb->t[r * rb->k];
+            int64_t nlo[OQ_MAX_ATOMS], nhi[OQ_MAX_ATOMS];
+            int ok = 1;
+            for (int q = 0; q < na && ok; ++q) {
+                int a = s.ops[0][q];
+                if (q == L.best) { nlo[q] = r; nhi[q] = r1; continue; }
+                const oq_rel* ra = &s.rel[a];
+                int64_t e0 = lower_row(ra, 0, 0, ra->rows, v);
+                int64_t e1 = upper_row(ra, 0, e0, ra->rows, v);
+                if (e0 == e1) ok = 0;
+                nlo[q] = e0; nhi[q] = e1;
             }
-#pragma omp critical
-            { tc += f.count; ts += f.dsum; tx ^= f.dxor; }
+            if (ok) bind_and_recurse(&s, &f, 0, v, nlo, nhi);
+            ++my_done;
+            t_last = now_s();
+            if (t_last >= deadline) stop = 1;
         }
-        (void)tw;
-        counts[k] = tc;
-        secs[k] = now_s() - t1;
-        spent += secs[k];
+#pragma omp critical
+        { tc += f.count; bsum += t_last - t1; done += my_done; }
     }
-    free(P.starts);
+    *wall = now_s() - t1;
+    *count = tc;
+    *busy = bsum;
+    *runs_done = done;
+    free(perm);
     free(L.starts);
     free_state(&s);
-    return k;
+    return nruns;
 }
 
 /* Digest of an explicit list of head-order tuples (so tests can digest brute-force

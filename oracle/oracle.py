@@ -41,12 +41,9 @@ def lib():
         L.oracle_gj.restype = ctypes.c_int64
         L.oracle_gj.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P, P,
                                 ctypes.c_int64, P, P, ctypes.c_int]
-        L.oracle_gj_sample.restype = ctypes.c_int64
-        L.oracle_gj_sample.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, ctypes.c_int64, P, P,
-                                       ctypes.c_double, P, P, P, ctypes.c_int]
-        L.oracle_gj_strided.restype = ctypes.c_int64
-        L.oracle_gj_strided.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, ctypes.c_int64,
-                                        ctypes.c_double, P, P, P, ctypes.c_int]
+        L.oracle_gj_timed.restype = ctypes.c_int64
+        L.oracle_gj_timed.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, ctypes.c_uint64,
+                                      ctypes.c_double, P, P, P, P, P, ctypes.c_int]
         L.oracle_digest_rows.restype = None
         L.oracle_digest_rows.argtypes = [P, ctypes.c_int64, ctypes.c_int, P]
         L.textbook_triangles.restype = ctypes.c_int64
@@ -146,10 +143,11 @@ def gj(n_vars: int, atoms, relations, order=None, lo=None, hi=None, emit=False,
                   [int(x) for x in wk] if wk is not None else None)
 
 
-def gj_sample(n_vars: int, atoms, relations, ranges, budget_s: float, order=None, threads: int = 0):
-    """Sort once, then count the ranges (lo, hi) of the first variable of the order one
-    after the other until budget_s seconds of join time are spent.
-    Returns (sort_seconds, [(lo, hi, count, seconds), ...])."""
+def gj_timed(n_vars: int, atoms, relations, budget_s: float, seed: int = 1, order=None, threads: int = 0):
+    """Sort once, then run Generic Join over the first variable's values in a seeded
+    random order as one parallel loop that takes no new value once budget_s seconds
+    have passed.  Returns a dict with sort_s, count (of the values done), wall, busy
+    (thread-seconds), runs_done and runs."""
     L = lib()
     order = list(range(n_vars)) if order is None else list(order)
     arity = np.array([len(a) for a in atoms], dtype=np.int32)
@@ -158,39 +156,15 @@ def gj_sample(n_vars: int, atoms, relations, ranges, budget_s: float, order=None
     rows = np.array([r.shape[0] for r in rels], dtype=np.int64)
     ptrs = (ctypes.c_void_p * len(rels))(*[r.ctypes.data for r in rels])
     ordr = np.array(order, dtype=np.int32)
-    lo = np.array([r[0] for r in ranges], dtype=np.int64)
-    hi = np.array([r[1] for r in ranges], dtype=np.int64)
-    counts = np.zeros(len(ranges), dtype=np.uint64)
-    secs = np.zeros(len(ranges), dtype=np.float64)
-    sort_s = np.zeros(1, dtype=np.float64)
-    k = L.oracle_gj_sample(n_vars, len(atoms), _ptr(arity), _ptr(avars), ptrs, _ptr(rows), _ptr(ordr),
-                           len(ranges), _ptr(lo), _ptr(hi), budget_s, _ptr(counts), _ptr(secs), _ptr(sort_s),
-                           threads)
-    if k < 0:
+    count = np.zeros(1, dtype=np.uint64)
+    f = np.zeros(3, dtype=np.float64)            # wall, busy, sort
+    done = np.zeros(1, dtype=np.int64)
+    n = L.oracle_gj_timed(n_vars, len(atoms), _ptr(arity), _ptr(avars), ptrs, _ptr(rows), _ptr(ordr), seed,
+                          budget_s, _ptr(count), _ptr(f[0:1]), _ptr(f[1:2]), _ptr(done), _ptr(f[2:3]), threads)
+    if n < 0:
         raise ValueError("invalid query")
-    return float(sort_s[0]), [(int(lo[i]), int(hi[i]), int(counts[i]), float(secs[i])) for i in range(k)]
-
-
-def gj_strided(n_vars: int, atoms, relations, stride: int, budget_s: float, order=None, threads: int = 0):
-    """Sort once, then count the first variable's values of every stride-th rank
-    (phase 0, then 1, ...) until budget_s seconds of join time; each phase runs as
-    one parallel loop.  Returns (sort_seconds, [(phase, count, seconds), ...])."""
-    L = lib()
-    order = list(range(n_vars)) if order is None else list(order)
-    arity = np.array([len(a) for a in atoms], dtype=np.int32)
-    avars = np.array([v for a in atoms for v in a], dtype=np.int32)
-    rels = _as_int64(relations, atoms)
-    rows = np.array([r.shape[0] for r in rels], dtype=np.int64)
-    ptrs = (ctypes.c_void_p * len(rels))(*[r.ctypes.data for r in rels])
-    ordr = np.array(order, dtype=np.int32)
-    counts = np.zeros(stride, dtype=np.uint64)
-    secs = np.zeros(stride, dtype=np.float64)
-    sort_s = np.zeros(1, dtype=np.float64)
-    k = L.oracle_gj_strided(n_vars, len(atoms), _ptr(arity), _ptr(avars), ptrs, _ptr(rows), _ptr(ordr), stride,
-                            budget_s, _ptr(counts), _ptr(secs), _ptr(sort_s), threads)
-    if k < 0:
-        raise ValueError("invalid query")
-    return float(sort_s[0]), [(i, int(counts[i]), float(secs[i])) for i in range(k)]
+    return {"sort_s": float(f[2]), "count": int(count[0]), "wall": float(f[0]), "busy": float(f[1]),
+            "runs_done": int(done[0]), "runs": int(n)}
 
 
 def digest_rows(rows: np.ndarray) -> tuple:

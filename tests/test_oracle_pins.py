@@ -360,33 +360,23 @@ def test_cells_mode_equals_brute_force_partition(name, shares):
         assert int(got.sum()) == exp.shape[0]
 
 
-def test_gj_sample_blocks_sum_to_the_count():
-    """The CPU-baseline sampler: the counts of first-variable id blocks that cover the
-    domain add up to the Generic Join count, and each block's count equals Generic
-    Join under the same range predicate."""
-    n, atoms = Q["triangle"]
-    E = inputs.rmat(10, 6000, 44)
-    full = oracle.gj(n, atoms, [E] * 3).count
-    nid = int(E.max()) + 1
-    w = 37
-    ranges = [(a, a + w) for a in range(0, nid, w)]
-    perm = np.random.default_rng(1).permutation(len(ranges))
-    ranges = [ranges[i] for i in perm]
-    _, done = oracle.gj_sample(n, atoms, [E] * 3, ranges, budget_s=1e9, threads=2)
-    assert len(done) == len(ranges)
-    assert sum(d[2] for d in done) == full
-    for lo, hi, cnt, _ in done[:12]:
-        big = 1 << 40
-        assert cnt == oracle.gj(n, atoms, [E] * 3, lo=[lo, 0, 0], hi=[hi, big, big]).count
-
-
-def test_gj_strided_phases_sum_to_the_count():
-    """The strided CPU-baseline sampler: the phases of a stride partition the first
-    variable's values, so their counts add up to the Generic Join count."""
+def test_gj_timed_sample():
+    """The CPU-baseline sampler: with no deadline it runs every first-variable value
+    (the Generic Join count); with a zero deadline and one thread it runs exactly one
+    value, whose count is the number of result tuples with that first value; the
+    seeded order does not depend on the thread count."""
     n, atoms = Q["clique4"]
     E = inputs.chung_lu(1024, 6000, 45)
-    full = oracle.gj(n, atoms, [E] * 6).count
-    _, done = oracle.gj_strided(n, atoms, [E] * 6, stride=7, budget_s=1e9, threads=2)
-    assert len(done) == 7 and sum(d[1] for d in done) == full
-    _, one = oracle.gj_strided(n, atoms, [E] * 6, stride=1, budget_s=1e9, threads=2)
-    assert one[0][1] == full
+    res = oracle.gj(n, atoms, [E] * 6, emit=True)
+    full = res.count
+    r = oracle.gj_timed(n, atoms, [E] * 6, budget_s=1e9, seed=7, threads=2)
+    assert r["count"] == full and r["runs_done"] == r["runs"]
+    assert 0 <= r["busy"] <= 2 * r["wall"] + 1e-3
+    per_value = {int(v): int(c) for v, c in zip(*np.unique(res.rows[:, 0], return_counts=True))}
+    firsts = set()
+    for seed in range(1, 9):
+        one = oracle.gj_timed(n, atoms, [E] * 6, budget_s=0.0, seed=seed, threads=1)
+        assert one["runs_done"] == 1
+        firsts.add(one["count"])
+        assert one["count"] == 0 or one["count"] in per_value.values()
+    assert len(firsts) > 1                     # the seed changes the order
