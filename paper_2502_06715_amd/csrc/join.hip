@@ -625,6 +625,12 @@ __device__ inline void digest_add(const KData& D, const KStep& S, const int32_t*
 }
 
 __device__ inline int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+// Smallest power of two >= max(x, lo) (lo a power of two, x <= 2^30): a count of
+// leading zeros instead of a doubling loop.
+__device__ inline int32_t pow2_at_least(int32_t x, int32_t lo) {
+    return x <= lo ? lo : (int32_t)(1u << (32 - __builtin_clz((uint32_t)(x - 1))));
+}
+
 __device__ inline uint64_t uni64(uint64_t v) {
     return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(v >> 32)) << 32) |
            (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)v);
@@ -868,8 +874,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                 for (int k = 0; k < kSub; ++k) {
                     const int j = k * 64 + lane;
                     v[k] = j < nsc;
-                    const int rem = nsc - 64 * k;
-                    fm[k] = rem >= 64 ? ~0ull : (rem > 0 ? (1ull << rem) - 1 : 0ull);
+                    fm[k] = __ballot(v[k]);   // one vector compare, no scalar mask arithmetic
                     const uint32_t o4 = lane4 + 256u * k;
                     a[k] = *(const uint32_t*)((const char*)ab + (o4 < last4 ? o4 : last4));
 #pragma unroll
@@ -930,8 +935,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                         const int32_t base = beg[o] & ~3;
                         const int32_t sh = beg[o] - base;
                         const int32_t len_al = full + sh;
-                        int32_t p2 = 4;
-                        while (p2 < len_al) p2 <<= 1;
+                        const int32_t p2 = pow2_at_least(len_al, 4);
                         if (!(wc_ptr[o] == B && wc_beg[o] == beg[o] && wc_end[o] == end[o])) {
                             wave_sync();   // earlier searches of this region are done
                             stage_window(rw, B, base, sh, len_al, p2, lane);
@@ -960,11 +964,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                     // over about est = nsc * (rest of B) / (rest of the iterated list) elements
                     // from the cursor: that many, with a margin, are staged in LDS from the
                     // cursor without searching for the range's end, and the step searches
-                    // there.  When the estimate exceeds the region, or the staged window
-                    // ends below a_last (an overshoot), the range is found by two wave searches
-                    // from the cursor (the second starting with strides sized by est) and
-                    // staged when it fits; otherwise every s-th element is (fences), and each
-                    // value finishes with a search of its s-element bucket in place.
+                    // there.  When the estimate exceeds the region, every s-th element of the
+                    // estimated cover is staged instead (fences, s = cover / region), the step
+                    // searches the fences and each value finishes with a search of its
+                    // s-element bucket in place.  When the staged window or fences end below
+                    // a_last (an overshoot), the range is found by two wave searches from the
+                    // cursor (the second starting with strides sized by est) and staged when
+                    // it fits, else fenced.
 #pragma unroll
                     for (int u = 0; u < NOPS; ++u) wc_ptr[u] = nullptr;   // the window overwrites every region
                     const uint32_t a_first = sload(ab), a_last = sload(ab + last);
@@ -974,8 +980,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                         const int32_t sh0 = cur[o] - ws;
                         const uint32_t want = est + (est >> 2) + 32u + (uint32_t)sh0;
                         if (want <= (uint32_t)kWin) {
-                            int32_t P = 64;
-                            while ((uint32_t)P < want) P <<= 1;
+                            const int32_t P = pow2_at_least((int32_t)want, 64);
                             const bool to_end = ws + P >= end[o];
                             const int32_t len_al = to_end ? end[o] - ws : P;
                             if (!to_end)
@@ -1003,6 +1008,56 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                             wave_sync();
                         }
                     }
+                    if (est + (est >> 2) + 32u > (uint32_t)kWin) {
+                        // estimated fences: nf fences s apart from the cursor over the
+                        // estimated cover (capped at the list's end, where the last bucket
+                        // then reaches the end)
+                        const uint32_t left_b = (uint32_t)(end[o] - cur[o]);
+                        const uint32_t want = min(est + (est >> 2) + 32u, left_b);
+                        const bool capped = want == left_b;
+                        const int32_t sp = uni((int32_t)((want + (uint32_t)kWin - 1u) / (uint32_t)kWin));
+                        const int32_t nf = uni((int32_t)((want + (uint32_t)sp - 1u) / (uint32_t)sp));   // <= kWin
+                        const int32_t p2 = pow2_at_least(nf, 4);
+                        const int32_t c0 = cur[o], e_o = end[o];
+                        {   // fence loads first, then the LDS stores; (nf - 1) * sp < want <= end - cursor
+                            uint32_t fv[16];
+#pragma unroll
+                            for (int i = 0; i < 16; ++i) {
+                                const int q = lane + 64 * i;
+                                fv[i] = q < nf ? B[c0 + q * sp] : 0xFFFFFFFFu;
+                            }
+#pragma unroll
+                            for (int i = 0; i < 16; ++i)
+                                if (lane + 64 * i < p2) win[lane + 64 * i] = fv[i];
+                        }
+                        wave_sync();
+                        if (capped || (uint32_t)uni((int32_t)win[nf - 1]) >= a_last) {
+                            int32_t p[kSub];
+                            lds_search<kSub>(win, p2, a, p);   // p[k]: fences below the value (<= nf)
+#pragma unroll
+                            for (int k = 0; k < kSub; ++k) {
+                                int32_t q = c0;   // every value's lower bound is at or past the cursor
+                                if (v[k] && p[k] > 0) {
+                                    const int32_t l = c0 + (p[k] - 1) * sp + 1;
+                                    const int32_t r = c0 + p[k] * sp < e_o ? c0 + p[k] * sp : e_o;
+                                    q = lower_bound32(B, l, r, a[k]);
+                                }
+                                p[k] = q;
+                            }
+                            int32_t ql = c0;
+#pragma unroll
+                            for (int k = 0; k < kSub; ++k) {
+                                const int32_t qc = p[k] < e_o ? p[k] : e_o - 1;
+                                fm[k] &= __ballot(p[k] < e_o) & __ballot(B[qc] == a[k]);
+                                if (kPos) pos[o][k] = p[k];
+                                if (k == (last >> 6)) ql = __builtin_amdgcn_readlane(p[k], last & 63);
+                            }
+                            wave_sync();
+                            cur[o] = ql;   // lower bound of the step's last value
+                            continue;
+                        }
+                        wave_sync();
+                    }
                     const int32_t lo = uni(wave_search(B, cur[o], end[o], a_first, lane));
                     const int32_t hi = uni(wave_search_hint(B, lo, end[o], a_last, lane, est));
                     const int32_t cover = (hi < end[o] ? hi + 1 : end[o]) - lo;
@@ -1014,8 +1069,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                         const int32_t lo_al = lo & ~3;
                         const int32_t sh = lo - lo_al;
                         const int32_t len_al = cover + sh;
-                        int32_t p2 = 4;
-                        while (p2 < len_al) p2 <<= 1;
+                        const int32_t p2 = pow2_at_least(len_al, 4);
                         if (lo_al + p2 <= end[o])
                             stage_window_inlist(win, B, lo_al, sh, len_al, p2, lane);
                         else
@@ -1032,8 +1086,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                     } else {
                         const int32_t sp = (cover + (kWin - 4) - 1) / (kWin - 4);   // fence spacing
                         const int32_t nf = (cover + sp - 1) / sp;
-                        int32_t p2 = 4;
-                        while (p2 < nf) p2 <<= 1;
+                        const int32_t p2 = pow2_at_least(nf, 4);
                         {   // fence loads first, then the LDS stores (p2 <= 1024 = 16 x 64 lanes)
                             uint32_t fv[16];
 #pragma unroll
