@@ -654,8 +654,11 @@ __device__ inline void lds_level(int32_t p2, const uint32_t (&a)[KS], lds_cptr (
     for (int k = 0; k < KS; ++k) q[k] += x[k] < a[k] ? S : 0;
 }
 
+// p[k] is the lower bound of a[k] (p2 if every key is smaller) and x[k] the key at
+// min(p[k], p2 - 1): the key at the lower bound whenever it lies in the window.
 template <int KS>
-__device__ inline void lds_search(const uint32_t* w, int32_t p2, const uint32_t (&a)[KS], int32_t (&p)[KS]) {
+__device__ inline void lds_search(const uint32_t* w, int32_t p2, const uint32_t (&a)[KS], int32_t (&p)[KS],
+                                  uint32_t (&x)[KS]) {
     const lds_cptr w3 = (lds_cptr)w;
     lds_cptr q[KS];
 #pragma unroll
@@ -670,7 +673,6 @@ __device__ inline void lds_search(const uint32_t* w, int32_t p2, const uint32_t 
     lds_level<KS, 4>(p2, a, q);
     lds_level<KS, 2>(p2, a, q);
     lds_level<KS, 1>(p2, a, q);
-    uint32_t x[KS];
 #pragma unroll
     for (int k = 0; k < KS; ++k) x[k] = q[k][0];
 #pragma unroll
@@ -949,12 +951,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                             wc_end[o] = end[o];
                         }
                         int32_t p[kSub];
-                        lds_search<kSub>(rw, p2, a, p);
+                        uint32_t x[kSub];
+                        const uint32_t w_sh = rw[sh];   // the list's first key (off the search's path)
+                        lds_search<kSub>(rw, p2, a, p, x);
 #pragma unroll
                         for (int k = 0; k < kSub; ++k) {
-                            // slots below sh hold zeros: a lower bound there moves up to sh
+                            // slots below sh hold zeros: a lower bound there moves up to sh, whose
+                            // key is the list's first; elsewhere the search read the bound's key
                             const int32_t pc = min(max(p[k], sh), p2 - 1);
-                            fm[k] &= __ballot(pc < len_al) & __ballot(rw[pc] == a[k]);
+                            const uint32_t xk = p[k] < sh ? w_sh : x[k];
+                            fm[k] &= __ballot(pc < len_al) & __ballot(xk == a[k]);
                             if (kPos) pos[o][k] = base + pc;
                         }
                         continue;
@@ -992,12 +998,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                             // that the branch and the cursor stay scalar)
                             if (to_end || (uint32_t)uni((int32_t)win[P - 1]) >= a_last) {
                                 int32_t p[kSub];
-                                lds_search<kSub>(win, P, a, p);
+                                uint32_t x[kSub];
+                                const uint32_t w_sh = win[sh0];   // the key at the cursor
+                                lds_search<kSub>(win, P, a, p, x);
                                 int32_t pl = 0;
 #pragma unroll
                                 for (int k = 0; k < kSub; ++k) {
                                     const int32_t pc = min(max(p[k], sh0), P - 1);
-                                    fm[k] &= __ballot(pc < len_al) & __ballot(win[pc] == a[k]);
+                                    const uint32_t xk = p[k] < sh0 ? w_sh : x[k];
+                                    fm[k] &= __ballot(pc < len_al) & __ballot(xk == a[k]);
                                     if (kPos) pos[o][k] = ws + pc;
                                     if (k == (last >> 6)) pl = __builtin_amdgcn_readlane(max(p[k], sh0), last & 63);
                                 }
@@ -1033,7 +1042,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                         wave_sync();
                         if (capped || (uint32_t)uni((int32_t)win[nf - 1]) >= a_last) {
                             int32_t p[kSub];
-                            lds_search<kSub>(win, p2, a, p);   // p[k]: fences below the value (<= nf)
+                            uint32_t xf[kSub];
+                            lds_search<kSub>(win, p2, a, p, xf);   // p[k]: fences below the value (<= nf)
 #pragma unroll
                             for (int k = 0; k < kSub; ++k) {
                                 int32_t q = c0;   // every value's lower bound is at or past the cursor
@@ -1076,11 +1086,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                             stage_window(win, B, lo_al, sh, len_al, p2, lane);
                         wave_sync();
                         int32_t p[kSub];
-                        lds_search<kSub>(win, p2, a, p);   // all kSub searches advance together
+                        uint32_t x[kSub];
+                        const uint32_t w_sh = win[sh];   // the key at lo
+                        lds_search<kSub>(win, p2, a, p, x);   // all kSub searches advance together
 #pragma unroll
                         for (int k = 0; k < kSub; ++k) {
                             const int32_t pc = min(max(p[k], sh), p2 - 1);
-                            fm[k] &= __ballot(pc < len_al) & __ballot(win[pc] == a[k]);
+                            const uint32_t xk = p[k] < sh ? w_sh : x[k];
+                            fm[k] &= __ballot(pc < len_al) & __ballot(xk == a[k]);
                             if (kPos) pos[o][k] = lo_al + pc;
                         }
                     } else {
@@ -1100,7 +1113,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                         }
                         wave_sync();
                         int32_t p[kSub];
-                        lds_search<kSub>(win, p2, a, p);   // p[k]: fences below the value
+                        uint32_t xf[kSub];
+                        lds_search<kSub>(win, p2, a, p, xf);   // p[k]: fences below the value
 #pragma unroll
                         for (int k = 0; k < kSub; ++k) {
                             int32_t q = lo;
