@@ -1042,23 +1042,62 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                         wave_sync();
                         if (capped || (uint32_t)uni((int32_t)win[nf - 1]) >= a_last) {
                             int32_t p[kSub];
-                            uint32_t xf[kSub];
+                            uint32_t xf[kSub];   // the key of fence p[k] when p[k] < nf
                             lds_search<kSub>(win, p2, a, p, xf);   // p[k]: fences below the value (<= nf)
+                            bool hit[kSub];
+                            if (NOPS <= 3 && sp <= 5) {   // (4-operand levels keep their registers)
+                                // buckets of at most 4 keys: one 16-byte load of the 4 keys from
+                                // max(r - 4, 0), r the bucket's end (est <= the keys left in the
+                                // list, so more than 790 keys precede the list's end and the 4 lie
+                                // in the array; only keys in the bucket [l, r) are counted), the
+                                // lower bound is l plus the bucket keys below the value, and a bound
+                                // at r, fence p, has that fence's key
 #pragma unroll
-                            for (int k = 0; k < kSub; ++k) {
-                                int32_t q = c0;   // every value's lower bound is at or past the cursor
-                                if (v[k] && p[k] > 0) {
-                                    const int32_t l = c0 + (p[k] - 1) * sp + 1;
-                                    const int32_t r = c0 + p[k] * sp < e_o ? c0 + p[k] * sp : e_o;
-                                    q = lower_bound32(B, l, r, a[k]);
+                                for (int k = 0; k < kSub; ++k) {
+                                    int32_t q = c0;
+                                    bool h = p[k] == 0 && xf[k] == a[k];   // the cursor's key is fence 0
+                                    if (p[k] > 0) {
+                                        const int32_t l = c0 + (p[k] - 1) * sp + 1;
+                                        const int32_t r = c0 + p[k] * sp < e_o ? c0 + p[k] * sp : e_o;
+                                        const int32_t s4 = r >= 4 ? r - 4 : 0;
+                                        uint4 qd;
+                                        __builtin_memcpy(&qd, B + s4, 16);
+                                        const uint32_t kv[4] = {qd.x, qd.y, qd.z, qd.w};
+                                        int32_t nb = 0;
+#pragma unroll
+                                        for (int t = 0; t < 4; ++t)
+                                            nb += (s4 + t >= l && s4 + t < r && kv[t] < a[k]) ? 1 : 0;
+                                        q = l + nb;
+                                        uint32_t kq = kv[3];
+#pragma unroll
+                                        for (int t = 0; t < 3; ++t)
+                                            if (s4 + t == q) kq = kv[t];
+                                        h = q < r ? kq == a[k] : (r < e_o && xf[k] == a[k]);
+                                    }
+                                    p[k] = q;
+                                    hit[k] = h;
                                 }
-                                p[k] = q;
+                            } else {
+#pragma unroll
+                                for (int k = 0; k < kSub; ++k) {
+                                    int32_t q = c0;   // every value's lower bound is at or past the cursor
+                                    if (v[k] && p[k] > 0) {
+                                        const int32_t l = c0 + (p[k] - 1) * sp + 1;
+                                        const int32_t r = c0 + p[k] * sp < e_o ? c0 + p[k] * sp : e_o;
+                                        q = lower_bound32(B, l, r, a[k]);
+                                    }
+                                    p[k] = q;
+                                }
+#pragma unroll
+                                for (int k = 0; k < kSub; ++k) {
+                                    const int32_t qc = p[k] < e_o ? p[k] : e_o - 1;
+                                    hit[k] = p[k] < e_o && B[qc] == a[k];
+                                }
                             }
                             int32_t ql = c0;
 #pragma unroll
                             for (int k = 0; k < kSub; ++k) {
-                                const int32_t qc = p[k] < e_o ? p[k] : e_o - 1;
-                                fm[k] &= __ballot(p[k] < e_o) & __ballot(B[qc] == a[k]);
+                                fm[k] &= __ballot(hit[k]);
                                 if (kPos) pos[o][k] = p[k];
                                 if (k == (last >> 6)) ql = __builtin_amdgcn_readlane(p[k], last & 63);
                             }
