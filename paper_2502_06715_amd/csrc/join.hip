@@ -507,10 +507,10 @@ __device__ inline int32_t wave_search_hint(const uint32_t* __restrict__ B, int32
     return wave_search(B, lo, hi, v, lane);
 }
 
-// Stage B[base, base + len_al) in an LDS region with 16-byte loads (base is a
-// multiple of 4): the first sh slots are zeroed (they hold the tail of the
-// previous list, so the region stays sorted) and slots len_al .. p2-1 hold the
-// largest key, which no searched value exceeds.
+// Stage B[base, base + len_al) in an LDS region with 16-byte loads (gfx950 takes
+// them at any 4-byte-aligned address): the first sh slots are zeroed (they hold
+// keys before the list's start, so the region stays sorted) and slots
+// len_al .. p2-1 hold the largest key, which no searched value exceeds.
 __device__ inline void stage_window(uint32_t* rw, const uint32_t* __restrict__ B, int32_t base, int32_t sh,
                                     int32_t len_al, int32_t p2, int lane) {
     // all loads first, then the LDS stores: the loads of one lane overlap
@@ -522,7 +522,7 @@ __device__ inline void stage_window(uint32_t* rw, const uint32_t* __restrict__ B
         const int k0 = 4 * (lane + 64 * i);
         val[i] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
         if (k0 + 4 <= len_al) {
-            val[i] = *reinterpret_cast<const uint4*>(B + base + k0);
+            __builtin_memcpy(&val[i], B + base + k0, 16);   // 16-byte load, any 4-byte-aligned base
         } else if (k0 < len_al) {
             val[i].x = B[base + k0];
             if (k0 + 1 < len_al) val[i].y = B[base + k0 + 1];
@@ -569,23 +569,27 @@ __device__ inline void stage_window_inlist(uint32_t* rw, const uint32_t* __restr
 // no smaller than any searched value; whole rows of 64 quads need no lane test.
 __device__ inline void stage_full(uint32_t* rw, const uint32_t* __restrict__ B, int32_t base, int32_t sh, int32_t p2,
                                   int lane) {
-    const uint4* src = reinterpret_cast<const uint4*>(B + base);
+    const uint32_t* src = B + base + 4 * lane;   // 16-byte loads at any 4-byte-aligned base
     uint4* dst = reinterpret_cast<uint4*>(rw);
     const int nq = p2 >> 2;
+    uint4 v0, v1, v2, v3;
     if (nq >= 256) {
-        const uint4 v0 = src[lane], v1 = src[lane + 64], v2 = src[lane + 128], v3 = src[lane + 192];
+        __builtin_memcpy(&v0, src, 16);
+        __builtin_memcpy(&v1, src + 256, 16);
+        __builtin_memcpy(&v2, src + 512, 16);
+        __builtin_memcpy(&v3, src + 768, 16);
         dst[lane] = v0;
         dst[lane + 64] = v1;
         dst[lane + 128] = v2;
         dst[lane + 192] = v3;
     } else if (nq == 128) {
-        const uint4 v0 = src[lane], v1 = src[lane + 64];
+        __builtin_memcpy(&v0, src, 16);
+        __builtin_memcpy(&v1, src + 256, 16);
         dst[lane] = v0;
         dst[lane + 64] = v1;
-    } else if (nq == 64) {
-        dst[lane] = src[lane];
-    } else if (lane < nq) {
-        dst[lane] = src[lane];
+    } else if (nq == 64 || lane < nq) {
+        __builtin_memcpy(&v0, src, 16);
+        dst[lane] = v0;
     }
     if (lane < sh) rw[lane] = 0u;
 }
@@ -982,33 +986,31 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                     const uint32_t a_first = sload(ab), a_last = sload(ab + last);
                     const uint32_t est = est_cover((uint32_t)nsc, (uint32_t)(end[o] - cur[o]), hi_rel - rc);
                     {
-                        const int32_t ws = cur[o] & ~3;
-                        const int32_t sh0 = cur[o] - ws;
-                        const uint32_t want = est + (est >> 2) + 32u + (uint32_t)sh0;
+                        // the window starts at the cursor itself (unaligned 16-byte loads): every
+                        // value's lower bound is at or past it, so no slot precedes the first key
+                        const int32_t ws = cur[o];
+                        const uint32_t want = est + (est >> 2) + 32u;
                         if (want <= (uint32_t)kWin) {
                             const int32_t P = pow2_at_least((int32_t)want, 64);
                             const bool to_end = ws + P >= end[o];
                             const int32_t len_al = to_end ? end[o] - ws : P;
                             if (!to_end)
-                                stage_full(win, B, ws, sh0, P, lane);
+                                stage_full(win, B, ws, 0, P, lane);
                             else
-                                stage_window(win, B, ws, sh0, len_al, P, lane);
+                                stage_window(win, B, ws, 0, len_al, P, lane);
                             wave_sync();
                             // (the LDS word is the same for every lane: read it as a uniform value, so
                             // that the branch and the cursor stay scalar)
                             if (to_end || (uint32_t)uni((int32_t)win[P - 1]) >= a_last) {
                                 int32_t p[kSub];
-                                uint32_t x[kSub];
-                                const uint32_t w_sh = win[sh0];   // the key at the cursor
+                                uint32_t x[kSub];   // the key at each bound (padding past the list's end)
                                 lds_search<kSub>(win, P, a, p, x);
                                 int32_t pl = 0;
 #pragma unroll
                                 for (int k = 0; k < kSub; ++k) {
-                                    const int32_t pc = min(max(p[k], sh0), P - 1);
-                                    const uint32_t xk = p[k] < sh0 ? w_sh : x[k];
-                                    fm[k] &= __ballot(pc < len_al) & __ballot(xk == a[k]);
-                                    if (kPos) pos[o][k] = ws + pc;
-                                    if (k == (last >> 6)) pl = __builtin_amdgcn_readlane(max(p[k], sh0), last & 63);
+                                    fm[k] &= __ballot(p[k] < len_al) & __ballot(x[k] == a[k]);
+                                    if (kPos) pos[o][k] = ws + min(p[k], P - 1);
+                                    if (k == (last >> 6)) pl = __builtin_amdgcn_readlane(p[k], last & 63);
                                 }
                                 wave_sync();
                                 cur[o] = ws + pl;   // lower bound of the step's last value
