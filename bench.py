@@ -452,6 +452,79 @@ def bench_tensor(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_query_table(args):
+    """The query table of Section 7.1 (Q1 triangle, Q2 4-loop, Q4 diamond, Q6
+    4-clique, Q8 two triangles sharing a vertex) on the workload-3 recipe scaled
+    down (2^16 vertices / 2^20 edges; Q8, whose output grows with the square of the
+    triangles per vertex, at 2^14 / 2^18).  A step per query is CoCo build + order
+    and share decision (the cost model's joint search, cache rule) + join count,
+    the graph resident in HBM; every count is checked against the stored values
+    (textbook counters and closed forms, written by tests/golden/make_golden.py)."""
+    import torch
+    from paper_2502_06715_amd import hc, inputs
+
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "workloads.json")))["9"]
+    ctx = hc.Context(0)
+    dev = torch.device("cuda:0")
+    graphs = {}
+    results = {}
+    tot_cnt, tot_ms = 0, 0.0
+    for rec in gold["queries"]:
+        qn, sd, want = rec["query"], rec["scale_down"], int(rec["count"])
+        if sd not in graphs:
+            graphs[sd] = torch.from_numpy(inputs.config_graph(3, scale_down=sd)).to(dev)
+        E = graphs[sd]
+        nv, atoms = inputs.QUERIES[qn]
+        q = hc.Query(nv, atoms)
+        rule = hc.HC_CACHE_SHARES if args.share_rule == "cache" else 0
+
+        def step():
+            c = hc.build_coco(ctx, E, [0, 1], symmetric=True)
+            order, shares = hc.compute_shares(ctx, q, [c] * len(atoms), args.log2_cells, flags=rule)
+            cnt = hc.join_count(ctx, q, [c] * len(atoms), order, shares)
+            c.free()
+            return cnt, order, shares
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        outs = [step() for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - ts) / args.steps
+        cnt, order, shares = outs[-1]
+        if any(o[0] != want for o in outs):
+            print("query table: %s count %d differs from the stored %d" % (qn, cnt, want), file=sys.stderr)
+            sys.exit(1)
+        results[qn] = {"count": cnt, "ms_per_step": round(ms, 3), "tuples_per_s": cnt / (ms / 1000.0),
+                       "order": order, "log2_shares": shares, "tuples_in": int(E.shape[0]),
+                       "graph": "2^%d vertices, 2^%d edges" % (18 - sd, 22 - sd), "check": rec["count_source"]}
+        tot_cnt += cnt
+        tot_ms += ms
+        print("# %s: %s" % (qn, json.dumps(results[qn])), file=sys.stderr, flush=True)
+    out = {
+        "metric": "output tuples/s over the query table (Q1, Q2, Q4, Q6, Q8)",
+        "value": tot_cnt / (tot_ms / 1000.0),
+        "unit": "tuples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(tot_ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "query table Q1/Q2/Q4/Q6 on a Chung-Lu graph (beta 2.1, 2^16 vertices, 2^20 "
+                               "undirected edges) and Q8 on one of 2^14 / 2^18, int32, count; a step runs every "
+                               "query once",
+                   "log2_cells": args.log2_cells, "share_rule": args.share_rule},
+        "results": results,
+        "roofline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def _spearman(a, b):
     ra = np.argsort(np.argsort(a)).astype(np.float64)
     rb = np.argsort(np.argsort(b)).astype(np.float64)
@@ -647,6 +720,8 @@ def main():
         return bench_order_sweep(args)
     if args.config == 8:
         return bench_share_sweep(args)
+    if args.config == 9:
+        return bench_query_table(args)
 
     import torch
     from paper_2502_06715_amd import hc, inputs

@@ -54,6 +54,8 @@ def lib():
         L.textbook_4clique_digest.argtypes = [P, ctypes.c_int64, ctypes.c_int, P]
         L.textbook_closed_4walks.restype = ctypes.c_int64
         L.textbook_closed_4walks.argtypes = [P, ctypes.c_int64, ctypes.c_int]
+        L.textbook_triangle_stats.restype = ctypes.c_int64
+        L.textbook_triangle_stats.argtypes = [P, ctypes.c_int64, ctypes.c_int, P]
         _lib = L
     return _lib
 
@@ -201,3 +203,17 @@ def textbook_cycle4(edges, threads: int = 0) -> int:
     if e.shape[0] == 0:
         return 0
     return int(lib().textbook_closed_4walks(_ptr(e), e.shape[0], threads))
+
+
+
+def textbook_diamond_twotriangle(edges, threads: int = 0):
+    """(ordered diamond count, ordered two-triangle count) on a symmetric loop-free
+    relation, in closed form from the triangles on every edge and vertex:
+    sum_e 2 t(e)^2 and sum_v (2 t(v))^2 (textbook.c)."""
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int64))
+    if e.shape[0] == 0:
+        return 0, 0
+    out = np.zeros(2, dtype=np.uint64)
+    if lib().textbook_triangle_stats(_ptr(e), e.shape[0], threads, _ptr(out)) != 0:
+        raise ValueError("negative id")
+    return int(out[0]), int(out[1])

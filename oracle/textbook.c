@@ -8,7 +8,11 @@
  *    Latapy 2008): orient every edge from lower to higher (degree, id) rank and
  *    count, for each oriented edge (u, v), the common out-neighbours of u and v;
  *  - 4-cliques: the same orientation (Chiba and Nishizeki 1985 style): for each
- *    oriented edge (u, v), W = out(u) & out(v), then count oriented edges inside W.
+ *    oriented edge (u, v), W = out(u) & out(v), then count oriented edges inside W;
+ *  - triangles per edge and per vertex (the same forward enumeration, each triangle
+ *    credited to its three edges and three vertices), which give the ordered
+ *    diamond count sum_e 2 t(e)^2 and the ordered two-triangle count
+ *    sum_v (2 t(v))^2 in closed form.
  * Both count unordered subgraphs of a simple undirected graph given as its
  * symmetric edge list (duplicates and self-loops ignored).
  */
@@ -271,4 +275,63 @@ int64_t textbook_closed_4walks(const int64_t* e, int64_t m, int nthreads) {
     }
     free(off); free(nb); free(cur); free(deg);
     return (int64_t)total;
+}
+
+/* Closed forms of two homomorphism counts over a symmetric loop-free relation E
+ * (ordered tuples, no inequalities between variables):
+ *   diamond  R(a,b) R(a,c) R(b,d) R(c,d) R(b,c): for every ordered edge (b,c), a and
+ *            d range independently over the common neighbours of b and c, so the
+ *            count is sum over unordered edges e of 2 t(e)^2, t(e) = triangles on e;
+ *   two triangles sharing a vertex c, R(a,b) R(a,c) R(b,c) R(c,d) R(c,e) R(d,e):
+ *            every side is an ordered pair of adjacent neighbours of c, 2 t(c) of
+ *            them, t(c) = triangles on c, so the count is sum over c of (2 t(c))^2.
+ * t(e) and t(v) come from the forward enumeration, each triangle credited to its
+ * three edges and vertices.  out[0] = diamond, out[1] = two-triangle; returns 0
+ * (-1 on a negative id). */
+int64_t textbook_triangle_stats(const int64_t* e, int64_t m, int nthreads, uint64_t* out) {
+    tb_graph g;
+    if (tb_build(e, m, &g) != 0) return -1;
+    const int64_t ne = g.off[g.n];
+    uint64_t* te = (uint64_t*)calloc((size_t)ne + 1, sizeof(uint64_t));
+    uint64_t* tv = (uint64_t*)calloc((size_t)g.n + 1, sizeof(uint64_t));
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+    {
+        int64_t* slot = (int64_t*)calloc((size_t)g.n + 1, sizeof(int64_t));   /* edge index + 1 of (u, w) */
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t u = 0; u < g.n; ++u) {
+            for (int64_t i = g.off[u]; i < g.off[u + 1]; ++i) slot[g.adj[i]] = i + 1;
+            for (int64_t i = g.off[u]; i < g.off[u + 1]; ++i) {
+                const int64_t v = g.adj[i];
+                for (int64_t j = g.off[v]; j < g.off[v + 1]; ++j) {
+                    const int64_t w = g.adj[j];
+                    if (slot[w] == 0) continue;
+                    /* triangle u, v, w: edges (u,v) = i, (v,w) = j, (u,w) = slot[w] - 1 */
+#pragma omp atomic
+                    te[i]++;
+#pragma omp atomic
+                    te[j]++;
+#pragma omp atomic
+                    te[slot[w] - 1]++;
+#pragma omp atomic
+                    tv[u]++;
+#pragma omp atomic
+                    tv[v]++;
+#pragma omp atomic
+                    tv[w]++;
+                }
+            }
+            for (int64_t i = g.off[u]; i < g.off[u + 1]; ++i) slot[g.adj[i]] = 0;
+        }
+        free(slot);
+    }
+    uint64_t dia = 0, two = 0;
+    for (int64_t i = 0; i < ne; ++i) dia += 2 * te[i] * te[i];
+    for (int64_t v = 0; v < g.n; ++v) two += 4 * tv[v] * tv[v];
+    out[0] = dia;
+    out[1] = two;
+    free(te); free(tv); free(g.off); free(g.adj);
+    return 0;
 }

@@ -10,6 +10,11 @@ Workload 2: R-MAT scale 20, 2^24 undirected edges, triangle query, count +
   galloping work counter (shares = 1, order a,b,c).
 Workload 3: Chung-Lu beta = 2.1, 2^18 vertices, 2^22 undirected edges, 4-clique
   query, count + digest, plus range-restricted chunks on variable 0.
+Query table (key "9"): the queries Q1, Q2, Q4, Q6 of Section 7.1 on the workload-3
+  recipe at 2^16 vertices / 2^20 edges and Q8 at 2^14 / 2^18; counts from textbook
+  counters and closed forms (triangles, closed 4-walks, 2 t(e)^2 over the edges,
+  K4 enumeration, (2 t(v))^2 over the vertices), the triangle count cross-checked
+  by the Generic Join oracle.
 Workload 4 (tests/golden/batch_config4.json): 4096 independent triangle / 4-cycle
   queries, each on its own ER or R-MAT graph (inputs.batch_spec); per-query counts
   from the textbook counters, every 16th query (m <= 2^15) cross-checked by the
@@ -56,6 +61,40 @@ def batch_golden(threads: int):
     print("4", {k: v for k, v in rec.items() if k != "counts"}, flush=True)
 
 
+# query table: (query, scale_down of the workload-3 recipe)
+QUERY_TABLE = [("triangle", 2), ("loop4", 2), ("diamond4", 2), ("clique4", 2), ("twotriangle", 4)]
+
+
+def query_table_golden(threads: int):
+    t0 = time.time()
+    rec = {"graph": "workload-3 recipe (Chung-Lu, beta 2.1) at scale_down 2 (2^16 vertices, 2^20 edges) "
+                    "and 4 (2^14, 2^18)", "queries": []}
+    stats = {}
+    for q, sd in QUERY_TABLE:
+        g = inputs.config_graph(3, scale_down=sd)
+        if sd not in stats:
+            stats[sd] = oracle.textbook_diamond_twotriangle(g, threads=threads)
+        if q == "triangle":
+            c = 6 * oracle.textbook_triangles(g, threads=threads)
+            n, atoms = inputs.QUERIES[q]
+            r = oracle.gj(n, atoms, [g] * len(atoms), threads=threads)
+            assert r.count == c, (r.count, c)
+            src = "textbook triangles x 6 = Generic Join oracle"
+        elif q == "loop4":
+            c, src = oracle.textbook_cycle4(g, threads=threads), "closed 4-walks"
+        elif q == "diamond4":
+            c, src = stats[sd][0], "sum over edges of 2 t(e)^2"
+        elif q == "clique4":
+            c, src = 24 * oracle.textbook_4cliques(g, threads=threads), "textbook K4 x 24"
+        else:
+            c, src = stats[sd][1], "sum over vertices of (2 t(v))^2"
+        rec["queries"].append({"query": q, "scale_down": sd, "rows": int(g.shape[0]), "count": str(c),
+                               "count_source": src})
+    rec["oracle_seconds"] = round(time.time() - t0, 1)
+    print("9", rec, flush=True)
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=0)
@@ -65,6 +104,9 @@ def main():
     out = json.load(open(path)) if os.path.exists(path) else {}
     if not args.only or args.only == 4:
         batch_golden(args.threads)
+    if not args.only or args.only == 9:
+        out["9"] = query_table_golden(args.threads)
+        json.dump(out, open(path, "w"), indent=1, sort_keys=True)
     for cfg in [1, 2, 3]:
         if args.only and cfg != args.only:
             continue

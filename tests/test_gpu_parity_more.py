@@ -226,3 +226,34 @@ def test_config3_chunk_rows(ctx, k):
                                flags=hc.HC_EMIT_SORTED, capacity=ch["count"])
     assert n_out == ch["count"]
     assert np.array_equal(rows.cpu().numpy(), exp.rows)
+
+
+@pytest.mark.parametrize("name", ["triangle", "loop4", "diamond4", "clique4", "twotriangle"])
+def test_query_table_optimizer_plans(ctx, name):
+    """The query table (Q1, Q2, Q4, Q6, Q8) with the order and shares the cost model
+    picks (cache rule), on the workload-3 recipe at 2^12 vertices / 2^16 edges,
+    against the oracle's Generic Join count."""
+    g = inputs.config_graph(3, scale_down=6)
+    n, atoms = inputs.QUERIES[name]
+    log("query table %s on %d tuples" % (name, g.shape[0]))
+    want = oracle.gj(n, atoms, [g] * len(atoms), threads=8).count
+    c = hc.build_coco(ctx, _dev(g), [0, 1], symmetric=True)
+    q = hc.Query(n, atoms)
+    order, shares = hc.compute_shares(ctx, q, [c] * len(atoms), 8, flags=hc.HC_CACHE_SHARES)
+    assert hc.join_count(ctx, q, [c] * len(atoms), order, shares) == want
+    c.free()
+
+
+@pytest.mark.parametrize("name", ["loop4", "diamond4"])
+def test_query_table_full_size(ctx, name):
+    """Q2 and Q4 at the query table's size (2^16 vertices, 2^20 edges: 4.6e10 and
+    1.9e10 ordered tuples) against the stored closed-form counts."""
+    rec = [r for r in GOLD["9"]["queries"] if r["query"] == name][0]
+    g = inputs.config_graph(3, scale_down=rec["scale_down"])
+    n, atoms = inputs.QUERIES[name]
+    log("query table %s at full size, %d tuples" % (name, g.shape[0]))
+    c = hc.build_coco(ctx, _dev(g), [0, 1], symmetric=True)
+    q = hc.Query(n, atoms)
+    order, shares = hc.compute_shares(ctx, q, [c] * len(atoms), 12, flags=hc.HC_CACHE_SHARES)
+    assert hc.join_count(ctx, q, [c] * len(atoms), order, shares) == int(rec["count"])
+    c.free()

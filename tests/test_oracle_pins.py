@@ -380,3 +380,24 @@ def test_gj_timed_sample():
         firsts.add(one["count"])
         assert one["count"] == 0 or one["count"] in per_value.values()
     assert len(firsts) > 1                     # the seed changes the order
+
+
+def test_query_table_closed_forms():
+    """Q2, Q4 and Q8 of the query table against closed forms that share nothing
+    with Generic Join: the 4-loop is the closed 4-walk count, the diamond sums
+    2 t(e)^2 over the edges and the two-triangle query (2 t(v))^2 over the vertices,
+    t the triangles on an edge or vertex (textbook.c)."""
+    for g in (inputs.chung_lu(300, 2000, 3), inputs.rmat(9, 1500, 4), inputs.erdos_renyi(256, 1500, 5)):
+        q4, q8 = oracle.textbook_diamond_twotriangle(g, threads=2)
+        n, atoms = Q["loop4"]
+        assert oracle.gj(n, atoms, [g] * len(atoms), threads=2).count == oracle.textbook_cycle4(g, threads=2)
+        n, atoms = Q["diamond4"]
+        assert oracle.gj(n, atoms, [g] * len(atoms), threads=2).count == q4
+        n, atoms = Q["twotriangle"]
+        assert oracle.gj(n, atoms, [g] * len(atoms), threads=2).count == q8
+    # a planted mistake is caught: one edge fewer changes both closed forms
+    g = inputs.chung_lu(300, 2000, 3)
+    base = oracle.textbook_diamond_twotriangle(g, threads=2)
+    u, v = int(g[0, 0]), int(g[0, 1])
+    keep = ~(((g[:, 0] == u) & (g[:, 1] == v)) | ((g[:, 0] == v) & (g[:, 1] == u)))
+    assert oracle.textbook_diamond_twotriangle(g[keep], threads=2) != base
