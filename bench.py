@@ -471,6 +471,7 @@ def bench_query_table(args):
     tot_cnt, tot_ms = 0, 0.0
     for rec in gold["queries"]:
         qn, sd, want = rec["query"], rec["scale_down"], int(rec["count"])
+        print("# query table: %s (scale_down %d)" % (qn, sd), file=sys.stderr, flush=True)
         if sd not in graphs:
             graphs[sd] = torch.from_numpy(inputs.config_graph(3, scale_down=sd)).to(dev)
         E = graphs[sd]
