@@ -691,6 +691,38 @@ __device__ inline int32_t lower_bound32(const uint32_t* __restrict__ B, int32_t 
     return l;
 }
 
+// Lower bound of v in a sorted list given B[lo] = blo < v <= bhi = B[hi] (lo < hi):
+// interpolation probes (the keys are hashed, so they spread evenly over the key
+// range and the guess lands near the bound), each one load that narrows [lo, hi],
+// then a binary search once at most 4 keys remain or after 6 probes.
+__device__ inline int32_t interp_lb_between(const uint32_t* __restrict__ B, int32_t lo, uint32_t blo, int32_t hi,
+                                            uint32_t bhi, uint32_t v) {
+#pragma unroll 1
+    for (int it = 0; it < 6 && hi - lo > 4; ++it) {
+        const float f = (float)(v - blo) * __builtin_amdgcn_rcpf((float)(bhi - blo));
+        int32_t p = lo + (int32_t)(f * (float)(hi - lo));
+        p = min(max(p, lo + 1), hi - 1);
+        const uint32_t bp = B[p];
+        if (bp < v) {
+            lo = p;
+            blo = bp;
+        } else {
+            hi = p;
+            bhi = bp;
+        }
+    }
+    return lower_bound32(B, lo + 1, hi, v);   // B[hi] >= v
+}
+
+// First p in [l, h) with B[p] >= v (h if none) by interpolation from the range's ends.
+__device__ inline int32_t interp_lb(const uint32_t* __restrict__ B, int32_t l, int32_t h, uint32_t v) {
+    if (l >= h) return l;
+    const uint32_t b0 = B[l], b1 = B[h - 1];
+    if (v <= b0) return l;
+    if (v > b1) return h;
+    return interp_lb_between(B, l, b0, h - 1, b1, v);
+}
+
 // ---- the per-element search methods of Section 5 (one search per lane), each
 // returning the first p in [l, h) with B[p] >= v (h if none):
 //   exponential: jumps of 1, 2, 4, ... from l until one overshoots, then binary search;
@@ -1084,9 +1116,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                                 for (int k = 0; k < kSub; ++k) {
                                     int32_t q = c0;   // every value's lower bound is at or past the cursor
                                     if (v[k] && p[k] > 0) {
+                                        // between fence p - 1 (key below the value) and fence p
+                                        // (key xf, at least the value) when that one exists
                                         const int32_t l = c0 + (p[k] - 1) * sp + 1;
-                                        const int32_t r = c0 + p[k] * sp < e_o ? c0 + p[k] * sp : e_o;
-                                        q = lower_bound32(B, l, r, a[k]);
+                                        if (!kPos && NOPS <= 3 && p[k] < nf)   // (counting levels)
+                                            q = interp_lb_between(B, l - 1, win[p[k] - 1], c0 + p[k] * sp, xf[k], a[k]);
+                                        else
+                                            q = lower_bound32(B, l, c0 + p[k] * sp < e_o ? c0 + p[k] * sp : e_o, a[k]);
                                     }
                                     p[k] = q;
                                 }
@@ -1273,7 +1309,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
 #pragma unroll
                         for (int o = 0; o < NOPS; ++o) {
                             if (o == il || !found) continue;
-                            const int32_t q = lane_search(search, arr0[o], bl[o], el[o], av);
+                            // (counting levels search by interpolation: the keys are hashed)
+                            const int32_t q = !kPos && search == SEARCH_WINDOW
+                                                  ? interp_lb(arr0[o], bl[o], el[o], av)
+                                                  : lane_search(search, arr0[o], bl[o], el[o], av);
                             pp[o] = q;
                             found = q < el[o] && arr0[o][q] == av;
                         }
