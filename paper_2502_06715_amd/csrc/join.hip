@@ -693,12 +693,13 @@ __device__ inline int32_t lower_bound32(const uint32_t* __restrict__ B, int32_t 
 
 // Lower bound of v in a sorted list given B[lo] = blo < v <= bhi = B[hi] (lo < hi):
 // interpolation probes (the keys are hashed, so they spread evenly over the key
-// range and the guess lands near the bound), each one load that narrows [lo, hi],
-// then a binary search once at most 4 keys remain or after 6 probes.
+// range and the guess lands near the bound), each one load that narrows [lo, hi];
+// once at most 4 keys remain, the up to 3 between lo and hi are read together and
+// counted.  Returns the bound and, in key, the key there (bhi when it is hi).
 __device__ inline int32_t interp_lb_between(const uint32_t* __restrict__ B, int32_t lo, uint32_t blo, int32_t hi,
-                                            uint32_t bhi, uint32_t v) {
+                                            uint32_t bhi, uint32_t v, uint32_t& key) {
 #pragma unroll 1
-    for (int it = 0; it < 6 && hi - lo > 4; ++it) {
+    for (int it = 0; it < 8 && hi - lo > 4; ++it) {
         const float f = (float)(v - blo) * __builtin_amdgcn_rcpf((float)(bhi - blo));
         int32_t p = lo + (int32_t)(f * (float)(hi - lo));
         p = min(max(p, lo + 1), hi - 1);
@@ -711,16 +712,29 @@ __device__ inline int32_t interp_lb_between(const uint32_t* __restrict__ B, int3
             bhi = bp;
         }
     }
-    return lower_bound32(B, lo + 1, hi, v);   // B[hi] >= v
+    if (hi - lo > 4) {   // (keys far from even: finish by bisection)
+        const int32_t q = lower_bound32(B, lo + 1, hi, v);
+        key = q < hi ? B[q] : bhi;
+        return q;
+    }
+    // positions lo+1 .. lo+3 clamped to hi (whose key is known to be >= v)
+    const uint32_t k1 = lo + 1 < hi ? B[lo + 1] : bhi;
+    const uint32_t k2 = lo + 2 < hi ? B[lo + 2] : bhi;
+    const uint32_t k3 = lo + 3 < hi ? B[lo + 3] : bhi;
+    const int32_t nb = (k1 < v ? 1 : 0) + (k2 < v ? 1 : 0) + (k3 < v ? 1 : 0);
+    key = nb == 0 ? k1 : (nb == 1 ? k2 : (nb == 2 ? k3 : bhi));
+    return min(lo + 1 + nb, hi);
 }
 
-// First p in [l, h) with B[p] >= v (h if none) by interpolation from the range's ends.
-__device__ inline int32_t interp_lb(const uint32_t* __restrict__ B, int32_t l, int32_t h, uint32_t v) {
+// First p in [l, h) with B[p] >= v (h if none) by interpolation from the range's
+// ends; key receives B[p] when p < h.
+__device__ inline int32_t interp_lb(const uint32_t* __restrict__ B, int32_t l, int32_t h, uint32_t v, uint32_t& key) {
     if (l >= h) return l;
     const uint32_t b0 = B[l], b1 = B[h - 1];
+    key = b0;
     if (v <= b0) return l;
     if (v > b1) return h;
-    return interp_lb_between(B, l, b0, h - 1, b1, v);
+    return interp_lb_between(B, l, b0, h - 1, b1, v, key);
 }
 
 // ---- the per-element search methods of Section 5 (one search per lane), each
@@ -1115,21 +1129,27 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
 #pragma unroll
                                 for (int k = 0; k < kSub; ++k) {
                                     int32_t q = c0;   // every value's lower bound is at or past the cursor
+                                    bool have = false;   // the bound's key is known
+                                    uint32_t kq = 0;
                                     if (v[k] && p[k] > 0) {
                                         // between fence p - 1 (key below the value) and fence p
                                         // (key xf, at least the value) when that one exists
                                         const int32_t l = c0 + (p[k] - 1) * sp + 1;
-                                        if (!kPos && NOPS <= 3 && p[k] < nf)   // (counting levels)
-                                            q = interp_lb_between(B, l - 1, win[p[k] - 1], c0 + p[k] * sp, xf[k], a[k]);
-                                        else
+                                        if (!kPos && NOPS <= 3 && SM == 0 && p[k] < nf) {   // (counting levels)
+                                            q = interp_lb_between(B, l - 1, win[p[k] - 1], c0 + p[k] * sp, xf[k], a[k],
+                                                                  kq);
+                                            have = true;
+                                        } else {
                                             q = lower_bound32(B, l, c0 + p[k] * sp < e_o ? c0 + p[k] * sp : e_o, a[k]);
+                                        }
+                                    }
+                                    if (have) {
+                                        hit[k] = kq == a[k];
+                                    } else {
+                                        const int32_t qc = q < e_o ? q : e_o - 1;
+                                        hit[k] = q < e_o && B[qc] == a[k];
                                     }
                                     p[k] = q;
-                                }
-#pragma unroll
-                                for (int k = 0; k < kSub; ++k) {
-                                    const int32_t qc = p[k] < e_o ? p[k] : e_o - 1;
-                                    hit[k] = p[k] < e_o && B[qc] == a[k];
                                 }
                             }
                             int32_t ql = c0;
@@ -1309,12 +1329,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
 #pragma unroll
                         for (int o = 0; o < NOPS; ++o) {
                             if (o == il || !found) continue;
-                            // (counting levels search by interpolation: the keys are hashed)
-                            const int32_t q = !kPos && search == SEARCH_WINDOW
-                                                  ? interp_lb(arr0[o], bl[o], el[o], av)
-                                                  : lane_search(search, arr0[o], bl[o], el[o], av);
+                            // (counting levels with the default method search by interpolation: the
+                            // keys are hashed)
+                            int32_t q;
+                            if (!kPos && SM == 0) {
+                                uint32_t kq = 0;
+                                q = interp_lb(arr0[o], bl[o], el[o], av, kq);
+                                found = q < el[o] && kq == av;
+                            } else {
+                                q = lane_search(search, arr0[o], bl[o], el[o], av);
+                                found = q < el[o] && arr0[o][q] == av;
+                            }
                             pp[o] = q;
-                            found = q < el[o] && arr0[o][q] == av;
                         }
                         if (found && S.has_pred) found = pred_ok(S, F + my_e * S.W_in, av, D.mix);
                         if (MODE == M_BITMAP && out.pos != nullptr) {
