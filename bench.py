@@ -219,8 +219,79 @@ def bench_batch(args):
                                  "ms_total": round(ms_seq, 3)},
         "speedup_vs_one_query_per_launch": round(ms_seq / ms_batched, 3),
         "roofline": None,
+        "resident": _batch_resident(ctx, groups, graphs, expect, max(args.steps, 2)),
     }
     print(json.dumps(out), flush=True)
+
+
+def _batch_resident(ctx, groups, graphs, expect, steps):
+    """The batched joins over segmented CoCos built once (resident indexes): a step
+    of eager fused counts against a step of captured joins (hc_join_graph_*) for the
+    groups whose frontier capacities (batch.graph_caps) fit, eager for the rest;
+    per-query counts checked on every step."""
+    import torch
+    from paper_2502_06715_amd import batch, hc
+    cocos, graphs_of = {}, {}
+    for key, g in groups.items():
+        cocos[key] = hc.build_coco(ctx, g["rel"], [0, 1], key_bits=g["mb"], segment_bits=g["seg"], symmetric=True)
+        caps = batch.graph_caps(key[0], [graphs[i] for i in g["idx"]])
+        if caps is not None:
+            graphs_of[key] = batch.BatchGraph(ctx, key[0], cocos[key], g["n"], g["extra"], caps)
+
+    def eager_step():
+        got = np.zeros(expect.shape[0], dtype=np.uint64)
+        for key, g in groups.items():
+            got[g["idx"]] = batch.count_batched(ctx, key[0], g["rel"], g["n"], g["mb"], g["seg"],
+                                                extra_bits=g["extra"], coco=cocos[key], method=g["method"])
+        return got
+
+    def graph_step():
+        got = np.zeros(expect.shape[0], dtype=np.uint64)
+        for bg in graphs_of.values():
+            bg.launch()
+        for key, g in groups.items():
+            if key in graphs_of:
+                per, rep = graphs_of[key].result()
+                if not rep:
+                    raise RuntimeError("captured batch %s/%d exceeded its capacities" % key)
+                got[g["idx"]] = per
+            else:
+                got[g["idx"]] = batch.count_batched(ctx, key[0], g["rel"], g["n"], g["mb"], g["seg"],
+                                                    extra_bits=g["extra"], coco=cocos[key], method=g["method"])
+        return got
+
+    out = {"captured_groups": ["%s/%d" % k for k in graphs_of]}
+    for name, fn in (("eager", eager_step), ("captured", graph_step)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            if np.any(fn() != expect):
+                raise RuntimeError("resident %s batch: per-query counts differ from the oracle's" % name)
+        torch.cuda.synchronize()
+        out[name + "_ms_per_step"] = round(1000.0 * (time.perf_counter() - t0) / steps, 3)
+        # the small groups alone (what the capture changes)
+        keys = list(graphs_of)
+        if keys:
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                if name == "eager":
+                    for key in keys:
+                        g = groups[key]
+                        batch.count_batched(ctx, key[0], g["rel"], g["n"], g["mb"], g["seg"], extra_bits=g["extra"],
+                                            coco=cocos[key], method=g["method"])
+                else:
+                    for key in keys:
+                        graphs_of[key].launch()
+                    for key in keys:
+                        graphs_of[key].result()
+            torch.cuda.synchronize()
+            out[name + "_captured_groups_ms"] = round(1000.0 * (time.perf_counter() - t0) / steps, 3)
+    for bg in graphs_of.values():
+        bg.free()
+    for c in cocos.values():
+        c.free()
+    return out
 
 
 def bench_serve(args):
@@ -850,9 +921,58 @@ def main():
                       for k in ["build_ms", "shares_ms", "join_ms", "leaf_ms"]},
         "roofline": roof,
     }
+    if emit:
+        out["captured"] = bench_captured_join(ctx, q, E_dev, b, atoms, res[-1]["order"], res[-1]["shares"],
+                                              expect, rows_buf)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(E, n_vars, atoms, expect, args.cpu_budget)
     print(json.dumps(out), flush=True)
+
+
+def bench_captured_join(ctx, q, E_dev, b, atoms, order, shares, expect, rows_buf, reps=50):
+    """The join of the step (count and full output) over a resident CoCo, eager against
+    replays of the captured launch sequences (hc_join_graph_*: frontier sizes stay on
+    the device, no host round trip between levels); every result checked."""
+    import torch
+    from paper_2502_06715_amd import hc
+    coco = hc.build_coco(ctx, E_dev, [0, 1], key_bits=b)
+    cocos = [coco] * len(atoms)
+    ctx.set_profiling(False)
+
+    def eager():
+        cnt = hc.join_count(ctx, q, cocos, order, shares)
+        _, n_out = hc.join_emit(ctx, q, cocos, order, shares, out=rows_buf)
+        return cnt, n_out
+
+    gc = hc.JoinGraph(ctx, q, cocos, order, shares)
+    ge = hc.JoinGraph(ctx, q, cocos, order, shares, mode="emit", out=rows_buf)
+
+    def graph():
+        gc.launch()
+        ge.launch()
+        c, _, r1 = gc.result()
+        n, _, r2 = ge.result()
+        if not (r1 and r2):
+            raise RuntimeError("a captured join exceeded its capacities")
+        return c, n
+
+    out = {}
+    for name, fn in (("eager", eager), ("graph", graph)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            c, n = fn()
+            if c != expect or n != expect:
+                raise RuntimeError("%s join: count %d, rows %d, expected %d" % (name, c, n, expect))
+        torch.cuda.synchronize()
+        out[name + "_join_ms"] = round(1000.0 * (time.perf_counter() - t0) / reps, 4)
+    gc.free()
+    ge.free()
+    coco.free()
+    ctx.set_profiling(True)
+    return out
 
 
 if __name__ == "__main__":

@@ -51,6 +51,7 @@ typedef enum { HC_I32 = 0, HC_I64 = 1 } hc_dtype;
 
 typedef struct hc_ctx hc_ctx;
 typedef struct hc_coco hc_coco;
+typedef struct hc_join_graph hc_join_graph;
 
 /*
  * A full conjunctive query (Section 2, Eq. (1)).  Variables are 0..n_vars-1,
@@ -383,6 +384,52 @@ hc_status hc_join_workspace_bound(hc_ctx* ctx, const hc_query* q, const hc_coco*
 hc_status hc_join_emit(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
                        const int32_t* var_order, const int32_t* log2_shares, uint32_t flags,
                        void* out, int64_t capacity, int64_t* n_out);
+
+/*
+ * A Generic Join (Sections 5 and 6) recorded once as a fixed launch sequence in a
+ * HIP graph and replayed: every kernel reads the frontier sizes the kernel before
+ * it wrote in device memory, so a replay makes no host round trip between the
+ * levels (the eager calls read each level's sizes back to size the next).  The
+ * frontiers below F_0 hold at most frontier_cap entries and every level that
+ * materialises (all but a counting deepest level) at most item_cap elements
+ * (0: 2^20 and 2^22); a replay whose data exceeds them raises a device flag, and
+ * hc_join_graph_result then computes that call's result with the eager path, so
+ * results are always exact.  The graph is bound to the CoCo handles, their
+ * contents, the query, order and shares it was created with, and to ctx (all must
+ * outlive it); replays run on ctx's stream.
+ *   cell_group  < 0: a count; >= 0: per-cell counts as hc_join_count_cells, summed
+ *               over groups of 2^cell_group consecutive cells (with segmented
+ *               CoCos and the first variable's share segment_bits + extra,
+ *               cell_group = extra gives per-segment counts as
+ *               hc_join_count_segments)
+ *   out         device, nullable: emit the rows as hc_join_emit (unsorted) into
+ *               capacity rows; then cell_group must be < 0
+ * Supported plans: no lifted intersection (HC_NO_REWRITE, or queries whose plan
+ * lifts nothing, e.g. the triangle and the 4-cycle), at most 4 operands per
+ * level, the default search (flags take HC_NO_REWRITE only).
+ * Errors: HC_ERR_INVALID (as hc_join_count; capacities above 2^28 entries or
+ * 2^30 elements), HC_ERR_UNSUPPORTED (plans outside the above), HC_ERR_OOM,
+ * HC_ERR_DEVICE.
+ */
+hc_status hc_join_graph_create(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
+                               const int32_t* var_order, const int32_t* log2_shares, uint32_t flags,
+                               int32_t cell_group, void* out, int64_t capacity, int64_t frontier_cap,
+                               int64_t item_cap, hc_join_graph** graph_out);
+/* Enqueue one replay on ctx's stream (asynchronous). */
+hc_status hc_join_graph_launch(hc_join_graph* g);
+/*
+ * Wait for the last replay and return its result: count_out (host) the count, or
+ * the rows emitted; cell_counts (host, nullable; 2^(K - cell_group) entries) the
+ * per-cell counts; n_out (host, nullable) the rows; replayed (host, nullable) 1
+ * when the replay's own result was used, 0 when a capacity was exceeded and the
+ * eager path computed it.  Errors: HC_ERR_INVALID (no replay launched),
+ * HC_ERR_OVERFLOW (emit: more rows than the capacity; n_out holds the total),
+ * HC_ERR_CANCELLED, HC_ERR_DEVICE.
+ */
+hc_status hc_join_graph_result(hc_join_graph* g, uint64_t* count_out, uint64_t* cell_counts, int64_t* n_out,
+                               int32_t* replayed);
+/* Wait for every replay on ctx's stream, then release the graph and its buffers. */
+void hc_join_graph_destroy(hc_join_graph* g);
 
 /*
  * Describe the compiled Generic Join plan (per level: operands and the lifted

@@ -102,6 +102,52 @@ def count_batched(ctx: hc.Context, shape: str, rel_dev, n_queries: int, mix_bits
     return per_query[:n_queries]
 
 
+def graph_caps(shape: str, graphs, limit: int = 1 << 26):
+    """Exact frontier and element capacities of a fused batch's captured join (order
+    0..n-1, only the first variable split, so no frontier entry is replicated), from
+    the degrees: the triangle's frontiers and materialised levels hold at most the
+    directed edges; the 4-cycle's third frontier holds every 2-path (a, b, c), the
+    sum of the squared degrees (the edge lists hold both directions).  None when that exceeds `limit` (the batch then runs
+    eagerly)."""
+    need = sum(int(g.shape[0]) for g in graphs)   # directed edges: the lists hold both directions
+    if shape == "cycle4":
+        paths = 0
+        for g in graphs:
+            if g.shape[0]:
+                deg = np.bincount(g[:, 0].astype(np.int64))
+                paths += int((deg ** 2).sum())
+        need = max(need, paths)
+    if need > limit:
+        return None
+    return max(need, 1 << 12), max(need, 1 << 12)
+
+
+class BatchGraph:
+    """A fused batch's count per query as a captured join (hc_join_graph) over its
+    resident segmented CoCo: replayed per step, with the per-query counts summed over
+    each query's 2^extra cells on the device."""
+
+    def __init__(self, ctx: hc.Context, shape: str, coco, n_queries: int, extra_bits: int, caps):
+        n, atoms = inputs.QUERIES[shape]
+        seg = int(coco.info.key_bits - coco.info.mix_bits)
+        shares = [0] * n
+        shares[0] = seg + extra_bits
+        self.n_queries = n_queries
+        self.g = hc.JoinGraph(ctx, hc.Query(n, atoms), [coco] * len(atoms), list(range(n)), shares,
+                              mode="cells", cell_group=extra_bits, frontier_cap=caps[0], item_cap=caps[1])
+
+    def launch(self):
+        self.g.launch()
+
+    def result(self):
+        """(per-query counts, replayed)."""
+        _, per, rep = self.g.result()
+        return per[: self.n_queries], rep
+
+    def free(self):
+        self.g.free()
+
+
 def count_sequential(ctx: hc.Context, shape: str, graphs_dev, log2_cells: int = 6):
     """One query per launch: build, choose shares by the cost model, count."""
     n, atoms = inputs.QUERIES[shape]

@@ -502,6 +502,43 @@ hc_status hc_join_emit(hc_ctx* ctx, const hc_query* q, const hc_coco* const* ato
     });
 }
 
+hc_status hc_join_graph_create(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,
+                               const int32_t* var_order, const int32_t* log2_shares, uint32_t flags,
+                               int32_t cell_group, void* out, int64_t capacity, int64_t frontier_cap,
+                               int64_t item_cap, hc_join_graph** graph_out) {
+    if (!ctx) return HC_ERR_INVALID;
+    return guarded(ctx, [&] {
+        check_query_ptrs(q);
+        HC_REQUIRE(atom_index && var_order && graph_out, HC_ERR_INVALID, "NULL argument");
+        *graph_out = nullptr;
+        check_flags(flags, kJoinFlags, "hc_join_graph_create");
+        HC_REQUIRE((flags & ~HC_NO_REWRITE) == 0, HC_ERR_UNSUPPORTED, "captured joins use the default search");
+        HC_REQUIRE(capacity >= 0 && frontier_cap >= 0 && item_cap >= 0, HC_ERR_INVALID, "negative capacity");
+        HC_REQUIRE(out != nullptr || capacity == 0, HC_ERR_INVALID, "capacity without out");
+        for (int j = 0; j < q->n_atoms; ++j) HC_REQUIRE(atom_index[j] != nullptr, HC_ERR_INVALID, "atom CoCo handle is NULL");
+        *graph_out = hc::join_graph_create(ctx, q, atom_index, var_order, log2_shares, flags, cell_group, out, capacity,
+                                           frontier_cap, item_cap);
+    });
+}
+
+hc_status hc_join_graph_launch(hc_join_graph* g) {
+    if (!g) return HC_ERR_INVALID;
+    hc_ctx* ctx = hc::join_graph_ctx(g);
+    return guarded(ctx, [&] { hc::join_graph_launch(g); });
+}
+
+hc_status hc_join_graph_result(hc_join_graph* g, uint64_t* count_out, uint64_t* cell_counts, int64_t* n_out,
+                               int32_t* replayed) {
+    if (!g || !count_out) return HC_ERR_INVALID;
+    hc_ctx* ctx = hc::join_graph_ctx(g);
+    int64_t no = 0;
+    const hc_status st = guarded(ctx, [&] { hc::join_graph_result(g, count_out, cell_counts, &no, replayed); });
+    if (n_out) *n_out = no;
+    return st;
+}
+
+void hc_join_graph_destroy(hc_join_graph* g) { hc::join_graph_destroy(g); }
+
 hc_status hc_plan_describe(const hc_query* q, const int32_t* var_order, uint32_t flags, char* buf, size_t cap) {
     try {
         check_query_ptrs(q);

@@ -269,4 +269,13 @@ uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, co
                               const int32_t* shares, uint32_t flags, int64_t n_queries, int64_t first_width,
                               int64_t cap_entries = kDefaultCap);
 
+// Device-sized joins captured in a HIP graph (join.hip).
+hc_join_graph* join_graph_create(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
+                                 const int32_t* shares, uint32_t flags, int32_t cell_group, void* out,
+                                 int64_t capacity, int64_t frontier_cap, int64_t item_cap);
+void join_graph_launch(hc_join_graph* g);
+void join_graph_result(hc_join_graph* g, uint64_t* count, uint64_t* cell_counts, int64_t* n_out, int32_t* replayed);
+void join_graph_destroy(hc_join_graph* g);
+hc_ctx* join_graph_ctx(const hc_join_graph* g);
+
 }  // namespace hc

@@ -31,6 +31,8 @@
 // the top-level positions of their sources, and referenced by (offset, length)
 // from the entries until the consuming level.
 #include <algorithm>
+#include <cstddef>
+#include <memory>
 
 #include "prim_dev.h"
 
@@ -110,6 +112,21 @@ struct Seg {
     uint32_t* m;       // its length (0 if any operand is empty)
     int64_t stride;
 };
+
+// Sizes of one level in a device-sized launch sequence (a captured graph): each
+// kernel reads the counts the one before it wrote, instead of the host reading
+// them back between launches.
+struct DevSizes {
+    uint64_t n;          // entries of the level's frontier
+    uint64_t total;      // elements of the level (the prefix sum of the entry lengths)
+    uint64_t n_chunks;   // work-queue chunks of the next pass (0: the pass does nothing)
+    uint64_t chunk_sz;   // elements per chunk
+    uint64_t nw;         // match words of the bitmap pass
+    uint64_t got;        // matches
+    unsigned long long queue[8];   // per-XCD work-queue counters
+    uint64_t pad[2];
+};
+static_assert(sizeof(DevSizes) == 128, "DevSizes is two 64-byte lines");
 
 // Id predicate on the value bound by a step: the raw id (the key unmixed) must lie
 // in the step's range and, for entries that carry one, in the entry's own range.
@@ -208,8 +225,10 @@ __device__ inline void v0_bounds(const KData& D, const KOp& op, const int32_t* e
 }
 
 // Resolve every operand of every entry to a [begin, end) range, restricted to the cell.
+// n_dev, when set, holds the entry count instead of n (device-sized sequences).
 __global__ __launch_bounds__(kBlock) void k_prep(KData D, KStep S, const int32_t* __restrict__ F, int64_t e0,
-                                                 int64_t n, Seg G) {
+                                                 int64_t n, Seg G, const uint64_t* __restrict__ n_dev) {
+    if (n_dev) n = (int64_t)*n_dev;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t e = e0 + t;
         const int32_t* ent = F + e * S.W_in;
@@ -777,14 +796,23 @@ __device__ inline int32_t lane_search(int method, const uint32_t* __restrict__ B
 
 // SM = 0: the window method only (the default; the per-element methods are compiled
 // out, which keeps their registers out of the hot loop); SM = 1: the method S.search.
-template <int MODE, int NOPS, int SM>
+// DEV: the entry and element counts, the chunk count and size come from dsz (a
+// device-sized sequence) instead of the arguments.
+template <int MODE, int NOPS, int SM, bool DEV = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_probe2(KData D, KStep S, const int32_t* __restrict__ F, Seg G,
                                                    const uint64_t* __restrict__ prefix, int64_t e_begin,
                                                    int64_t e_end, uint64_t item_begin, uint64_t n_items,
                                                    const int64_t* __restrict__ chunk_entry,
                                                    unsigned long long* queue, uint64_t n_chunks, uint32_t chunk_sz,
                                                    uint64_t* __restrict__ words, unsigned long long* acc,
-                                                   const uint64_t* __restrict__ wprefix, MatOut out) {
+                                                   const uint64_t* __restrict__ wprefix, MatOut out,
+                                                   const DevSizes* __restrict__ dsz = nullptr) {
+    if constexpr (DEV) {
+        e_end = (int64_t)sload(&dsz->n);
+        n_items = sload(&dsz->total);
+        n_chunks = sload(&dsz->n_chunks);
+        chunk_sz = (uint32_t)sload(&dsz->chunk_sz);
+    }
     constexpr bool kMat = mat_mode(MODE);
     constexpr bool kPos = kMat || MODE == M_BITMAP;   // positions in the probed operands are needed
     const int search = SM ? S.search : (int)SEARCH_WINDOW;
@@ -819,6 +847,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
     }
     const int xcd = (int)(blockIdx.x % kXcd);
     const uint64_t c_lo = n_chunks * (uint64_t)xcd / kXcd, c_hi = n_chunks * (uint64_t)(xcd + 1) / kXcd;
+    // A wave whose rank among its XCD's waves reaches the XCD's chunk count would find
+    // the queue empty: it leaves without claiming (a device-sized launch always runs
+    // the full grid, and idle waves contending on the queue counters cost more than
+    // the small launch's work).  The waves that stay claim until the queue is empty.
+    if ((uint64_t)(blockIdx.x / kXcd) * kWaves + (threadIdx.x >> 6) >= c_hi - c_lo) return;
     for (;;) {
         unsigned long long t = 0;
         int stop = 0;
@@ -1869,7 +1902,7 @@ struct Runner {
         B.G.seg = B.seg.p - e0;
         B.G.iter = B.iter.p - e0;
         B.G.m = B.m.p - e0;
-        k_prep<<<grid_for(n), kBlock, 0, s>>>(D, S, F, e0, n, B.G);
+        k_prep<<<grid_for(n), kBlock, 0, s>>>(D, S, F, e0, n, B.G, nullptr);
         HC_HIP(hipGetLastError());
         scan_exclusive(A, LoadU32{B.m.p}, B.prefix.p, n, s);
     }
@@ -2092,11 +2125,11 @@ void Runner::run_level(int i, const int32_t* F, int32_t* Fmut, int64_t n) {
     }
 }
 
-void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order, const int32_t* shares,
-              uint32_t flags, bool emit, uint64_t* count, uint64_t* digest, void* out, int64_t capacity,
-              int64_t* n_out, uint64_t* cell_counts, int64_t n_multi, const int64_t* multi_ranges,
-              const Alloc* alloc, int64_t cap_entries, int cell_group) {
-    Runner R(ctx, alloc ? *alloc : ctx->alloc);
+// Validates a join call and sets R up: plan, CoCo descriptors, shares and cell
+// layout, frontier layouts, steps and the operands' range tables.
+static void setup_runner(Runner& R, hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
+                         const int32_t* shares, uint32_t flags, bool emit, bool digest, void* out, int64_t capacity,
+                         int64_t n_multi, const int64_t* multi_ranges, int64_t cap_entries, bool cell_counts) {
     // A batch of queries has one F_0 entry per query: an intersection of whole top
     // levels lifted to F_0 would be recomputed for every query, so it is not lifted.
     R.P = compile_plan(q, order, !(flags & HC_NO_REWRITE), n_multi > 0 ? 1 : 0);
@@ -2160,7 +2193,7 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
                            "a query's id range spans two segments (query " + std::to_string(t) + ")");
             }
         }
-        HC_REQUIRE(!emit && cell_counts != nullptr && multi_ranges != nullptr, HC_ERR_INVALID,
+        HC_REQUIRE(!emit && cell_counts && multi_ranges != nullptr, HC_ERR_INVALID,
                    "query batches are a per-query counting mode");
         HC_REQUIRE(n_multi <= ((int64_t)1 << 24), HC_ERR_INVALID, "more than 2^24 queries in one batch");
     }
@@ -2191,7 +2224,7 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
     R.D.grid_limit = ctx->grid_limit;
     R.D.dtype64 = dtype64;
     R.emit = emit;
-    R.digest = digest != nullptr;
+    R.digest = digest;
     R.out_rows = out;
     R.out_cap = capacity;
     R.cap_entries = cap_entries > 0 ? cap_entries : kDefaultCap;
@@ -2226,6 +2259,18 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
         R.level_step[0].pred_word = range_word;
     }
     R.refresh_tmp_ptrs();
+}
+
+void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order, const int32_t* shares,
+              uint32_t flags, bool emit, uint64_t* count, uint64_t* digest, void* out, int64_t capacity,
+              int64_t* n_out, uint64_t* cell_counts, int64_t n_multi, const int64_t* multi_ranges,
+              const Alloc* alloc, int64_t cap_entries, int cell_group) {
+    Runner R(ctx, alloc ? *alloc : ctx->alloc);
+    setup_runner(R, ctx, q, atoms, order, shares, flags, emit, digest != nullptr, out, capacity, n_multi, multi_ranges,
+                 cap_entries, cell_counts != nullptr);
+    const Plan& P = R.P;
+    const int K = R.K, b = R.D.b;
+    const int range_word = R.range_word;
     if (ctx->profiling) {
         HC_HIP(hipEventCreate(&R.ev0));
         HC_HIP(hipEventCreate(&R.ev1));
@@ -2410,6 +2455,352 @@ uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, co
         chunk = std::max(kCap, m);
     }
     return (uint64_t)std::min(bytes, 1.8e19);
+}
+
+// ---------------------------------------------------------------- device-sized joins (captured graphs)
+// The same levels as Runner::run_level, with every count read by the kernel that
+// needs it from a DevSizes block the kernel before it wrote: no host read-back
+// between launches, so the whole sequence is captured once in a HIP graph and
+// replayed.  Frontiers and match-word arrays have fixed capacities; a level that
+// exceeds one raises the overflow word, the levels after it see no entries, and
+// the caller's result then comes from the eager path.
+
+// Zero the control words (per-level sizes, overflow word, accumulators) and set
+// F_0's size.
+__global__ void k_graph_start(uint64_t* __restrict__ ctl, int64_t n_ctl, uint64_t n0) {
+    for (int64_t i = threadIdx.x; i < n_ctl; i += blockDim.x) ctl[i] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) ctl[0] = n0;   // DevSizes::n of level 0
+}
+
+__global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// After the entry scan: the level's elements (checked against item_cap when it is
+// nonzero), the chunking of its passes (chosen as launch_probe chooses it, with
+// chunks grown until they fit the chunk table of chunk_cap entries) and the table
+// itself.  Every thread derives the chunking from the scanned total; the first
+// records it and resets the queues.
+__global__ void k_size_chunks(DevSizes* __restrict__ d, const uint64_t* __restrict__ prefix, uint64_t item_cap,
+                              uint64_t chunk_cap, uint64_t min_chunks, unsigned long long* __restrict__ overflow,
+                              int64_t* __restrict__ ce) {
+    const int64_t n = (int64_t)d->n;
+    uint64_t total = prefix[n];
+    const bool over = item_cap && total > item_cap;
+    if (over) total = 0;
+    uint64_t cs = kChunk;
+    while (cs > kMinChunk && total / cs < min_chunks) cs >>= 1;
+    while ((total + cs - 1) / cs > chunk_cap) cs <<= 1;
+    const uint64_t nc = (total + cs - 1) / cs;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (over) *overflow = 1ull;
+        d->total = total;
+        d->chunk_sz = cs;
+        d->n_chunks = nc;
+        d->nw = (total + 63) >> 6;
+        d->got = 0;
+        for (int x = 0; x < kXcd; ++x) d->queue[x] = 0;
+    }
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nc; t += (uint64_t)gridDim.x * blockDim.x)
+        ce[t] = find_entry(prefix, 0, n, t * cs);
+}
+
+// After the match-word scan: the matches, the next frontier's size (checked
+// against its capacity) and a fresh queue for the materialising pass, which does
+// nothing when there is no match or the next frontier would overflow.
+__global__ void k_size_matches(DevSizes* __restrict__ d, DevSizes* __restrict__ next,
+                               const uint64_t* __restrict__ wpre, uint64_t next_cap,
+                               unsigned long long* __restrict__ overflow) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    uint64_t got = wpre[d->nw];
+    d->got = got;
+    if (next) {
+        if (got > next_cap) {
+            *overflow = 1ull;
+            got = 0;
+        }
+        next->n = got;
+    }
+    if (got == 0) d->n_chunks = 0;
+    for (int x = 0; x < kXcd; ++x) d->queue[x] = 0;
+}
+
+static uint64_t persistent_blocks(const KData& D) {
+    return D.grid_limit > 0 ? std::max<uint64_t>(kXcd, (uint64_t)D.grid_limit / kXcd * kXcd) : kPersistBlocks;
+}
+
+// One pass of a level over its elements, every count from d (the grid is the full
+// persistent grid; waves leave when their XCD's queue is empty).
+template <int MODE>
+static void launch_probe_dev(const KData& D, const KStep& S, const int32_t* F, const Seg& G, const uint64_t* prefix,
+                             const int64_t* ce, DevSizes* d, uint64_t* words, unsigned long long* acc,
+                             const uint64_t* wprefix, MatOut out, hipStream_t s) {
+    const unsigned blocks = (unsigned)persistent_blocks(D);
+#define HC_PROBE2D(N)                                                                                     \
+    k_probe2<MODE, N, 0, true><<<blocks, kBlock, 0, s>>>(D, S, F, G, prefix, 0, 0, 0, 0, ce, d->queue, 0, 0, \
+                                                         words, acc, wprefix, out, d)
+    switch (S.n_ops) {
+        case 1: HC_PROBE2D(1); break;
+        case 2: HC_PROBE2D(2); break;
+        case 3: HC_PROBE2D(3); break;
+        default: HC_PROBE2D(4); break;
+    }
+#undef HC_PROBE2D
+    HC_HIP(hipGetLastError());
+}
+
+}  // namespace hc
+
+// Device buffers of one level of a captured join.
+struct GraphLevel {
+    hc::DevBuf<int32_t> F;          // F_i (ecap entries)
+    hc::DevBuf<int32_t> seg, iter;  // prepared ranges and iterated operand
+    hc::DevBuf<uint32_t> m;
+    hc::DevBuf<uint64_t> prefix, scan_ws;
+    hc::DevBuf<int64_t> ce;         // work-queue chunk table
+    hc::DevBuf<uint64_t> words, wpre, wscan_ws;
+    hc::DevBuf<int32_t> pos;        // positions found by the bitmap pass
+    hc::Seg G{};
+    int64_t ecap = 0, ce_cap = 0;
+};
+
+struct hc_join_graph {
+    hc_ctx* ctx = nullptr;
+    std::unique_ptr<hc::Runner> R;
+    // the call, kept for the eager path
+    std::vector<int32_t> arity, vars, order, shares;
+    std::vector<int64_t> lo, hi;
+    hc_query q{};
+    std::vector<const hc_coco*> atoms;
+    uint32_t flags = 0;
+    int32_t cell_group = -1;   // >= 0: per-cell counts in groups of 2^cell_group cells
+    void* out = nullptr;       // emit: device rows
+    int64_t capacity = 0;
+    // capacities and buffers
+    int64_t ncell = 0, ngroup = 0, fcap = 0, icap = 0;
+    std::vector<GraphLevel> lv;
+    hc::DevBuf<uint64_t> ctl;   // DevSizes per level, then the overflow word and 4 accumulators
+    hc::DevBuf<unsigned long long> cells;
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int launched = 0;
+    ~hc_join_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+};
+
+namespace hc {
+
+constexpr int kCtlPerLevel = (int)(sizeof(DevSizes) / sizeof(uint64_t));
+
+static void graph_record(hc_join_graph* g, hipStream_t s) {
+    Runner& R = *g->R;
+    const int nv = R.P.n_vars;
+    uint64_t* ctl = g->ctl.p;
+    auto dsz = [&](int i) { return (DevSizes*)(ctl + (size_t)kCtlPerLevel * i); };
+    unsigned long long* ovf = (unsigned long long*)(ctl + (size_t)kCtlPerLevel * nv);
+    unsigned long long* acc = ovf + 1;
+    const bool emit = g->out != nullptr;
+    const uint64_t min_chunks = persistent_blocks(R.D) * kWaves;
+    k_graph_start<<<1, kBlock, 0, s>>>(ctl, (int64_t)kCtlPerLevel * nv + 8, (uint64_t)g->ncell);
+    HC_HIP(hipGetLastError());
+    if (g->cell_group >= 0) {
+        k_fill_u64<<<grid_for(g->ngroup), kBlock, 0, s>>>(g->cells.p, g->ngroup);
+        HC_HIP(hipGetLastError());
+    }
+    k_init_cells<<<grid_for(g->ncell), kBlock, 0, s>>>(g->lv[0].F.p, g->ncell, R.lay[0].W);
+    HC_HIP(hipGetLastError());
+    for (int i = 0; i < nv; ++i) {
+        GraphLevel& L = g->lv[i];
+        const KStep& S = R.level_step[i];
+        DevSizes* d = dsz(i);
+        const bool leaf = i == nv - 1;
+        const bool bitmap = !leaf || emit;
+        k_prep<<<grid_for(L.ecap, 512), kBlock, 0, s>>>(R.D, S, L.F.p, 0, L.ecap, L.G, &d->n);
+        HC_HIP(hipGetLastError());
+        scan_exclusive_dn(LoadU32{L.m.p}, L.prefix.p, &d->n, L.ecap, L.scan_ws.p, s);
+        k_size_chunks<<<grid_for(L.ce_cap, 512), kBlock, 0, s>>>(d, L.prefix.p, bitmap ? (uint64_t)g->icap : 0,
+                                                                (uint64_t)L.ce_cap, min_chunks, ovf, L.ce.p);
+        HC_HIP(hipGetLastError());
+        if (!bitmap) {
+            if (g->cell_group >= 0) {
+                MatOut mo{};
+                mo.cells = g->cells.p;
+                launch_probe_dev<M_CELLS>(R.D, S, L.F.p, L.G, L.prefix.p, L.ce.p, d, nullptr, acc, nullptr, mo, s);
+            } else {
+                launch_probe_dev<M_COUNT>(R.D, S, L.F.p, L.G, L.prefix.p, L.ce.p, d, nullptr, acc, nullptr, MatOut{},
+                                          s);
+            }
+            continue;
+        }
+        MatOut mb{};
+        mb.pos = L.pos.p;
+        launch_probe_dev<M_BITMAP>(R.D, S, L.F.p, L.G, L.prefix.p, L.ce.p, d, L.words.p, nullptr, nullptr, mb, s);
+        scan_exclusive_dn(LoadPopc{L.words.p}, L.wpre.p, &d->nw, g->icap / 64 + 1, L.wscan_ws.p, s);
+        k_size_matches<<<1, 64, 0, s>>>(d, leaf ? nullptr : dsz(i + 1), L.wpre.p,
+                                        leaf ? 0 : (uint64_t)g->lv[i + 1].ecap, ovf);
+        HC_HIP(hipGetLastError());
+        MatOut mo{};
+        mo.pos = L.pos.p;
+        if (leaf) {
+            mo.rows = g->out;
+            mo.row_base = 0;
+            mo.row_cap = g->capacity;
+            launch_probe_dev<M_EMIT>(R.D, S, L.F.p, L.G, L.prefix.p, L.ce.p, d, L.words.p, nullptr, L.wpre.p, mo, s);
+        } else {
+            mo.F = g->lv[i + 1].F.p;
+            launch_probe_dev<M_EXPAND>(R.D, S, L.F.p, L.G, L.prefix.p, L.ce.p, d, L.words.p, nullptr, L.wpre.p, mo,
+                                       s);
+        }
+    }
+}
+
+hc_join_graph* join_graph_create(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
+                                 const int32_t* shares, uint32_t flags, int32_t cell_group, void* out,
+                                 int64_t capacity, int64_t frontier_cap, int64_t item_cap) {
+    std::unique_ptr<hc_join_graph> g(new hc_join_graph());
+    g->ctx = ctx;
+    // own copies of the call
+    int n_terms = 0;
+    for (int j = 0; j < q->n_atoms; ++j) n_terms += q->atom_arity[j];
+    g->arity.assign(q->atom_arity, q->atom_arity + q->n_atoms);
+    g->vars.assign(q->atom_vars, q->atom_vars + n_terms);
+    g->q = *q;
+    g->q.atom_arity = g->arity.data();
+    g->q.atom_vars = g->vars.data();
+    if (q->var_lo) {
+        g->lo.assign(q->var_lo, q->var_lo + q->n_vars);
+        g->hi.assign(q->var_hi, q->var_hi + q->n_vars);
+        g->q.var_lo = g->lo.data();
+        g->q.var_hi = g->hi.data();
+    }
+    g->atoms.assign(atoms, atoms + q->n_atoms);
+    g->order.assign(order, order + q->n_vars);
+    g->shares.assign((size_t)q->n_vars, 0);
+    if (shares) g->shares.assign(shares, shares + q->n_vars);
+    g->flags = flags;
+    g->cell_group = cell_group;
+    g->out = out;
+    g->capacity = capacity;
+    g->fcap = frontier_cap > 0 ? frontier_cap : (int64_t)1 << 20;
+    g->icap = item_cap > 0 ? item_cap : (int64_t)1 << 22;
+    HC_REQUIRE(g->fcap <= ((int64_t)1 << 28) && g->icap <= ((int64_t)1 << 30), HC_ERR_INVALID,
+               "graph capacities above 2^28 entries or 2^30 elements");
+    HC_REQUIRE(!(out && cell_group >= 0), HC_ERR_INVALID, "a graph either emits rows or counts per cell");
+    g->R.reset(new Runner(ctx, ctx->alloc));
+    Runner& R = *g->R;
+    setup_runner(R, ctx, &g->q, g->atoms.data(), g->order.data(), g->shares.data(), flags, out != nullptr, false,
+                 out, capacity, 0, nullptr, 0, cell_group >= 0);
+    const Plan& P = R.P;
+    HC_REQUIRE(P.n_groups == 0, HC_ERR_UNSUPPORTED,
+               "captured joins take plans without lifted intersections (use HC_NO_REWRITE or the eager calls)");
+    for (int i = 0; i < P.n_vars; ++i)
+        HC_REQUIRE(P.levels[i].n_ops <= 4, HC_ERR_UNSUPPORTED, "captured joins take at most 4 operands per level");
+    HC_REQUIRE(R.search_mode == SEARCH_WINDOW, HC_ERR_UNSUPPORTED, "captured joins use the default search");
+    g->ncell = (int64_t)1 << R.K;
+    HC_REQUIRE(cell_group <= R.K, HC_ERR_INVALID, "cell groups larger than the cells");
+    R.D.cell_group = cell_group > 0 ? cell_group : 0;
+    g->ngroup = cell_group >= 0 ? g->ncell >> cell_group : 0;
+    if (cell_group >= 0) g->cells = DevBuf<unsigned long long>(R.A, (size_t)g->ngroup);
+    const int nv = P.n_vars;
+    g->ctl = DevBuf<uint64_t>(R.A, (size_t)kCtlPerLevel * nv + 8);
+    g->lv.resize((size_t)nv);
+    for (int i = 0; i < nv; ++i) {
+        GraphLevel& L = g->lv[i];
+        const KStep& S = R.level_step[i];
+        const bool leaf = i == nv - 1;
+        const bool bitmap = !leaf || out != nullptr;
+        L.ecap = i == 0 ? g->ncell : g->fcap;
+        L.F = DevBuf<int32_t>(R.A, (size_t)L.ecap * (size_t)R.lay[i].W);
+        L.seg = DevBuf<int32_t>(R.A, (size_t)(2 * S.n_ops) * (size_t)L.ecap);
+        L.iter = DevBuf<int32_t>(R.A, (size_t)L.ecap);
+        L.m = DevBuf<uint32_t>(R.A, (size_t)L.ecap);
+        L.prefix = DevBuf<uint64_t>(R.A, (size_t)L.ecap + 1);
+        L.scan_ws = DevBuf<uint64_t>(R.A, (size_t)scan_dn_ws_size(L.ecap));
+        L.G.stride = L.ecap;
+        L.G.seg = L.seg.p;
+        L.G.iter = L.iter.p;
+        L.G.m = L.m.p;
+        // chunk table: chunks of at least kMinChunk elements over the item capacity,
+        // or (a counting leaf) 2^20 chunks, larger ones beyond 2^32 elements
+        L.ce_cap = bitmap ? g->icap / (int64_t)kMinChunk + 1 : (int64_t)1 << 20;
+        L.ce = DevBuf<int64_t>(R.A, (size_t)L.ce_cap + 1);
+        if (bitmap) {
+            const int64_t nw = g->icap / 64 + 1;
+            L.words = DevBuf<uint64_t>(R.A, (size_t)nw + 1);
+            L.wpre = DevBuf<uint64_t>(R.A, (size_t)nw + 1);
+            L.wscan_ws = DevBuf<uint64_t>(R.A, (size_t)scan_dn_ws_size(nw));
+            L.pos = DevBuf<int32_t>(R.A, (size_t)S.n_ops * (size_t)g->icap);
+        }
+    }
+    HC_HIP(hipStreamCreateWithFlags(&g->cs, hipStreamNonBlocking));
+    HC_HIP(hipStreamBeginCapture(g->cs, hipStreamCaptureModeThreadLocal));
+    try {
+        graph_record(g.get(), g->cs);
+    } catch (...) {
+        hipGraph_t tmp = nullptr;
+        (void)hipStreamEndCapture(g->cs, &tmp);
+        if (tmp) (void)hipGraphDestroy(tmp);
+        throw;
+    }
+    HC_HIP(hipStreamEndCapture(g->cs, &g->graph));
+    HC_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    // the set-up tables were computed on the context's stream, where the replays run
+    return g.release();
+}
+
+void join_graph_launch(hc_join_graph* g) {
+    HC_REQUIRE(!g->ctx->cancel.load(), HC_ERR_CANCELLED, "cancelled");
+    HC_HIP(hipGraphLaunch(g->exec, g->ctx->stream));
+    g->launched = 1;
+}
+
+void join_graph_result(hc_join_graph* g, uint64_t* count, uint64_t* cell_counts, int64_t* n_out, int32_t* replayed) {
+    HC_REQUIRE(g->launched, HC_ERR_INVALID, "hc_join_graph_result before hc_join_graph_launch");
+    hc_ctx* ctx = g->ctx;
+    const int nv = g->R->P.n_vars;
+    std::vector<uint64_t> h((size_t)kCtlPerLevel * nv + 8);
+    HC_HIP(hipMemcpyAsync(h.data(), g->ctl.p, sizeof(uint64_t) * h.size(), hipMemcpyDeviceToHost, ctx->stream));
+    if (cell_counts && g->cell_group >= 0)
+        HC_HIP(hipMemcpyAsync(cell_counts, g->cells.p, sizeof(uint64_t) * (size_t)g->ngroup, hipMemcpyDeviceToHost,
+                              ctx->stream));
+    HC_HIP(hipStreamSynchronize(ctx->stream));
+    g->launched = 0;
+    HC_REQUIRE(!ctx->cancel.load(), HC_ERR_CANCELLED, "cancelled");   // a kernel may have left early
+    const bool ovf = h[(size_t)kCtlPerLevel * nv] != 0;
+    if (!ovf) {
+        const uint64_t got = g->out ? h[(size_t)kCtlPerLevel * (nv - 1) + offsetof(DevSizes, got) / 8]
+                                    : h[(size_t)kCtlPerLevel * nv + 1];
+        *count = got;
+        *n_out = (int64_t)got;
+        if (replayed) *replayed = 1;
+    } else {
+        // a frontier or a level's elements exceeded the capacities: the eager path
+        if (replayed) *replayed = 0;
+        int64_t no = 0;
+        join_run(ctx, &g->q, g->atoms.data(), g->order.data(), g->shares.data(), g->flags, g->out != nullptr, count,
+                 nullptr, g->out, g->capacity, &no, g->cell_group >= 0 ? cell_counts : nullptr, 0, nullptr, nullptr,
+                 0, g->cell_group > 0 ? g->cell_group : 0);
+        if (g->out) *count = (uint64_t)no;
+        *n_out = g->out ? no : (int64_t)*count;
+    }
+    if (g->out && *n_out > g->capacity)
+        fail(HC_ERR_OVERFLOW, "hc_join_graph_result: " + std::to_string(*n_out) + " rows exceed capacity " +
+                                  std::to_string(g->capacity));
+}
+
+hc_ctx* join_graph_ctx(const hc_join_graph* g) { return g->ctx; }
+
+void join_graph_destroy(hc_join_graph* g) {
+    if (!g) return;
+    (void)hipSetDevice(g->ctx->device);
+    (void)hipStreamSynchronize(g->ctx->stream);   // no replay may still use the buffers
+    delete g;
 }
 
 }  // namespace hc

@@ -61,7 +61,7 @@ constexpr int kScanItems = 8;
 constexpr int kScanTile = kBlock * kScanItems;   // 2048 items per workgroup
 
 template <class Load>
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(Load ld, int64_t n, uint64_t* partial) {
+__device__ inline void scan_reduce_tile(Load ld, int64_t n, uint64_t* partial) {
     __shared__ uint64_t lds4[kWaves];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     uint64_t s = 0;
@@ -81,10 +81,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(Load ld, int64_t n, uint
 }
 
 // out[i] = (partial ? partial[block] : 0) + sum of ld(j) for tile_base <= j < i;
-// the last block also writes out[n] = grand total.
+// the block with writes_total set also writes out[n] = grand total.
 template <class Load>
-__global__ __launch_bounds__(kBlock) void k_scan_down(Load ld, int64_t n, const uint64_t* partial,
-                                                      uint64_t* out) {
+__device__ inline void scan_down_tile(Load ld, int64_t n, const uint64_t* partial, uint64_t* out,
+                                      bool writes_total) {
     __shared__ uint64_t tile[kScanTile];
     __shared__ uint64_t lds4[kWaves];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
@@ -111,7 +111,33 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(Load ld, int64_t n, const 
         if (i < n) out[i] = off;
         off += v[k];
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = pb + total;
+    if (writes_total && threadIdx.x == 0) out[n] = pb + total;
+}
+
+template <class Load>
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(Load ld, int64_t n, uint64_t* partial) {
+    scan_reduce_tile(ld, n, partial);
+}
+template <class Load>
+__global__ __launch_bounds__(kBlock) void k_scan_down(Load ld, int64_t n, const uint64_t* partial,
+                                                      uint64_t* out) {
+    scan_down_tile(ld, n, partial, out, blockIdx.x == gridDim.x - 1);
+}
+
+// Device-sized variants: the element count is read from device memory, so the
+// launch sequence does not depend on it (a captured graph); the grid covers a
+// fixed capacity, and blocks past the count write zero partials or leave.  The
+// block holding position n writes out[n].
+template <class Load>
+__global__ __launch_bounds__(kBlock) void k_scan_reduce_dn(Load ld, const uint64_t* n_dev, uint64_t* partial) {
+    scan_reduce_tile(ld, (int64_t)*n_dev, partial);
+}
+template <class Load>
+__global__ __launch_bounds__(kBlock) void k_scan_down_dn(Load ld, const uint64_t* n_dev, const uint64_t* partial,
+                                                         uint64_t* out) {
+    const int64_t n = (int64_t)*n_dev;
+    if ((int64_t)blockIdx.x * kScanTile > n) return;   // block-uniform
+    scan_down_tile(ld, n, partial, out, (int64_t)blockIdx.x == n / kScanTile);
 }
 
 struct LoadU32 {
@@ -144,6 +170,46 @@ void scan_exclusive(const Alloc& a, Load ld, uint64_t* out, int64_t n, hipStream
     HC_HIP(hipGetLastError());
     scan_exclusive(a, LoadU64{part.p}, part.p, nb, s);   // in place: each tile is staged in LDS first
     k_scan_down<Load><<<(unsigned)nb, kBlock, 0, s>>>(ld, n, part.p, out);
+    HC_HIP(hipGetLastError());
+}
+
+// Workspace (u64 values) of scan_exclusive_ws over n elements: the partial sums of
+// every level of the reduce-then-scan recursion.
+inline int64_t scan_ws_size(int64_t n) {
+    if (n <= kScanTile) return 0;
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    return nb + 1 + scan_ws_size(nb);
+}
+// scan_exclusive with its partial sums in a caller-provided workspace (no
+// allocation, so it can be captured in a graph); n > 0.
+template <class Load>
+void scan_exclusive_ws(Load ld, uint64_t* out, int64_t n, uint64_t* ws, hipStream_t s) {
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb <= 1) {
+        k_scan_down<Load><<<1, kBlock, 0, s>>>(ld, n, nullptr, out);
+        HC_HIP(hipGetLastError());
+        return;
+    }
+    k_scan_reduce<Load><<<(unsigned)nb, kBlock, 0, s>>>(ld, n, ws);
+    HC_HIP(hipGetLastError());
+    scan_exclusive_ws(LoadU64{ws}, ws, nb, ws + nb + 1, s);
+    k_scan_down<Load><<<(unsigned)nb, kBlock, 0, s>>>(ld, n, ws, out);
+    HC_HIP(hipGetLastError());
+}
+// Workspace of scan_exclusive_dn for counts up to cap.
+inline int64_t scan_dn_ws_size(int64_t cap) {
+    const int64_t nb = cap / kScanTile + 1;
+    return nb + 1 + scan_ws_size(nb);
+}
+// Exclusive scan of *n_dev <= cap elements (out has cap + 1 entries) with a launch
+// sequence fixed by cap alone.
+template <class Load>
+void scan_exclusive_dn(Load ld, uint64_t* out, const uint64_t* n_dev, int64_t cap, uint64_t* ws, hipStream_t s) {
+    const int64_t nb = cap / kScanTile + 1;
+    k_scan_reduce_dn<Load><<<(unsigned)nb, kBlock, 0, s>>>(ld, n_dev, ws);
+    HC_HIP(hipGetLastError());
+    scan_exclusive_ws(LoadU64{ws}, ws, nb, ws + nb + 1, s);
+    k_scan_down_dn<Load><<<(unsigned)nb, kBlock, 0, s>>>(ld, n_dev, ws, out);
     HC_HIP(hipGetLastError());
 }
 

@@ -91,6 +91,10 @@ SIGNATURES = {
     "hc_join_count_segments": (ctypes.c_int, [P, P, P, P, I32, U32, P, P]),
     "hc_join_workspace_bound": (ctypes.c_int, [P, P, P, P, P, U32, I64, I64, P]),
     "hc_join_count_multi": (ctypes.c_int, [P, P, P, P, U32, I64, P, P]),
+    "hc_join_graph_create": (ctypes.c_int, [P, P, P, P, P, U32, I32, P, I64, I64, I64, P]),
+    "hc_join_graph_launch": (ctypes.c_int, [P]),
+    "hc_join_graph_result": (ctypes.c_int, [P, P, P, P, P]),
+    "hc_join_graph_destroy": (None, [P]),
     "hc_plan_describe": (ctypes.c_int, [P, P, U32, P, ctypes.c_size_t]),
     "hc_plan_cost_from_info": (ctypes.c_int, [P, P, P, P, U32, P, P]),
     "hc_ctx_set_profiling": (ctypes.c_int, [P, ctypes.c_int]),
@@ -429,6 +433,69 @@ def join_emit(ctx: Context, q: Query, cocos, order, log2_shares=None, flags: int
         raise e
     ctx.check(st)
     return out[: n_out.value], int(n_out.value)
+
+
+class JoinGraph:
+    """hc_join_graph_*: a join recorded once as a fixed launch sequence in a HIP graph
+    (frontier sizes stay on the device) and replayed.  mode "count", "cells" (per-cell
+    counts in groups of 2^cell_group cells) or "emit" (rows into `out`, a device tensor
+    [capacity, n_vars] that the graph keeps writing to)."""
+
+    def __init__(self, ctx: Context, q: Query, cocos, order, log2_shares=None, flags: int = 0, mode: str = "count",
+                 cell_group: int = 0, out=None, frontier_cap: int = 0, item_cap: int = 0):
+        assert mode in ("count", "cells", "emit")
+        self.ctx = ctx
+        self.mode = mode
+        self._keep = (list(cocos), out)
+        order_a = _i32(order)
+        sh = _i32(log2_shares) if log2_shares is not None else np.zeros(q.n_vars, np.int32)
+        self.n_cells = (1 << int(sh.sum())) >> (cell_group if mode == "cells" else 0)
+        self.out = out
+        cap = int(out.shape[0]) if (mode == "emit" and out is not None) else 0
+        h = ctypes.c_void_p()
+        qc = q.c()
+        ctx.check(lib().hc_join_graph_create(ctx.h, ctypes.byref(qc), _handles(cocos), order_a.ctypes.data,
+                                             sh.ctypes.data, flags, cell_group if mode == "cells" else -1,
+                                             ctypes.c_void_p(out.data_ptr()) if mode == "emit" else None, cap,
+                                             int(frontier_cap), int(item_cap), ctypes.byref(h)))
+        self.h = h
+
+    def launch(self):
+        """Enqueue one replay on the context's stream."""
+        self.ctx.check(lib().hc_join_graph_launch(self.h))
+
+    def result(self):
+        """Wait for the last replay: (count, per-cell counts or emitted rows or None,
+        replayed) -- replayed is False when a capacity was exceeded and the eager path
+        computed the result."""
+        cnt = ctypes.c_uint64(0)
+        n_out = ctypes.c_int64(0)
+        rep = ctypes.c_int32(0)
+        cells = np.zeros(self.n_cells, dtype=np.uint64) if self.mode == "cells" else None
+        st = lib().hc_join_graph_result(self.h, ctypes.byref(cnt), cells.ctypes.data if cells is not None else None,
+                                        ctypes.byref(n_out), ctypes.byref(rep))
+        if st == HC_ERR_OVERFLOW:
+            e = HCError(st, lib().hc_last_error(self.ctx.h).decode())
+            e.n_out = int(n_out.value)
+            raise e
+        self.ctx.check(st)
+        extra = cells if self.mode == "cells" else (self.out[: n_out.value] if self.mode == "emit" else None)
+        return int(cnt.value), extra, bool(rep.value)
+
+    def run(self):
+        self.launch()
+        return self.result()
+
+    def free(self):
+        if self.h:
+            lib().hc_join_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def plan_cost_from_info(q: Query, infos, order, log2_shares=None, flags: int = 0):
