@@ -142,7 +142,10 @@ __global__ void k_coco_scatter(const uint64_t* __restrict__ K, int64_t n, int ar
     }
 }
 
+// Largest child list: a maximum per block, then one atomic per block (one address
+// takes every atomic, so there are few).
 __global__ void k_max_children(const int32_t* __restrict__ O, int64_t l, unsigned long long* out) {
+    __shared__ unsigned long long wmax[kWaves];
     unsigned long long local = 0;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < l; e += (int64_t)gridDim.x * blockDim.x) {
         const unsigned long long d = (unsigned long long)(O[e + 1] - O[e]);
@@ -152,9 +155,15 @@ __global__ void k_max_children(const int32_t* __restrict__ O, int64_t l, unsigne
         unsigned long long o = __shfl_xor(local, dd, 64);
         local = o > local ? o : local;
     }
-    if ((threadIdx.x & 63) == 0) atomicMax(out, local);
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = local;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kWaves; ++w) local = wmax[w] > local ? wmax[w] : local;
+        atomicMax(out, local);
+    }
 }
 
+// Distinct values of a level with wide keys: one bit per value.
 __global__ void k_bitmap_mark(const uint32_t* __restrict__ V, int64_t l, uint32_t* bitmap) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < l; e += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t v = V[e];
@@ -165,12 +174,26 @@ __global__ void k_bitmap_mark(const uint32_t* __restrict__ V, int64_t l, uint32_
     }
 }
 
-__global__ void k_bitmap_count(const uint32_t* __restrict__ bm, int64_t words, unsigned long long* out) {
+// Distinct values of a level: one byte flag per value, set by plain stores (setting
+// a flag twice is harmless, so no atomics and no test read), then counted.
+__global__ void k_flag_mark(const uint32_t* __restrict__ V, int64_t l, uint8_t* __restrict__ flags) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < l; e += (int64_t)gridDim.x * blockDim.x)
+        flags[V[e]] = 1;
+}
+
+// Adds the set flags of words[0 .. n) (byte flags of 0 or 1, or bitmap bits) to *out.
+__global__ void k_flag_count(const uint32_t* __restrict__ words, int64_t n, unsigned long long* out) {
+    __shared__ unsigned long long wsum[kWaves];
     unsigned long long local = 0;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < words; e += (int64_t)gridDim.x * blockDim.x)
-        local += (unsigned long long)__popc(bm[e]);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        local += (unsigned long long)__popc(words[e]);
     local = wave_sum(local);
-    if ((threadIdx.x & 63) == 0) atomicAdd(out, local);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = local;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kWaves; ++w) local += wsum[w];
+        atomicAdd(out, local);
+    }
 }
 
 // Symmetry check of a binary relation: every key (x, y) must have (y, x).
@@ -287,60 +310,55 @@ void build_coco(hc_ctx* ctx, const void* tuples, int64_t n, int arity, hc_dtype 
     } else {
         for (int r = 0; r + 1 < arity; ++r) HC_HIP(hipMemsetAsync(out->O[r], 0, sizeof(int32_t), s));
     }
-    // statistics: largest child list per level, distinct values per column
-    for (int r = 0; r + 1 < arity; ++r) {
-        HC_HIP(hipMemsetAsync(scal.p + 1, 0, sizeof(unsigned long long), s));
+    // statistics: largest child list per level (scal[1 + r]), distinct values per
+    // column (scal[4 + r]), the symmetry check (bad[1]); read back together
+    HC_REQUIRE(!(flags & HC_BUILD_SYMMETRIC) || arity == 2, HC_ERR_INVALID,
+               "hc_build_coco: HC_BUILD_SYMMETRIC needs a binary relation");
+    for (int r = 0; r + 1 < arity; ++r)
         if (out->level_len[r] > 0) {
-            k_max_children<<<grid_for(out->level_len[r]), kBlock, 0, s>>>(out->O[r], out->level_len[r], scal.p + 1);
+            k_max_children<<<grid_for(out->level_len[r]), kBlock, 0, s>>>(out->O[r], out->level_len[r], scal.p + 1 + r);
             HC_HIP(hipGetLastError());
         }
-        unsigned long long mc = 0;
-        HC_HIP(hipMemcpyAsync(&mc, scal.p + 1, sizeof(mc), hipMemcpyDeviceToHost, s));
-        HC_HIP(hipStreamSynchronize(s));
-        out->max_children[r] = (int64_t)mc;
-    }
-    for (int r = 0; r < arity; ++r) {
-        const int c = out->col_order[r];
-        if (r == 0 || out->level_len[r] == 0) {
-            out->distinct[c] = out->level_len[r];
-            continue;
-        }
-        if (b > 30) {   // bitmap too large to be worth it: upper bound
-            out->distinct[c] = out->level_len[r];
-            continue;
-        }
-        if ((flags & HC_BUILD_SYMMETRIC) && arity == 2) {
-            // a symmetric binary relation holds the same values in both columns (the
-            // symmetry itself is verified below, failing the build otherwise)
-            out->distinct[c] = out->level_len[0];
-            continue;
-        }
-        const int64_t words = ((int64_t)1 << b) / 32 + 1;
-        DevBuf<uint32_t> bm(A, (size_t)words);
-        HC_HIP(hipMemsetAsync(bm.p, 0, sizeof(uint32_t) * words, s));
-        HC_HIP(hipMemsetAsync(scal.p + 2, 0, sizeof(unsigned long long), s));
-        k_bitmap_mark<<<grid_for(out->level_len[r]), kBlock, 0, s>>>(out->V[r], out->level_len[r], bm.p);
-        k_bitmap_count<<<grid_for(words), kBlock, 0, s>>>(bm.p, words, scal.p + 2);
+    bool counted[4] = {false, false, false, false};
+    DevBuf<uint8_t> fl;
+    for (int r = 1; r < arity; ++r) {
+        // the first level's values are distinct; wide keys get the level length as an
+        // upper bound; a symmetric binary relation holds the same values in both
+        // columns (the symmetry itself is verified below, failing the build otherwise)
+        if (out->level_len[r] == 0 || b > 30 || ((flags & HC_BUILD_SYMMETRIC) && arity == 2)) continue;
+        // byte flags (plain stores) up to 2^26 values, a bitmap (atomics) above
+        const bool bytes_ = b <= 26;
+        const int64_t nfl = bytes_ ? ((int64_t)1 << b) : ((int64_t)1 << b) / 8;
+        if (!fl.p) fl = DevBuf<uint8_t>(A, (size_t)nfl + 4);
+        HC_HIP(hipMemsetAsync(fl.p, 0, (size_t)nfl + 4, s));
+        if (bytes_)
+            k_flag_mark<<<grid_for(out->level_len[r]), kBlock, 0, s>>>(out->V[r], out->level_len[r], fl.p);
+        else
+            k_bitmap_mark<<<grid_for(out->level_len[r]), kBlock, 0, s>>>(out->V[r], out->level_len[r],
+                                                                         (uint32_t*)fl.p);
         HC_HIP(hipGetLastError());
-        unsigned long long dc = 0;
-        HC_HIP(hipMemcpyAsync(&dc, scal.p + 2, sizeof(dc), hipMemcpyDeviceToHost, s));
-        HC_HIP(hipStreamSynchronize(s));
-        out->distinct[c] = (int64_t)dc;
+        // a set byte flag and a set bitmap bit both count one (popcount of the words)
+        k_flag_count<<<grid_for(nfl / 4 + 1), kBlock, 0, s>>>((const uint32_t*)fl.p, nfl / 4 + 1, scal.p + 4 + r);
+        HC_HIP(hipGetLastError());
+        counted[r] = true;
     }
+    if ((flags & HC_BUILD_SYMMETRIC) && n > 0) {
+        k_check_symmetric<<<grid_for(n), kBlock, 0, s>>>(keys.p, n, b, bad.p + 1);
+        HC_HIP(hipGetLastError());
+    }
+    unsigned long long st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int sb[2] = {0, 0};
+    HC_HIP(hipMemcpyAsync(st, scal.p, sizeof(st), hipMemcpyDeviceToHost, s));
+    HC_HIP(hipMemcpyAsync(sb, bad.p, sizeof(sb), hipMemcpyDeviceToHost, s));
+    HC_HIP(hipStreamSynchronize(s));
+    for (int r = 0; r + 1 < arity; ++r) out->max_children[r] = (int64_t)st[1 + r];
+    for (int r = 0; r < arity; ++r)
+        out->distinct[out->col_order[r]] = counted[r] ? (int64_t)st[4 + r] : out->level_len[r];
+    if ((flags & HC_BUILD_SYMMETRIC) && arity == 2) out->distinct[out->col_order[1]] = out->level_len[0];
     if (flags & HC_BUILD_SYMMETRIC) {
-        HC_REQUIRE(arity == 2, HC_ERR_INVALID, "hc_build_coco: HC_BUILD_SYMMETRIC needs a binary relation");
-        if (n > 0) {
-            HC_HIP(hipMemsetAsync(bad.p + 1, 0, sizeof(int), s));
-            k_check_symmetric<<<grid_for(n), kBlock, 0, s>>>(keys.p, n, b, bad.p + 1);
-            HC_HIP(hipGetLastError());
-            int sb = 0;
-            HC_HIP(hipMemcpyAsync(&sb, bad.p + 1, sizeof(int), hipMemcpyDeviceToHost, s));
-            HC_HIP(hipStreamSynchronize(s));
-            HC_REQUIRE(!sb, HC_ERR_INVALID, "hc_build_coco: relation is not symmetric");
-        }
+        HC_REQUIRE(!sb[1], HC_ERR_INVALID, "hc_build_coco: relation is not symmetric");
         out->symmetric = 1;
     }
-    HC_HIP(hipStreamSynchronize(s));
 }
 
 // ---------------------------------------------------------------- partition sizes

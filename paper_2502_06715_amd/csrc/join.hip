@@ -717,6 +717,53 @@ __device__ inline int32_t lower_bound32(const uint32_t* __restrict__ B, int32_t 
 // counted.  Returns the bound and, in key, the key there (bhi when it is hi).
 __device__ inline int32_t interp_lb_between(const uint32_t* __restrict__ B, int32_t lo, uint32_t blo, int32_t hi,
                                             uint32_t bhi, uint32_t v, uint32_t& key) {
+    if (hi >= 16) {
+        // 16 keys per probe (four unaligned 16-byte loads in one round trip): a
+        // window [s, s + 16) inside [0, hi] around the interpolated position, or
+        // ending at hi once it covers every key between lo and hi.  The keys below
+        // the value in it give the bound unless they are none (bound below s) or all
+        // (bound above s + 15) of a window that does not reach lo or hi.
+#pragma unroll 1
+        for (int it = 0; it < 6 && hi - lo > 1; ++it) {
+            int32_t s = hi - 16;
+            if (hi - lo > 17) {
+                const float f = (float)(v - blo) * __builtin_amdgcn_rcpf((float)(bhi - blo));
+                const int32_t p = lo + (int32_t)(f * (float)(hi - lo));
+                s = min(max(p - 8, lo + 1), hi - 16);
+            }
+            uint4 w[4];
+            __builtin_memcpy(&w[0], B + s, 16);
+            __builtin_memcpy(&w[1], B + s + 4, 16);
+            __builtin_memcpy(&w[2], B + s + 8, 16);
+            __builtin_memcpy(&w[3], B + s + 12, 16);
+            const uint32_t k[16] = {w[0].x, w[0].y, w[0].z, w[0].w, w[1].x, w[1].y, w[1].z, w[1].w,
+                                    w[2].x, w[2].y, w[2].z, w[2].w, w[3].x, w[3].y, w[3].z, w[3].w};
+            int32_t c = 0;
+#pragma unroll
+            for (int t = 0; t < 16; ++t) c += (s + t <= lo || k[t] < v) ? 1 : 0;   // slots up to lo: another list
+            const bool below = c == 0 && s > lo + 1;
+            const bool above = c == 16 && s + 16 < hi;
+            if (!below && !above) {
+                uint32_t kc = bhi;   // c = 16: the bound is hi
+#pragma unroll
+                for (int t = 0; t < 16; ++t)
+                    if (t == c) kc = k[t];
+                key = kc;
+                return s + c;
+            }
+            if (below) {
+                hi = s;
+                bhi = k[0];
+            } else {
+                lo = s + 15;
+                blo = k[15];
+            }
+        }
+        if (hi - lo == 1) {
+            key = bhi;
+            return hi;
+        }
+    }
 #pragma unroll 1
     for (int it = 0; it < 8 && hi - lo > 4; ++it) {
         const float f = (float)(v - blo) * __builtin_amdgcn_rcpf((float)(bhi - blo));
