@@ -712,41 +712,42 @@ __device__ inline int32_t lower_bound32(const uint32_t* __restrict__ B, int32_t 
 
 // Lower bound of v in a sorted list given B[lo] = blo < v <= bhi = B[hi] (lo < hi):
 // interpolation probes (the keys are hashed, so they spread evenly over the key
-// range and the guess lands near the bound), each one load that narrows [lo, hi];
-// once at most 4 keys remain, the up to 3 between lo and hi are read together and
-// counted.  Returns the bound and, in key, the key there (bhi when it is hi).
+// range and the guess lands near the bound), each reading the 8 keys around its
+// guess in one round trip, which usually hold the bound; near the array's start
+// single-key probes narrow [lo, hi] instead and, once at most 4 keys remain, the up
+// to 3 between lo and hi are read together and counted.  Returns the bound and, in
+// key, the key there (bhi when it is hi).
 __device__ inline int32_t interp_lb_between(const uint32_t* __restrict__ B, int32_t lo, uint32_t blo, int32_t hi,
                                             uint32_t bhi, uint32_t v, uint32_t& key) {
-    if (hi >= 16) {
-        // 16 keys per probe (four unaligned 16-byte loads in one round trip): a
-        // window [s, s + 16) inside [0, hi] around the interpolated position, or
-        // ending at hi once it covers every key between lo and hi.  The keys below
-        // the value in it give the bound unless they are none (bound below s) or all
-        // (bound above s + 15) of a window that does not reach lo or hi.
+    {
+        // 8 keys per probe (two unaligned 16-byte loads in one round trip): a window
+        // [s, s + 8) inside [0, hi] around the interpolated position, or ending at hi
+        // once it covers every key between lo and hi (slots up to lo then belong to
+        // another list and count as below).  The keys below the value in it give the
+        // bound unless they are none (bound below s) or all (bound above s + 7) of a
+        // window that does not reach lo or hi.  Every window starts at or above 0: a
+        // window below the value lowers hi, and the windows stop once hi is below 8.
 #pragma unroll 1
-        for (int it = 0; it < 6 && hi - lo > 1; ++it) {
-            int32_t s = hi - 16;
-            if (hi - lo > 17) {
+        for (int it = 0; it < 8 && hi - lo > 1 && hi >= 8; ++it) {   // (hi drops on a window below)
+            int32_t s = hi - 8;
+            if (hi - lo > 9) {
                 const float f = (float)(v - blo) * __builtin_amdgcn_rcpf((float)(bhi - blo));
                 const int32_t p = lo + (int32_t)(f * (float)(hi - lo));
-                s = min(max(p - 8, lo + 1), hi - 16);
+                s = min(max(p - 4, lo + 1), hi - 8);
             }
-            uint4 w[4];
-            __builtin_memcpy(&w[0], B + s, 16);
-            __builtin_memcpy(&w[1], B + s + 4, 16);
-            __builtin_memcpy(&w[2], B + s + 8, 16);
-            __builtin_memcpy(&w[3], B + s + 12, 16);
-            const uint32_t k[16] = {w[0].x, w[0].y, w[0].z, w[0].w, w[1].x, w[1].y, w[1].z, w[1].w,
-                                    w[2].x, w[2].y, w[2].z, w[2].w, w[3].x, w[3].y, w[3].z, w[3].w};
+            uint4 w0, w1;
+            __builtin_memcpy(&w0, B + s, 16);
+            __builtin_memcpy(&w1, B + s + 4, 16);
+            const uint32_t k[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
             int32_t c = 0;
 #pragma unroll
-            for (int t = 0; t < 16; ++t) c += (s + t <= lo || k[t] < v) ? 1 : 0;   // slots up to lo: another list
+            for (int t = 0; t < 8; ++t) c += (s + t <= lo || k[t] < v) ? 1 : 0;
             const bool below = c == 0 && s > lo + 1;
-            const bool above = c == 16 && s + 16 < hi;
+            const bool above = c == 8 && s + 8 < hi;
             if (!below && !above) {
-                uint32_t kc = bhi;   // c = 16: the bound is hi
+                uint32_t kc = bhi;   // c = 8: the bound is hi
 #pragma unroll
-                for (int t = 0; t < 16; ++t)
+                for (int t = 0; t < 8; ++t)
                     if (t == c) kc = k[t];
                 key = kc;
                 return s + c;
@@ -755,8 +756,8 @@ __device__ inline int32_t interp_lb_between(const uint32_t* __restrict__ B, int3
                 hi = s;
                 bhi = k[0];
             } else {
-                lo = s + 15;
-                blo = k[15];
+                lo = s + 7;
+                blo = k[7];
             }
         }
         if (hi - lo == 1) {
