@@ -1216,7 +1216,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                                         // between fence p - 1 (key below the value) and fence p
                                         // (key xf, at least the value) when that one exists
                                         const int32_t l = c0 + (p[k] - 1) * sp + 1;
-                                        if (!kPos && NOPS <= 3 && SM == 0 && p[k] < nf) {   // (counting levels)
+                                        if (NOPS <= 3 && SM == 0 && p[k] < nf) {
                                             q = interp_lb_between(B, l - 1, win[p[k] - 1], c0 + p[k] * sp, xf[k], a[k],
                                                                   kq);
                                             have = true;
@@ -1410,10 +1410,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
 #pragma unroll
                         for (int o = 0; o < NOPS; ++o) {
                             if (o == il || !found) continue;
-                            // (counting levels with the default method search by interpolation: the
-                            // keys are hashed)
+                            // (the default method searches by interpolation: the keys are hashed)
                             int32_t q;
-                            if (!kPos && SM == 0) {
+                            if (SM == 0) {
                                 uint32_t kq = 0;
                                 q = interp_lb(arr0[o], bl[o], el[o], av, kq);
                                 found = q < el[o] && kq == av;
