@@ -404,9 +404,10 @@ hc_status hc_join_emit(hc_ctx* ctx, const hc_query* q, const hc_coco* const* ato
  *               hc_join_count_segments)
  *   out         device, nullable: emit the rows as hc_join_emit (unsorted) into
  *               capacity rows; then cell_group must be < 0
- * Supported plans: no lifted intersection (HC_NO_REWRITE, or queries whose plan
- * lifts nothing, e.g. the triangle and the 4-cycle), at most 4 operands per
- * level, the default search (flags take HC_NO_REWRITE only).
+ * Lifted intersections (Section 6.1) run on the frontier they are lifted to, each
+ * with at most item_cap elements per call, into a pool of item_cap elements.
+ * Supported plans: at most 4 operands per level and per lifted intersection, the
+ * default search (flags take HC_NO_REWRITE only).
  * Errors: HC_ERR_INVALID (as hc_join_count; capacities above 2^28 entries or
  * 2^30 elements), HC_ERR_UNSUPPORTED (plans outside the above), HC_ERR_OOM,
  * HC_ERR_DEVICE.

@@ -1620,9 +1620,12 @@ static void launch_probe(const Alloc& A, const KData& D, const KStep& S, const i
 }
 
 // (offset, length) of every entry's temporary result, from the match words.
+// (n_dev, when set, holds the entry count: entries [0, *n_dev), device-sized sequences)
 __global__ void k_tmp_refs(int32_t* F, int W, int word, const uint64_t* __restrict__ prefix, int64_t e_begin,
                            int64_t e_end, uint64_t item_begin, const uint64_t* __restrict__ words,
-                           const uint64_t* __restrict__ wprefix, int64_t pool_base) {
+                           const uint64_t* __restrict__ wprefix, int64_t pool_base,
+                           const uint64_t* __restrict__ n_dev = nullptr) {
+    if (n_dev) e_end = e_begin + (int64_t)*n_dev;
     auto rank = [&](uint64_t g) -> uint64_t {
         const uint64_t rel = g - item_begin;
         const uint64_t w = rel >> 6, bit = rel & 63;
@@ -2525,8 +2528,20 @@ __global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n) {
         p[i] = 0;
 }
 
+__global__ void k_copy_u64(uint64_t* __restrict__ dst, const uint64_t* __restrict__ src) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *dst = *src;
+}
+
+// Empties a level once the overflow word is raised: after a lifted intersection that
+// overflowed, the level's entries would reference pool ranges this replay never
+// wrote.
+__global__ void k_drop_on_overflow(uint64_t* __restrict__ n, const unsigned long long* __restrict__ overflow) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && *overflow) *n = 0;
+}
+
 // After the entry scan: the level's elements (checked against item_cap when it is
-// nonzero), the chunking of its passes (chosen as launch_probe chooses it, with
+// nonzero; beyond it the overflow word is raised and the level emptied), the
+// chunking of its passes (chosen as launch_probe chooses it, with
 // chunks grown until they fit the chunk table of chunk_cap entries) and the table
 // itself.  Every thread derives the chunking from the scanned total; the first
 // records it and resets the queues.
@@ -2542,7 +2557,13 @@ __global__ void k_size_chunks(DevSizes* __restrict__ d, const uint64_t* __restri
     while ((total + cs - 1) / cs > chunk_cap) cs <<= 1;
     const uint64_t nc = (total + cs - 1) / cs;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        if (over) *overflow = 1ull;
+        if (over) {
+            // the level's entries are dropped too, so no later kernel of the sequence
+            // reads their element ranks (other threads then read n = 0 or an n whose
+            // total overflows: either way no chunk)
+            *overflow = 1ull;
+            d->n = 0;
+        }
         d->total = total;
         d->chunk_sz = cs;
         d->n_chunks = nc;
@@ -2628,7 +2649,9 @@ struct hc_join_graph {
     // capacities and buffers
     int64_t ncell = 0, ngroup = 0, fcap = 0, icap = 0;
     std::vector<GraphLevel> lv;
-    hc::DevBuf<uint64_t> ctl;   // DevSizes per level, then the overflow word and 4 accumulators
+    std::vector<GraphLevel> grp;   // per lifted intersection: its step's buffers (F unused)
+    hc::DevBuf<uint64_t> ctl;   // DevSizes per level and per lifted intersection, then the
+                                // overflow word and 4 accumulators
     hc::DevBuf<unsigned long long> cells;
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;
@@ -2647,14 +2670,14 @@ constexpr int kCtlPerLevel = (int)(sizeof(DevSizes) / sizeof(uint64_t));
 
 static void graph_record(hc_join_graph* g, hipStream_t s) {
     Runner& R = *g->R;
-    const int nv = R.P.n_vars;
+    const int nv = R.P.n_vars, ng = R.P.n_groups;
     uint64_t* ctl = g->ctl.p;
-    auto dsz = [&](int i) { return (DevSizes*)(ctl + (size_t)kCtlPerLevel * i); };
-    unsigned long long* ovf = (unsigned long long*)(ctl + (size_t)kCtlPerLevel * nv);
+    auto dsz = [&](int i) { return (DevSizes*)(ctl + (size_t)kCtlPerLevel * i); };   // groups at nv + g
+    unsigned long long* ovf = (unsigned long long*)(ctl + (size_t)kCtlPerLevel * (nv + ng));
     unsigned long long* acc = ovf + 1;
     const bool emit = g->out != nullptr;
     const uint64_t min_chunks = persistent_blocks(R.D) * kWaves;
-    k_graph_start<<<1, kBlock, 0, s>>>(ctl, (int64_t)kCtlPerLevel * nv + 8, (uint64_t)g->ncell);
+    k_graph_start<<<1, kBlock, 0, s>>>(ctl, (int64_t)kCtlPerLevel * (nv + ng) + 8, (uint64_t)g->ncell);
     HC_HIP(hipGetLastError());
     if (g->cell_group >= 0) {
         k_fill_u64<<<grid_for(g->ngroup), kBlock, 0, s>>>(g->cells.p, g->ngroup);
@@ -2668,6 +2691,41 @@ static void graph_record(hc_join_graph* g, hipStream_t s) {
         DevSizes* d = dsz(i);
         const bool leaf = i == nv - 1;
         const bool bitmap = !leaf || emit;
+        // lifted intersections computed on this frontier (Section 6.1): the same
+        // passes as a level over the group's operands, their matches written to the
+        // group's pool, and every entry's (offset, length) into its words
+        for (int gi = 0; gi < ng; ++gi) {
+            if (R.P.groups[gi].lift != i) continue;
+            GraphLevel& GG = g->grp[gi];
+            const KStep& GS = R.group_step[gi];
+            DevSizes* dg = dsz(nv + gi);
+            k_copy_u64<<<1, 64, 0, s>>>(&dg->n, &d->n);
+            HC_HIP(hipGetLastError());
+            k_prep<<<grid_for(L.ecap, 512), kBlock, 0, s>>>(R.D, GS, L.F.p, 0, L.ecap, GG.G, &dg->n);
+            HC_HIP(hipGetLastError());
+            scan_exclusive_dn(LoadU32{GG.m.p}, GG.prefix.p, &dg->n, L.ecap, GG.scan_ws.p, s);
+            k_size_chunks<<<grid_for(GG.ce_cap, 512), kBlock, 0, s>>>(dg, GG.prefix.p, (uint64_t)g->icap,
+                                                                     (uint64_t)GG.ce_cap, min_chunks, ovf, GG.ce.p);
+            HC_HIP(hipGetLastError());
+            MatOut gb{};
+            gb.pos = GG.pos.p;
+            launch_probe_dev<M_BITMAP>(R.D, GS, L.F.p, GG.G, GG.prefix.p, GG.ce.p, dg, GG.words.p, nullptr, nullptr, gb,
+                                       s);
+            scan_exclusive_dn(LoadPopc{GG.words.p}, GG.wpre.p, &dg->nw, g->icap / 64 + 1, GG.wscan_ws.p, s);
+            k_size_matches<<<1, 64, 0, s>>>(dg, nullptr, GG.wpre.p, 0, ovf);
+            HC_HIP(hipGetLastError());
+            MatOut gt{};
+            gt.pos = GG.pos.p;
+            gt.tval = R.tmp_val[gi].p;
+            for (int u = 0; u < GS.n_src; ++u) gt.tsrc[u] = R.tmp_src[gi][u].p;
+            launch_probe_dev<M_TMPW>(R.D, GS, L.F.p, GG.G, GG.prefix.p, GG.ce.p, dg, GG.words.p, nullptr, GG.wpre.p,
+                                     gt, s);
+            k_tmp_refs<<<grid_for(L.ecap, 512), kBlock, 0, s>>>(L.F.p, R.lay[i].W, R.lay[i].tmp_word[gi], GG.prefix.p,
+                                                                0, 0, 0, GG.words.p, GG.wpre.p, 0, &dg->n);
+            HC_HIP(hipGetLastError());
+            k_drop_on_overflow<<<1, 64, 0, s>>>(&d->n, ovf);
+            HC_HIP(hipGetLastError());
+        }
         k_prep<<<grid_for(L.ecap, 512), kBlock, 0, s>>>(R.D, S, L.F.p, 0, L.ecap, L.G, &d->n);
         HC_HIP(hipGetLastError());
         scan_exclusive_dn(LoadU32{L.m.p}, L.prefix.p, &d->n, L.ecap, L.scan_ws.p, s);
@@ -2744,10 +2802,11 @@ hc_join_graph* join_graph_create(hc_ctx* ctx, const hc_query* q, const hc_coco* 
     setup_runner(R, ctx, &g->q, g->atoms.data(), g->order.data(), g->shares.data(), flags, out != nullptr, false,
                  out, capacity, 0, nullptr, 0, cell_group >= 0);
     const Plan& P = R.P;
-    HC_REQUIRE(P.n_groups == 0, HC_ERR_UNSUPPORTED,
-               "captured joins take plans without lifted intersections (use HC_NO_REWRITE or the eager calls)");
     for (int i = 0; i < P.n_vars; ++i)
         HC_REQUIRE(P.levels[i].n_ops <= 4, HC_ERR_UNSUPPORTED, "captured joins take at most 4 operands per level");
+    for (int gi = 0; gi < P.n_groups; ++gi)
+        HC_REQUIRE(P.groups[gi].n_ops <= 4, HC_ERR_UNSUPPORTED,
+                   "captured joins take at most 4 operands per lifted intersection");
     HC_REQUIRE(R.search_mode == SEARCH_WINDOW, HC_ERR_UNSUPPORTED, "captured joins use the default search");
     g->ncell = (int64_t)1 << R.K;
     HC_REQUIRE(cell_group <= R.K, HC_ERR_INVALID, "cell groups larger than the cells");
@@ -2755,7 +2814,7 @@ hc_join_graph* join_graph_create(hc_ctx* ctx, const hc_query* q, const hc_coco* 
     g->ngroup = cell_group >= 0 ? g->ncell >> cell_group : 0;
     if (cell_group >= 0) g->cells = DevBuf<unsigned long long>(R.A, (size_t)g->ngroup);
     const int nv = P.n_vars;
-    g->ctl = DevBuf<uint64_t>(R.A, (size_t)kCtlPerLevel * nv + 8);
+    g->ctl = DevBuf<uint64_t>(R.A, (size_t)kCtlPerLevel * (nv + P.n_groups) + 8);
     g->lv.resize((size_t)nv);
     for (int i = 0; i < nv; ++i) {
         GraphLevel& L = g->lv[i];
@@ -2785,6 +2844,32 @@ hc_join_graph* join_graph_create(hc_ctx* ctx, const hc_query* q, const hc_coco* 
             L.pos = DevBuf<int32_t>(R.A, (size_t)S.n_ops * (size_t)g->icap);
         }
     }
+    // lifted intersections: step buffers over the frontier they are lifted to, and a
+    // pool of item_cap elements (with the positions of its sources)
+    g->grp.resize((size_t)P.n_groups);
+    for (int gi = 0; gi < P.n_groups; ++gi) {
+        GraphLevel& GG = g->grp[gi];
+        const KStep& GS = R.group_step[gi];
+        const int64_t ecap = g->lv[(size_t)P.groups[gi].lift].ecap;
+        GG.ecap = ecap;
+        GG.seg = DevBuf<int32_t>(R.A, (size_t)(2 * GS.n_ops) * (size_t)ecap);
+        GG.iter = DevBuf<int32_t>(R.A, (size_t)ecap);
+        GG.m = DevBuf<uint32_t>(R.A, (size_t)ecap);
+        GG.prefix = DevBuf<uint64_t>(R.A, (size_t)ecap + 1);
+        GG.scan_ws = DevBuf<uint64_t>(R.A, (size_t)scan_dn_ws_size(ecap));
+        GG.G.stride = ecap;
+        GG.G.seg = GG.seg.p;
+        GG.G.iter = GG.iter.p;
+        GG.G.m = GG.m.p;
+        GG.ce_cap = g->icap / (int64_t)kMinChunk + 1;
+        GG.ce = DevBuf<int64_t>(R.A, (size_t)GG.ce_cap + 1);
+        const int64_t nw = g->icap / 64 + 1;
+        GG.words = DevBuf<uint64_t>(R.A, (size_t)nw + 1);
+        GG.wpre = DevBuf<uint64_t>(R.A, (size_t)nw + 1);
+        GG.wscan_ws = DevBuf<uint64_t>(R.A, (size_t)scan_dn_ws_size(nw));
+        GG.pos = DevBuf<int32_t>(R.A, (size_t)GS.n_ops * (size_t)g->icap);
+        R.grow_tmp(gi, g->icap);   // the pool (also sets the kernels' pool pointers)
+    }
     HC_HIP(hipStreamCreateWithFlags(&g->cs, hipStreamNonBlocking));
     HC_HIP(hipStreamBeginCapture(g->cs, hipStreamCaptureModeThreadLocal));
     try {
@@ -2810,8 +2895,8 @@ void join_graph_launch(hc_join_graph* g) {
 void join_graph_result(hc_join_graph* g, uint64_t* count, uint64_t* cell_counts, int64_t* n_out, int32_t* replayed) {
     HC_REQUIRE(g->launched, HC_ERR_INVALID, "hc_join_graph_result before hc_join_graph_launch");
     hc_ctx* ctx = g->ctx;
-    const int nv = g->R->P.n_vars;
-    std::vector<uint64_t> h((size_t)kCtlPerLevel * nv + 8);
+    const int nv = g->R->P.n_vars, nc = nv + g->R->P.n_groups;
+    std::vector<uint64_t> h((size_t)kCtlPerLevel * nc + 8);
     HC_HIP(hipMemcpyAsync(h.data(), g->ctl.p, sizeof(uint64_t) * h.size(), hipMemcpyDeviceToHost, ctx->stream));
     if (cell_counts && g->cell_group >= 0)
         HC_HIP(hipMemcpyAsync(cell_counts, g->cells.p, sizeof(uint64_t) * (size_t)g->ngroup, hipMemcpyDeviceToHost,
@@ -2819,10 +2904,10 @@ void join_graph_result(hc_join_graph* g, uint64_t* count, uint64_t* cell_counts,
     HC_HIP(hipStreamSynchronize(ctx->stream));
     g->launched = 0;
     HC_REQUIRE(!ctx->cancel.load(), HC_ERR_CANCELLED, "cancelled");   // a kernel may have left early
-    const bool ovf = h[(size_t)kCtlPerLevel * nv] != 0;
+    const bool ovf = h[(size_t)kCtlPerLevel * nc] != 0;
     if (!ovf) {
         const uint64_t got = g->out ? h[(size_t)kCtlPerLevel * (nv - 1) + offsetof(DevSizes, got) / 8]
-                                    : h[(size_t)kCtlPerLevel * nv + 1];
+                                    : h[(size_t)kCtlPerLevel * nc + 1];
         *count = got;
         *n_out = (int64_t)got;
         if (replayed) *replayed = 1;

@@ -178,23 +178,110 @@ def test_graph_overflow_falls_back_exactly(ctx):
     g.free()
 
 
-def test_graph_clique4_without_rewrite_and_unsupported_plans(ctx):
-    """The 4-clique without the rewriting (three operands at the deepest level) is
-    captured; with the rewriting (a lifted intersection) and with a per-element search
-    method the call is HC_ERR_UNSUPPORTED."""
+def test_graph_clique4_rewritten_and_plain(ctx):
+    """The 4-clique with the rewriting (its lifted intersections run inside the
+    graph, pools and (offset, length) words included) and without it (three operands
+    at the deepest level): counts, per-cell counts and emitted rows against the
+    oracle; capacities below the lifted intersections' sizes fall back exactly; a
+    per-element search method is HC_ERR_UNSUPPORTED."""
+    import torch
     E = inputs.chung_lu(2048, 12000, 77)
     n, atoms = inputs.QUERIES["clique4"]
     c = hc.build_coco(ctx, _dev(E), [0, 1], key_bits=11, seed=SEED, symmetric=True)
     q = hc.Query(n, atoms)
-    expect = oracle.gj(n, atoms, [E] * 6).count
-    g = hc.JoinGraph(ctx, q, [c] * 6, [0, 1, 2, 3], [1, 1, 1, 0], flags=hc.HC_NO_REWRITE)
-    for _ in range(2):
-        cnt, _, rep = g.run()
-        assert rep and cnt == expect
+    exp = oracle.gj(n, atoms, [E] * 6, emit=True)
+    assert exp.count > 0
+    for flags, shares in ((0, [1, 1, 1, 0]), (hc.HC_NO_REWRITE, [1, 1, 1, 0]), (0, [0, 0, 0, 0])):
+        log("graph clique4 flags=%d shares=%s" % (flags, shares))
+        g = hc.JoinGraph(ctx, q, [c] * 6, [0, 1, 2, 3], shares, flags=flags)
+        for _ in range(2):
+            cnt, _, rep = g.run()
+            assert rep and cnt == exp.count
+        g.free()
+        want, _ = cells.cells(n, atoms, [E] * 6, shares, 11, SEED, order=[0, 1, 2, 3])
+        g = hc.JoinGraph(ctx, q, [c] * 6, [0, 1, 2, 3], shares, flags=flags, mode="cells", cell_group=0)
+        tot, per, rep = g.run()
+        assert rep and tot == exp.count and np.array_equal(per, want)
+        g.free()
+        # emitting materialises the deepest level: without the rewriting its three-operand
+        # elements exceed the default item capacity
+        out = torch.empty((exp.count + 2, n), dtype=torch.int32, device="cuda:0")
+        g = hc.JoinGraph(ctx, q, [c] * 6, [0, 1, 2, 3], shares, flags=flags, mode="emit", out=out,
+                         item_cap=1 << 25)
+        cnt, rows, rep = g.run()
+        assert cnt == exp.count
+        assert np.array_equal(sort_rows(rows.cpu().numpy()), exp.rows)
+        assert rep
+        g.free()
+    g = hc.JoinGraph(ctx, q, [c] * 6, [0, 1, 2, 3], [0, 0, 0, 0], item_cap=256)
+    cnt, _, rep = g.run()
+    assert not rep and cnt == exp.count
     g.free()
-    with pytest.raises(hc.HCError) as ei:
-        hc.JoinGraph(ctx, q, [c] * 6, [0, 1, 2, 3], [0, 0, 0, 0])
-    assert ei.value.status == hc.HC_ERR_UNSUPPORTED
     with pytest.raises(hc.HCError) as ei:
         hc.JoinGraph(ctx, q, [c] * 6, [0, 1, 2, 3], [0, 0, 0, 0], flags=hc.HC_NO_REWRITE | hc.HC_SEARCH_EXPONENTIAL)
     assert ei.value.status == hc.HC_ERR_UNSUPPORTED
+
+
+def _atom_cocos(ctx, atoms, rels, var_order, b, seed=0):
+    import torch
+    pos = {v: i for i, v in enumerate(var_order)}
+    out = []
+    for a, r in zip(atoms, rels):
+        co = sorted(range(len(a)), key=lambda c: pos[a[c]])
+        out.append(hc.build_coco(ctx, torch.from_numpy(np.ascontiguousarray(r)).to("cuda:0"), co, key_bits=b,
+                                 seed=seed))
+    return out
+
+
+def test_graph_int64_ids_count_cells_and_emit(ctx):
+    """Ids above 2^31 stored as int64 (three different relations): a replay's count,
+    per-cell counts and emitted int64 rows against the oracle."""
+    import torch
+    n, atoms = inputs.QUERIES["triangle"]
+    base = (1 << 31) + 12345
+    rels = [inputs.random_relation(600 + 40 * j, 60, 610 + j).astype(np.int64) * 7919 + base for j in range(3)]
+    exp = oracle.gj(n, atoms, rels, emit=True)
+    assert exp.count > 0
+    for order, shares in (([0, 1, 2], [0, 0, 0]), ([2, 1, 0], [2, 1, 3])):
+        cocos = _atom_cocos(ctx, atoms, rels, order, 32, seed=SEED)
+        assert cocos[0].info.dtype == hc.HC_I64
+        q = hc.Query(n, atoms)
+        log("graph int64 order=%s shares=%s" % (order, shares))
+        g = hc.JoinGraph(ctx, q, cocos, order, shares)
+        cnt, _, rep = g.run()
+        assert rep and cnt == exp.count
+        g.free()
+        want, _ = cells.cells(n, atoms, rels, shares, 32, SEED, order=order)
+        g = hc.JoinGraph(ctx, q, cocos, order, shares, mode="cells", cell_group=0)
+        tot, per, rep = g.run()
+        assert rep and tot == exp.count and np.array_equal(per, want)
+        g.free()
+        out = torch.empty((exp.count + 5, n), dtype=torch.int64, device="cuda:0")
+        g = hc.JoinGraph(ctx, q, cocos, order, shares, mode="emit", out=out)
+        cnt, rows, rep = g.run()
+        assert rep and cnt == exp.count
+        assert np.array_equal(sort_rows(rows.cpu().numpy()), exp.rows)
+        g.free()
+
+
+def test_graph_range_predicates_equal_oracle(ctx):
+    """Range predicates on every variable (pushed into the levels): replayed counts and
+    rows against the oracle with the same predicates, for two ranges per query."""
+    import torch
+    E = config_graph(1)
+    n, atoms = inputs.QUERIES["triangle"]
+    c = hc.build_coco(ctx, _dev(E), [0, 1], symmetric=True)
+    for lo, hi in (([100, 0, 50], [900, 3000, 4096]), ([0, 2000, 0], [4096, 4096, 1500])):
+        exp = oracle.gj(n, atoms, [E] * 3, lo=lo, hi=hi, emit=True)
+        q = hc.Query(n, atoms, lo, hi)
+        log("graph predicates lo=%s hi=%s: %d rows" % (lo, hi, exp.count))
+        g = hc.JoinGraph(ctx, q, [c] * 3, [0, 1, 2], [0, 0, 0])
+        cnt, _, rep = g.run()
+        assert rep and cnt == exp.count
+        g.free()
+        out = torch.empty((exp.count + 1, n), dtype=torch.int32, device="cuda:0")
+        g = hc.JoinGraph(ctx, q, [c] * 3, [0, 1, 2], [0, 0, 0], mode="emit", out=out)
+        cnt, rows, rep = g.run()
+        assert rep and cnt == exp.count
+        assert np.array_equal(sort_rows(rows.cpu().numpy()), exp.rows)
+        g.free()
