@@ -226,17 +226,40 @@ def bench_batch(args):
 
 def _batch_resident(ctx, groups, graphs, expect, steps):
     """The batched joins over segmented CoCos built once (resident indexes): a step
-    of eager fused counts against a step of captured joins (hc_join_graph_*) for the
-    groups whose frontier capacities (batch.graph_caps) fit, eager for the rest;
-    per-query counts checked on every step."""
+    of eager fused counts against a step where each group runs as the autotuner
+    chose it: a captured join (hc_join_graph_*) when its frontier capacities
+    (batch.graph_caps) fit and a replay beats the eager count, else eager; per-query
+    counts checked on every step."""
     import torch
     from paper_2502_06715_amd import batch, hc
-    cocos, graphs_of = {}, {}
+    cocos, graphs_of, choice = {}, {}, {}
     for key, g in groups.items():
         cocos[key] = hc.build_coco(ctx, g["rel"], [0, 1], key_bits=g["mb"], segment_bits=g["seg"], symmetric=True)
         caps = batch.graph_caps(key[0], [graphs[i] for i in g["idx"]])
-        if caps is not None:
-            graphs_of[key] = batch.BatchGraph(ctx, key[0], cocos[key], g["n"], g["extra"], caps)
+        choice["%s/%d" % key] = "eager (capacities)"
+        if caps is None:
+            continue
+        bg = batch.BatchGraph(ctx, key[0], cocos[key], g["n"], g["extra"], caps)
+        # the autotuner's choice for the class: the captured join when a replay is the
+        # faster of the two (both timed once after a warm-up call)
+        tm = {}
+        for name in ("eager", "captured"):
+            for rep in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if name == "eager":
+                    batch.count_batched(ctx, key[0], g["rel"], g["n"], g["mb"], g["seg"], extra_bits=g["extra"],
+                                        coco=cocos[key], method=g["method"])
+                else:
+                    bg.launch()
+                    bg.result()
+                tm[name] = time.perf_counter() - t0
+        choice["%s/%d" % key] = "captured" if tm["captured"] < tm["eager"] else "eager"
+        choice["%s/%d" % key] += " (%.2f / %.2f ms)" % (1e3 * tm["captured"], 1e3 * tm["eager"])
+        if tm["captured"] < tm["eager"]:
+            graphs_of[key] = bg
+        else:
+            bg.free()
 
     def eager_step():
         got = np.zeros(expect.shape[0], dtype=np.uint64)
@@ -260,7 +283,7 @@ def _batch_resident(ctx, groups, graphs, expect, steps):
                                                     extra_bits=g["extra"], coco=cocos[key], method=g["method"])
         return got
 
-    out = {"captured_groups": ["%s/%d" % k for k in graphs_of]}
+    out = {"captured_groups": ["%s/%d" % k for k in graphs_of], "choice_captured_over_eager_ms": choice}
     for name, fn in (("eager", eager_step), ("captured", graph_step)):
         fn()
         torch.cuda.synchronize()

@@ -102,7 +102,7 @@ def count_batched(ctx: hc.Context, shape: str, rel_dev, n_queries: int, mix_bits
     return per_query[:n_queries]
 
 
-def graph_caps(shape: str, graphs, limit: int = 1 << 26):
+def graph_caps(shape: str, graphs, limit: int = 1 << 28):
     """Exact frontier and element capacities of a fused batch's captured join (order
     0..n-1, only the first variable split, so no frontier entry is replicated), from
     the degrees: the triangle's frontiers and materialised levels hold at most the
