@@ -11,6 +11,7 @@ from __future__ import annotations
 import ctypes
 import json
 import os
+import weakref
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -164,6 +165,7 @@ class Context:
         self._sptr = sptr
         self.max_bytes = int(max_bytes)
         self.live = {}
+        self._graphs = weakref.WeakSet()   # captured joins on this context, released before it
         self.alloc_error = None   # why the allocator last refused a request
         self.n_allocs = 0         # requests the library made through this context's allocator
         if use_torch_allocator:
@@ -183,7 +185,10 @@ class Context:
 
             def _free(ptr, user):
                 self.live.pop(ptr, None)
-                torch.cuda.caching_allocator_delete(ptr)
+                cuda = getattr(torch, "cuda", None)
+                if cuda is None:   # interpreter shutdown: torch is gone, the process ends
+                    return
+                cuda.caching_allocator_delete(ptr)
 
             self._cb = (_ALLOC(_alloc), _FREE(_free))
         else:
@@ -223,6 +228,8 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
+            for g in list(getattr(self, "_graphs", ())):
+                g.free()   # a graph uses the context's stream and allocator
             lib().hc_ctx_destroy(self.h)
             self.h = None
 
@@ -459,6 +466,7 @@ class JoinGraph:
                                              ctypes.c_void_p(out.data_ptr()) if mode == "emit" else None, cap,
                                              int(frontier_cap), int(item_cap), ctypes.byref(h)))
         self.h = h
+        ctx._graphs.add(self)
 
     def launch(self):
         """Enqueue one replay on the context's stream."""
@@ -487,9 +495,10 @@ class JoinGraph:
         return self.result()
 
     def free(self):
-        if self.h:
+        # (a closed context has released the graph already)
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
             lib().hc_join_graph_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:
