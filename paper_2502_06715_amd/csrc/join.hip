@@ -2523,7 +2523,7 @@ __global__ void k_graph_start(uint64_t* __restrict__ ctl, int64_t n_ctl, uint64_
     if (threadIdx.x == 0) ctl[0] = n0;   // DevSizes::n of level 0
 }
 
-__global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n) {
+__global__ void k_zero_u64(unsigned long long* __restrict__ p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0;
 }
@@ -2680,7 +2680,7 @@ static void graph_record(hc_join_graph* g, hipStream_t s) {
     k_graph_start<<<1, kBlock, 0, s>>>(ctl, (int64_t)kCtlPerLevel * (nv + ng) + 8, (uint64_t)g->ncell);
     HC_HIP(hipGetLastError());
     if (g->cell_group >= 0) {
-        k_fill_u64<<<grid_for(g->ngroup), kBlock, 0, s>>>(g->cells.p, g->ngroup);
+        k_zero_u64<<<grid_for(g->ngroup), kBlock, 0, s>>>(g->cells.p, g->ngroup);
         HC_HIP(hipGetLastError());
     }
     k_init_cells<<<grid_for(g->ncell), kBlock, 0, s>>>(g->lv[0].F.p, g->ncell, R.lay[0].W);
