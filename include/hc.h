@@ -43,7 +43,7 @@ typedef enum {
     HC_ERR_OOM = 2,          /* the allocator refused a request */
     HC_ERR_OVERFLOW = 3,     /* emit: more result rows than the capacity */
     HC_ERR_DEVICE = 4,       /* a HIP runtime call or a device-side check failed */
-    HC_ERR_UNSUPPORTED = 5,  /* valid but outside what this build implements */
+    HC_ERR_UNSUPPORTED = 5,  /* valid but outside what the library implements */
     HC_ERR_CANCELLED = 6     /* the context's cancel request stopped the call */
 } hc_status;
 
