@@ -953,16 +953,17 @@ def main():
 
 
 def bench_captured_join(ctx, q, E_dev, b, atoms, order, shares, expect, rows_buf, reps=50):
-    """The join of the step (count and full output) over a resident CoCo, eager against
-    replays of the captured launch sequences (hc_join_graph_*: frontier sizes stay on
-    the device, no host round trip between levels); every result checked."""
+    """The join of the step (count and full output) over a resident CoCo: the
+    library's count and emit calls (which run a join this small as the device-sized
+    sequence, launched directly) against replays of the same sequences captured in
+    HIP graphs (hc_join_graph_*); every result checked."""
     import torch
     from paper_2502_06715_amd import hc
     coco = hc.build_coco(ctx, E_dev, [0, 1], key_bits=b)
     cocos = [coco] * len(atoms)
     ctx.set_profiling(False)
 
-    def eager():
+    def calls():
         cnt = hc.join_count(ctx, q, cocos, order, shares)
         _, n_out = hc.join_emit(ctx, q, cocos, order, shares, out=rows_buf)
         return cnt, n_out
@@ -980,7 +981,7 @@ def bench_captured_join(ctx, q, E_dev, b, atoms, order, shares, expect, rows_buf
         return c, n
 
     out = {}
-    for name, fn in (("eager", eager), ("graph", graph)):
+    for name, fn in (("calls", calls), ("graph", graph)):
         for _ in range(3):
             fn()
         torch.cuda.synchronize()

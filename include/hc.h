@@ -275,6 +275,12 @@ hc_status hc_plan_cost_from_info(const hc_query* q, const hc_coco_info* infos, c
  *                h(t) = F(...F(F(c ^ (t_0 + G)) ^ (t_1 + 2G))...), F the
  *                SplitMix64 finaliser, c = 0x6A09E667F3BCC909, G = 0x9E3779B97F4A7C15)
  * flags: HC_NO_REWRITE, HC_SEARCH_*.
+ * A join whose CoCo statistics bound every frontier below 2^20 entries and every
+ * level below 2^23 elements (entries times the longest list of the level's
+ * shortest operand), with the default search and no digest, runs the
+ * captured joins' device-sized launch sequence directly (no host read-back
+ * between the levels; see hc_join_graph_create); likewise hc_join_emit,
+ * hc_join_count_cells and hc_join_count_segments.  Results do not depend on it.
  * Errors: HC_ERR_INVALID (bad query, order, shares, or CoCos that do not
  * match), HC_ERR_UNSUPPORTED (a frontier entry wider than the engine's limit),
  * HC_ERR_OOM, HC_ERR_CANCELLED (hc_ctx_cancel), HC_ERR_DEVICE.
@@ -364,7 +370,9 @@ hc_status hc_join_count_multi(hc_ctx* ctx, const hc_query* q, const hc_coco* con
  * entries of F_{i+1} are at most those of F_i times the longest list of level
  * i's shortest operand (an id range on the variable caps it by the range
  * width), and each frontier chunk, pool and table by the library's chunking
- * cap of 2^27 entries.  bytes_out (host) receives it.  Errors: HC_ERR_INVALID
+ * cap of 2^27 entries; a count call bounded to small frontiers (see
+ * hc_join_count) is charged the fixed capacities it then takes, when those are
+ * larger.  bytes_out (host) receives it.  Errors: HC_ERR_INVALID
  * for a bad query, order, NULL argument or negative count or width.
  */
 hc_status hc_join_workspace_bound(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atom_index,

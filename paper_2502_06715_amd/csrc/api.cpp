@@ -360,6 +360,10 @@ hc_status hc_join_count(hc_ctx* ctx, const hc_query* q, const hc_coco* const* at
                 return;
             }
         }
+        // small joins: the device-sized sequence, no read-back between the levels
+        if (!digest_out && hc::join_small_device_sized(ctx, q, atom_index, var_order, log2_shares, flags, -1, nullptr,
+                                                       0, count_out, nullptr, nullptr))
+            return;
         hc::join_run(ctx, q, atom_index, var_order, log2_shares, flags, false, count_out, digest_out, nullptr, 0,
                      nullptr);
     });
@@ -379,7 +383,7 @@ hc_status hc_join_count_noalloc(hc_ctx* ctx, const hc_query* q, const hc_coco* c
         int64_t cap = hc::kDefaultCap;
         uint64_t need = 0;
         for (;; cap >>= 2) {
-            need = hc::join_workspace_bound(q, atom_index, var_order, log2_shares, flags, 0, 0, cap);
+            need = hc::join_workspace_bound(q, atom_index, var_order, log2_shares, flags, 0, 0, cap, false);
             if (need <= hc::scratch_bytes() || cap <= ((int64_t)1 << 12)) break;
         }
         HC_REQUIRE(need <= hc::scratch_bytes(), HC_ERR_UNSUPPORTED,
@@ -419,6 +423,9 @@ hc_status hc_join_count_cells(hc_ctx* ctx, const hc_query* q, const hc_coco* con
         check_query_ptrs(q);
         HC_REQUIRE(atom_index && var_order && cell_counts && count_out, HC_ERR_INVALID, "NULL argument");
         check_flags(flags, kJoinFlags, "hc_join_count_cells");
+        if (hc::join_small_device_sized(ctx, q, atom_index, var_order, log2_shares, flags, 0, nullptr, 0, count_out,
+                                        cell_counts, nullptr))
+            return;
         hc::join_run(ctx, q, atom_index, var_order, log2_shares, flags, false, count_out, nullptr, nullptr, 0,
                      nullptr, cell_counts);
     });
@@ -440,6 +447,9 @@ hc_status hc_join_count_segments(hc_ctx* ctx, const hc_query* q, const hc_coco* 
         std::vector<int32_t> shares((size_t)q->n_vars, 0);
         shares[(size_t)var_order[0]] = seg + log2_extra;
         // the cell id is the first variable's coordinate (segment above the extra split)
+        if (hc::join_small_device_sized(ctx, q, atom_index, var_order, shares.data(), flags, log2_extra, nullptr, 0,
+                                        count_out, segment_counts, nullptr))
+            return;
         hc::join_run(ctx, q, atom_index, var_order, shares.data(), flags, false, count_out, nullptr, nullptr, 0,
                      nullptr, segment_counts, 0, nullptr, nullptr, 0, log2_extra);
     });
@@ -486,8 +496,11 @@ hc_status hc_join_emit(hc_ctx* ctx, const hc_query* q, const hc_coco* const* ato
         HC_REQUIRE(capacity == 0 || out != nullptr, HC_ERR_INVALID, "out is NULL");
         check_flags(flags, kJoinFlags | HC_EMIT_SORTED, "hc_join_emit");
         uint64_t count = 0;
-        hc::join_run(ctx, q, atom_index, var_order, log2_shares, flags & ~HC_EMIT_SORTED, true, &count, nullptr,
-                     out, capacity, n_out);
+        if (!(out != nullptr && hc::join_small_device_sized(ctx, q, atom_index, var_order, log2_shares,
+                                                             flags & ~HC_EMIT_SORTED, -1, out, capacity, &count,
+                                                             nullptr, n_out)))
+            hc::join_run(ctx, q, atom_index, var_order, log2_shares, flags & ~HC_EMIT_SORTED, true, &count, nullptr,
+                         out, capacity, n_out);
         *n_out = (int64_t)count;
         if ((int64_t)count > capacity)
             hc::fail(HC_ERR_OVERFLOW, "hc_join_emit: " + std::to_string(count) + " rows exceed capacity " +

@@ -265,9 +265,11 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
               void* out, int64_t capacity, int64_t* n_out, uint64_t* cell_counts = nullptr,
               int64_t n_multi = 0, const int64_t* multi_ranges = nullptr, const Alloc* alloc = nullptr,
               int64_t cap_entries = 0, int cell_group = 0);
+// with_small_path: also cover the device-sized sequence a small count takes
+// (hc_join_count, hc_join_count_cells); false for calls that always run eagerly.
 uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
                               const int32_t* shares, uint32_t flags, int64_t n_queries, int64_t first_width,
-                              int64_t cap_entries = kDefaultCap);
+                              int64_t cap_entries = kDefaultCap, bool with_small_path = true);
 
 // Device-sized joins captured in a HIP graph (join.hip).
 hc_join_graph* join_graph_create(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
@@ -277,5 +279,13 @@ void join_graph_launch(hc_join_graph* g);
 void join_graph_result(hc_join_graph* g, uint64_t* count, uint64_t* cell_counts, int64_t* n_out, int32_t* replayed);
 void join_graph_destroy(hc_join_graph* g);
 hc_ctx* join_graph_ctx(const hc_join_graph* g);
+// A join that its CoCo statistics bound to small frontiers (at most 2^20 entries
+// and 2^23 elements per level), run as the device-sized launch sequence directly on
+// the context's stream: no host read-back between the levels.  Returns false, having
+// done nothing, when the join is not such a join (the caller then runs the eager
+// path); results as join_run's.
+bool join_small_device_sized(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
+                             const int32_t* shares, uint32_t flags, int32_t cell_group, void* out, int64_t capacity,
+                             uint64_t* count, uint64_t* cell_counts, int64_t* n_out);
 
 }  // namespace hc

@@ -2417,6 +2417,9 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
     }
 }
 
+double small_join_count_bytes(const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
+                              const int32_t* shares, uint32_t flags);
+
 // Upper bound of the device memory one join call allocates (frontiers, per-level
 // step buffers, match words, lifted-intersection pools, work-queue tables), from
 // host-side CoCo statistics only.  Entries of F_{i+1} are bounded by those of F_i
@@ -2425,7 +2428,7 @@ void join_run(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const
 // most max(cap, one entry's elements) items, cap being the chunking cap of the call.
 uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
                               const int32_t* shares, uint32_t flags, int64_t n_queries, int64_t first_width,
-                              int64_t cap_entries) {
+                              int64_t cap_entries, bool with_small_path) {
     const Plan P = compile_plan(q, order, !(flags & HC_NO_REWRITE), n_queries > 0 ? 1 : 0);
     const double kCap = (double)cap_entries;   // frontier entries / pool elements per chunk
     int K = 0;
@@ -2470,6 +2473,7 @@ uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, co
         for (int g = 0; g < P.n_groups; ++g)
             for (int t = 0; t < P.groups[g].n_ops; ++t) op_tables(P.groups[g].ops[t], P.groups[g].var);
     }
+    const double setup_bytes = bytes;   // slack, per-cell counts and set-up tables, common to both paths
     double chunk = 1e30;   // entries of one frontier chunk: F_0 is never split
     for (int i = 0; i < P.n_vars; ++i) {
         const PlanLevel& L = P.levels[i];
@@ -2504,6 +2508,9 @@ uint64_t join_workspace_bound(const hc_query* q, const hc_coco* const* atoms, co
         E = std::min(E * m, 1e18);
         chunk = std::max(kCap, m);
     }
+    // a small count runs the device-sized sequence instead (fixed capacities)
+    if (n_queries == 0 && with_small_path)
+        bytes = std::max(bytes, setup_bytes + small_join_count_bytes(q, atoms, order, shares, flags));
     return (uint64_t)std::min(bytes, 1.8e19);
 }
 
@@ -2765,9 +2772,12 @@ static void graph_record(hc_join_graph* g, hipStream_t s) {
     }
 }
 
-hc_join_graph* join_graph_create(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
-                                 const int32_t* shares, uint32_t flags, int32_t cell_group, void* out,
-                                 int64_t capacity, int64_t frontier_cap, int64_t item_cap) {
+// capture = false: the buffers and set-up only (the sequence is then launched
+// directly on the context's stream, see join_small_device_sized).
+static hc_join_graph* graph_create(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
+                                   const int32_t* shares, uint32_t flags, int32_t cell_group, void* out,
+                                   int64_t capacity, int64_t frontier_cap, int64_t item_cap, bool capture,
+                                   int64_t leaf_items = 0) {
     std::unique_ptr<hc_join_graph> g(new hc_join_graph());
     g->ctx = ctx;
     // own copies of the call
@@ -2833,8 +2843,11 @@ hc_join_graph* join_graph_create(hc_ctx* ctx, const hc_query* q, const hc_coco* 
         L.G.iter = L.iter.p;
         L.G.m = L.m.p;
         // chunk table: chunks of at least kMinChunk elements over the item capacity,
-        // or (a counting leaf) 2^20 chunks, larger ones beyond 2^32 elements
-        L.ce_cap = bitmap ? g->icap / (int64_t)kMinChunk + 1 : (int64_t)1 << 20;
+        // or (a counting leaf) 2^20 chunks, larger ones beyond 2^32 elements (fewer
+        // when a bound on the leaf's elements is known; chunks grow to fit)
+        L.ce_cap = bitmap ? g->icap / (int64_t)kMinChunk + 1
+                          : (leaf_items > 0 ? std::min<int64_t>((int64_t)1 << 20, leaf_items / (int64_t)kMinChunk + 1)
+                                            : (int64_t)1 << 20);
         L.ce = DevBuf<int64_t>(R.A, (size_t)L.ce_cap + 1);
         if (bitmap) {
             const int64_t nw = g->icap / 64 + 1;
@@ -2870,6 +2883,7 @@ hc_join_graph* join_graph_create(hc_ctx* ctx, const hc_query* q, const hc_coco* 
         GG.pos = DevBuf<int32_t>(R.A, (size_t)GS.n_ops * (size_t)g->icap);
         R.grow_tmp(gi, g->icap);   // the pool (also sets the kernels' pool pointers)
     }
+    if (!capture) return g.release();
     HC_HIP(hipStreamCreateWithFlags(&g->cs, hipStreamNonBlocking));
     HC_HIP(hipStreamBeginCapture(g->cs, hipStreamCaptureModeThreadLocal));
     try {
@@ -2884,6 +2898,172 @@ hc_join_graph* join_graph_create(hc_ctx* ctx, const hc_query* q, const hc_coco* 
     HC_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
     // the set-up tables were computed on the context's stream, where the replays run
     return g.release();
+}
+
+hc_join_graph* join_graph_create(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
+                                 const int32_t* shares, uint32_t flags, int32_t cell_group, void* out,
+                                 int64_t capacity, int64_t frontier_cap, int64_t item_cap) {
+    return graph_create(ctx, q, atoms, order, shares, flags, cell_group, out, capacity, frontier_cap, item_cap, true);
+}
+
+// Frontier and element bounds of a join from the CoCo statistics alone: F_0 has
+// 2^K entries; a level's elements are at most its entries times the longest list of
+// its shortest operand (a predicate's width bounds it too), and the next frontier at
+// most those elements; a lifted intersection's elements at most its frontier's
+// entries times its shortest operand's longest list.  False when a level's operand
+// is beyond the captured sequence's reach (more than 4 operands).
+static bool small_join_bounds(const hc_query* q, const hc_coco* const* atoms, const Plan& P, const int32_t* shares,
+                              bool emit, double* fmax, double* imax, double* leaf) {
+    auto op_max = [&](const PlanOp& o) -> double {
+        const hc_coco* c = atoms[o.atom];
+        return o.kind == OP_CHILD ? (double)c->max_children[o.lvl - 1] : (double)c->level_len[0];
+    };
+    double gmax[kMaxGroups];
+    for (int g = 0; g < P.n_groups; ++g) {
+        if (P.groups[g].n_ops > 4) return false;
+        double m = 1e300;
+        for (int t = 0; t < P.groups[g].n_ops; ++t) m = std::min(m, op_max(P.groups[g].ops[t]));
+        gmax[g] = m;
+    }
+    int K = 0;
+    for (int v = 0; v < P.n_vars; ++v) K += shares ? shares[v] : 0;
+    double E = std::ldexp(1.0, K);
+    *fmax = 0;
+    *imax = 0;
+    for (int i = 0; i < P.n_vars; ++i) {
+        const PlanLevel& L = P.levels[i];
+        if (L.n_ops > 4) return false;
+        for (int g = 0; g < P.n_groups; ++g)
+            if (P.groups[g].lift == i) *imax = std::max(*imax, E * gmax[g]);
+        double m = 1e300;
+        for (int t = 0; t < L.n_ops; ++t)
+            m = std::min(m, L.ops[t].kind == OP_TMP ? gmax[L.ops[t].group] : op_max(L.ops[t]));
+        if (q->var_lo && q->var_hi[L.var] > q->var_lo[L.var])
+            m = std::min(m, (double)q->var_hi[L.var] - (double)q->var_lo[L.var]);
+        const double items = E * m;
+        if (i + 1 < P.n_vars || emit) *imax = std::max(*imax, items);
+        if (i + 1 < P.n_vars) *fmax = std::max(*fmax, items);
+        *leaf = items;
+        E = items;
+    }
+    return true;
+}
+
+// Bytes the buffers of a device-sized sequence take (graph_create) beyond the set-up
+// tables the eager call allocates as well: each rounded up to 512 bytes, and a
+// buffer over 1 MiB given 1 MiB more (a caching allocator may hand it a larger free
+// block without splitting it).
+static double dev_sequence_bytes(const Plan& P, int64_t ncell, int64_t fcap, int64_t icap, int64_t leaf_ce,
+                                 bool emit, bool cells) {
+    double b = 0;
+    auto buf = [&](double bytes) {
+        b += std::ceil(std::max(bytes, 1.0) / 512.0) * 512.0 + (bytes > 1048576.0 ? 1048576.0 : 0.0);
+    };
+    auto step = [&](int n_ops, int64_t ecap, bool bitmap, int64_t ce_cap) {
+        buf(2.0 * n_ops * ecap * 4);
+        buf(ecap * 4.0);
+        buf(ecap * 4.0);
+        buf((ecap + 1) * 8.0);
+        buf(scan_dn_ws_size(ecap) * 8.0);
+        buf((ce_cap + 1) * 8.0);
+        if (bitmap) {
+            const int64_t nw = icap / 64 + 1;
+            buf((nw + 1) * 8.0);
+            buf((nw + 1) * 8.0);
+            buf(scan_dn_ws_size(nw) * 8.0);
+            buf((double)n_ops * icap * 4);
+        }
+    };
+    if (cells) buf(ncell * 8.0);
+    buf((kCtlPerLevel * (P.n_vars + P.n_groups) + 8) * 8.0);
+    for (int i = 0; i < P.n_vars; ++i) {
+        const int64_t ecap = i == 0 ? ncell : fcap;
+        const bool bitmap = i + 1 < P.n_vars || emit;
+        buf(ecap * 4.0 * make_layout(P, i).W);
+        step(P.levels[i].n_ops, ecap, bitmap, bitmap ? icap / (int64_t)kMinChunk + 1 : leaf_ce);
+    }
+    for (int g = 0; g < P.n_groups; ++g) {
+        const int64_t ecap = P.groups[g].lift == 0 ? ncell : fcap;
+        step(P.groups[g].n_ops, ecap, true, icap / (int64_t)kMinChunk + 1);
+        for (int u = 0; u <= P.groups[g].n_ops; ++u) buf(icap * 4.0);   // the pool and its sources
+    }
+    return b;
+}
+
+// Whether a call takes the device-sized path, and its capacities: joins whose bounds
+// stay within 2^20 frontier entries and 2^23 elements per level, with the default
+// search (the plan is compiled here; invalid calls are left to the eager path's
+// checks).
+struct SmallJoin {
+    Plan P;
+    int64_t ncell = 0, fcap = 0, icap = 0, leaf_items = 0, leaf_ce = 0;
+};
+static bool small_join_plan(const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
+                            const int32_t* shares, uint32_t flags, bool emit, SmallJoin* sj) {
+    constexpr double kFrontierMax = (double)(1 << 20), kItemsMax = (double)(1 << 23);
+    if (flags & ~HC_NO_REWRITE) return false;   // the default search only
+    for (int j = 0; j < q->n_atoms; ++j)
+        if (!atoms[j]) return false;
+    int K = 0;
+    for (int v = 0; v < q->n_vars; ++v) K += shares ? shares[v] : 0;
+    if (K < 0 || K > 24) return false;
+    sj->P = compile_plan(q, order, !(flags & HC_NO_REWRITE));
+    double fmax = 0, imax = 0, leaf = 0;
+    if (!small_join_bounds(q, atoms, sj->P, shares, emit, &fmax, &imax, &leaf)) return false;
+    if (fmax > kFrontierMax || imax > kItemsMax) return false;
+    sj->ncell = (int64_t)1 << K;
+    sj->fcap = std::max<int64_t>(1024, (int64_t)fmax);
+    sj->icap = std::max<int64_t>(4096, (int64_t)imax);
+    sj->leaf_items = (int64_t)std::min(leaf, 1e15);
+    sj->leaf_ce = std::min<int64_t>((int64_t)1 << 20, sj->leaf_items / (int64_t)kMinChunk + 1);
+    return true;
+}
+
+// Device memory of a count or per-cell count call on the device-sized path (0 when
+// the call takes the eager one); hc_join_workspace_bound includes it.
+double small_join_count_bytes(const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
+                              const int32_t* shares, uint32_t flags) {
+    SmallJoin sj;
+    if (!small_join_plan(q, atoms, order, shares, flags, false, &sj)) return 0.0;
+    return dev_sequence_bytes(sj.P, sj.ncell, sj.fcap, sj.icap, sj.leaf_ce, false, true);
+}
+
+bool join_small_device_sized(hc_ctx* ctx, const hc_query* q, const hc_coco* const* atoms, const int32_t* order,
+                             const int32_t* shares, uint32_t flags, int32_t cell_group, void* out, int64_t capacity,
+                             uint64_t* count, uint64_t* cell_counts, int64_t* n_out) {
+    SmallJoin sj;
+    if (!small_join_plan(q, atoms, order, shares, flags, out != nullptr, &sj)) return false;
+    std::unique_ptr<hc_join_graph> g(graph_create(ctx, q, atoms, order, shares, flags, cell_group, out, capacity,
+                                                  sj.fcap, sj.icap, false, sj.leaf_items));
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (ctx->profiling) {
+        HC_HIP(hipEventCreate(&t0));
+        HC_HIP(hipEventCreate(&t1));
+        HC_HIP(hipEventRecord(t0, ctx->stream));
+    }
+    graph_record(g.get(), ctx->stream);
+    g->launched = 1;
+    int64_t no = 0;
+    try {
+        join_graph_result(g.get(), count, cell_counts, &no, nullptr);
+    } catch (...) {
+        if (n_out) *n_out = no;
+        if (t0) (void)hipEventDestroy(t0);
+        if (t1) (void)hipEventDestroy(t1);
+        throw;
+    }
+    if (n_out) *n_out = no;
+    ctx->timing = hc_timing{};
+    if (ctx->profiling) {
+        HC_HIP(hipEventRecord(t1, ctx->stream));
+        HC_HIP(hipEventSynchronize(t1));
+        float ms = 0;
+        HC_HIP(hipEventElapsedTime(&ms, t0, t1));
+        ctx->timing.total_ms = ms;
+        (void)hipEventDestroy(t0);
+        (void)hipEventDestroy(t1);
+    }
+    return true;
 }
 
 void join_graph_launch(hc_join_graph* g) {
