@@ -285,3 +285,36 @@ def test_graph_range_predicates_equal_oracle(ctx):
         assert rep and cnt == exp.count
         assert np.array_equal(sort_rows(rows.cpu().numpy()), exp.rows)
         g.free()
+
+
+def test_direct_small_joins_within_workspace_bound(ctx):
+    """Joins small enough to run the device-sized sequence directly (counts, per-cell
+    counts, predicates): results equal the oracle's, and the device memory of each
+    call, measured by torch's allocator, stays within hc_join_workspace_bound, which
+    admission relies on."""
+    import torch
+    E = config_graph(1)
+    n, atoms = inputs.QUERIES["triangle"]
+    c = hc.build_coco(ctx, _dev(E), [0, 1], key_bits=12, seed=SEED, symmetric=True)
+    cases = [(hc.Query(n, atoms), [0, 0, 0]), (hc.Query(n, atoms), [2, 1, 1]),
+             (hc.Query(n, atoms, [0, 100, 0], [3000, 4096, 4096]), [0, 0, 0])]
+    for q, shares in cases:
+        exp = oracle.gj(n, atoms, [E] * 3, lo=q.var_lo, hi=q.var_hi).count
+        bound = hc.join_workspace_bound(ctx, q, [c] * 3, [0, 1, 2], shares)
+        torch.cuda.synchronize()
+        base = torch.cuda.memory_allocated()
+        torch.cuda.reset_peak_memory_stats()
+        got = hc.join_count(ctx, q, [c] * 3, [0, 1, 2], shares)
+        torch.cuda.synchronize()
+        peak = torch.cuda.max_memory_allocated() - base
+        log("direct small join shares=%s: %d, peak %d bytes, bound %d" % (shares, got, peak, bound))
+        assert got == exp
+        assert 0 < peak <= bound
+        if q.var_lo is None:
+            want, _ = cells.cells(n, atoms, [E] * 3, shares, 12, SEED, order=[0, 1, 2])
+            base = torch.cuda.memory_allocated()
+            torch.cuda.reset_peak_memory_stats()
+            per, tot = hc.join_count_cells(ctx, q, [c] * 3, [0, 1, 2], shares)
+            torch.cuda.synchronize()
+            assert tot == exp and np.array_equal(per, want)
+            assert torch.cuda.max_memory_allocated() - base <= bound
